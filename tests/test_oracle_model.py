@@ -1,0 +1,317 @@
+"""Pins of the oracle's energy, forces and virial.
+
+The potential has no printed worked example, so the oracle is pinned by
+(a) an independent closed form of the K = 1 and K = 2 models written with
+Legendre polynomials of bond angles (no spherical harmonics, no coupling
+tables, no shared parser), (b) finite differences of the energy for forces
+and virial, (c) invariances and equivariances, (d) special cases (dimer,
+separability, depth-pruning truncation), and (e) the partition rules of
+Methods "Graph Partitioning" / "Global Output Integration".
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+RC = 5.0
+
+
+def hp_of(L, C, T, S=3):
+    return W.HParams(n_species=S, n_layers=T, l_max=L, channels=C)
+
+
+def cluster(n, seed, box=9.0, dmin=1.6):
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        p = rng.uniform(0, box, 3)
+        if all(np.linalg.norm(p - q) > dmin for q in pts):
+            pts.append(p)
+    return np.array(pts), rng.integers(0, 3, n).astype(np.int32)
+
+
+def ev(pos, sp, hp, blob, K=None, cell=None, pbc=(False,) * 3, **kw):
+    cell = np.eye(3) * 100.0 if cell is None else cell
+    return oracle.evaluate(pos, sp, cell, np.array(pbc), blob, hp, K=K, **kw)
+
+
+# ------------------------------------------------------------- closed forms
+
+def _unpack(blob, hp):
+    """The test's own reading of the blob, driven by the generator's layout."""
+    out, off = {}, 0
+    for name, shape, _ in W.weight_layout(hp):
+        n = int(np.prod(shape))
+        out[name] = blob[off:off + n].astype(np.float64).reshape(shape)
+        off += n
+    return out
+
+
+def _sig(x):
+    return 1 / (1 + np.exp(-x))
+
+
+def _silu(x):
+    return x * _sig(x)
+
+
+def legendre(l, x):
+    return [1.0, x, 0.5 * (3 * x * x - 1)][l]
+
+
+def closed_form_atom_energies(pos, sp, hp, blob, K):
+    """Direct evaluation of the K = 1 or K = 2 model for a non-periodic
+    cluster, with bond-angle Legendre polynomials in place of harmonics:
+    sum_m Y_lm(u) Y_lm(v) = (2l+1) P_l(u.v) and C^(0,l,l) = C^(l,l,0) = I/sqrt(2l+1)."""
+    w = _unpack(blob, hp)
+    C, L, N = hp.channels, hp.l_max, len(pos)
+    inv_n = 1 / hp.avg_neighbors
+    nbr = {i: [] for i in range(N)}
+    for i in range(N):
+        for j in range(N):
+            if i != j:
+                r = pos[j] - pos[i]
+                d = math.sqrt(r @ r)
+                if d < RC:
+                    nbr[i].append((j, r / d, d))
+
+    def R(t, d, path_idx):
+        e, _ = oracle.radial_features(np.array([d]), RC, hp.n_basis, hp.envelope_p)
+        a = _silu(_silu(e[0] @ w[f"L{t}.W1"]) @ w[f"L{t}.W2"])
+        out = a @ w[f"L{t}.W3"]
+        return out[path_idx * C:(path_idx + 1) * C]
+
+    h0 = w["W_emb"][sp]
+    ht1 = w["W_emb"] @ w["L1.W_up0"]            # per-species table
+    # layer 1: paths (0,l,l) are columns l of W3 (layer 1 input is scalar)
+    A10 = np.array([inv_n * sum(R(1, d, 0) * ht1[sp[k]] for k, _, d in nbr[j]) if nbr[j]
+                    else np.zeros(C) for j in range(N)])
+    z10 = A10 @ w["L1.W_down0"]
+    h10 = h0 + _silu(z10[:, :C])
+    if K == 1:
+        return w["e0"][sp] + h10 @ w["w_read"]
+
+    def T1(j, l, v):
+        """sum_m A1[j, :, l m] Y_lm(v)"""
+        acc = np.zeros(C)
+        for k, ujk, d in nbr[j]:
+            acc += R(1, d, l) * ht1[sp[k]] * math.sqrt(2 * l + 1) * legendre(l, ujk @ v)
+        return inv_n * acc
+
+    # layer-2 paths (l,l,0): index in the t>=2 path list
+    idx2 = {l: [p for p in _paths2(L)].index((l, l, 0)) for l in range(L + 1)}
+    ht20 = h10 @ w["L2.W_up0"]
+    E = np.zeros(N)
+    for i in range(N):
+        A2 = np.zeros(C)
+        for j, uij, d in nbr[i]:
+            msg = R(2, d, idx2[0]) * ht20[j]
+            for l in range(1, L + 1):
+                gate = _sig(z10[j, l * C:(l + 1) * C])
+                proj = ((gate * (T1(j, l, uij) @ w[f"L1.W_down{l}"])) @ w[f"L2.W_up{l}"])
+                msg = msg + R(2, d, idx2[l]) * proj / math.sqrt(2 * l + 1)
+            A2 += inv_n * msg
+        z2 = A2 @ w["L2.W_down0"][:, :C]
+        E[i] = w["e0"][sp[i]] + (h10[i] + _silu(z2)) @ w["w_read"]
+    return E
+
+
+def _paths2(L):
+    return [(a, b, c) for a in range(L + 1) for b in range(L + 1) for c in range(L + 1)
+            if (a + b + c) % 2 == 0 and abs(a - b) <= c <= a + b]
+
+
+@pytest.mark.parametrize("L,T,K", [(1, 2, 1), (1, 2, 2), (2, 2, 2), (2, 4, 2), (2, 3, 1)])
+def test_closed_form_body_order_expansion(L, T, K):
+    pos, sp = cluster(14, 10 + L + T)
+    hp = hp_of(L, 8, T)
+    blob = W.make_weights(hp, 5, e0=[0.3, -0.2, 0.1])
+    ref = closed_form_atom_energies(pos, sp, hp, blob, K)
+    res = ev(pos, sp, hp, blob, K=K, forces=False)
+    assert np.allclose(res.atom_energy, ref, rtol=0, atol=1e-12)
+    assert res.energy == pytest.approx(ref.sum(), abs=1e-11)
+
+
+# ------------------------------------------------------------- derivatives
+
+@pytest.mark.parametrize("L,C,T,K", [(1, 32, 2, 2), (2, 16, 3, 3)])
+def test_forces_match_finite_differences(L, C, T, K):
+    s = W.small_system()
+    hp = hp_of(L, C, T, S=2)
+    blob = W.make_weights(hp, 103)
+    res = oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, hp, K=K)
+    h = 1e-5
+    rng = np.random.default_rng(0)
+    for a in rng.choice(128, 4, replace=False):
+        for k in range(3):
+            p = s.positions.copy()
+            p[a, k] += h
+            ep = oracle.evaluate(p, s.species, s.cell, s.pbc, blob, hp, K=K, forces=False).energy
+            p[a, k] -= 2 * h
+            em = oracle.evaluate(p, s.species, s.cell, s.pbc, blob, hp, K=K, forces=False).energy
+            assert -(ep - em) / (2 * h) == pytest.approx(res.forces[a, k], abs=2e-9)
+    assert np.allclose(res.forces.sum(axis=0), 0.0, atol=1e-12)
+
+
+def test_virial_matches_strain_finite_differences():
+    s = W.small_system()
+    hp = W.HP_SMALL
+    blob = W.make_weights(hp, 103)
+    res = oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, hp)
+    assert np.allclose(res.virial, res.virial.T, atol=1e-12)
+    h = 1e-6
+    for a in range(3):
+        for b in range(3):
+            vals = []
+            for sgn in (1, -1):
+                eps = np.zeros((3, 3))
+                eps[a, b] = sgn * h
+                M = np.eye(3) + eps
+                vals.append(oracle.evaluate(s.positions @ M.T, s.species, s.cell @ M.T, s.pbc,
+                                            blob, hp, forces=False).energy)
+            dEde = (vals[0] - vals[1]) / (2 * h)
+            assert -dEde == pytest.approx(res.virial[a, b], abs=1e-8)
+
+
+# ------------------------------------------------------------- symmetries
+
+def test_rotation_translation_permutation():
+    s = W.small_system()
+    hp = W.HP_SMALL
+    blob = W.make_weights(hp, 103)
+    base = oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, hp)
+    scale = np.abs(base.forces).max()
+    rng = np.random.default_rng(7)
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    Q = q @ np.diag(np.sign(np.diag(r)))
+    rot = oracle.evaluate(s.positions @ Q.T, s.species, s.cell @ Q.T, s.pbc, blob, hp)
+    assert rot.energy == pytest.approx(base.energy, rel=1e-12)
+    assert np.allclose(rot.forces, base.forces @ Q.T, atol=1e-12 * max(1, scale))
+    assert np.allclose(rot.virial, Q @ base.virial @ Q.T, atol=1e-11)
+    tr = oracle.evaluate(s.positions + np.array([3.3, -7.1, 100.2]), s.species, s.cell, s.pbc, blob, hp)
+    assert tr.energy == pytest.approx(base.energy, rel=1e-12)
+    assert np.allclose(tr.forces, base.forces, atol=1e-12)
+    perm = rng.permutation(128)
+    pe = oracle.evaluate(s.positions[perm], s.species[perm], s.cell, s.pbc, blob, hp)
+    assert pe.energy == pytest.approx(base.energy, rel=1e-12)
+    assert np.allclose(pe.forces, base.forces[perm], atol=1e-12)
+    assert np.allclose(pe.atom_energy, base.atom_energy[perm], atol=1e-12)
+    # improper rotation (inversion): natural-parity paths make E O(3)-invariant
+    inv = oracle.evaluate(-s.positions, s.species, -s.cell, s.pbc, blob, hp)
+    assert inv.energy == pytest.approx(base.energy, rel=1e-12)
+    assert np.allclose(inv.forces, -base.forces, atol=1e-12)
+
+
+def test_dimer():
+    hp = hp_of(2, 16, 2)
+    blob = W.make_weights(hp, 9)
+    sp = np.array([0, 2], np.int32)
+    rng = np.random.default_rng(1)
+    E = []
+    for d in (2.2, 2.2, 3.7):
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        pos = np.array([[10.0, 10.0, 10.0], [10.0, 10.0, 10.0]]) + np.array([[0, 0, 0], d * u])
+        res = ev(pos, sp, hp, blob)
+        assert np.allclose(res.forces[0], -res.forces[1], atol=1e-14)
+        assert np.linalg.norm(np.cross(res.forces[0], u)) < 1e-12 * max(1, np.linalg.norm(res.forces[0]))
+        E.append(res.energy)
+    assert E[0] == pytest.approx(E[1], rel=1e-13)
+    assert E[0] != pytest.approx(E[2], rel=1e-6)
+
+
+def test_separability():
+    hp = hp_of(2, 8, 3)
+    blob = W.make_weights(hp, 11)
+    p1, s1 = cluster(10, 1)
+    p2, s2 = cluster(9, 2)
+    p2 = p2 + np.array([40.0, 0, 0])       # farther apart than K*r_cut = 15
+    a = ev(p1, s1, hp, blob).energy
+    b = ev(p2, s2, hp, blob).energy
+    both = ev(np.vstack([p1, p2]), np.concatenate([s1, s2]), hp, blob)
+    assert both.energy == pytest.approx(a + b, rel=1e-13)
+
+
+def test_depth_pruning_is_truncation():
+    """K < T reads out from layer K with the unchanged weights of layers
+    1..K (Methods, "Message Passing Depth Pruning")."""
+    pos, sp = cluster(16, 3)
+    hp6, hp2 = hp_of(2, 8, 6), hp_of(2, 8, 2)
+    blob6 = W.make_weights(hp6, 12)
+    lay6 = W.weight_layout(hp6)
+    sizes = [int(np.prod(s)) for _, s, _ in lay6]
+    offs = np.cumsum([0] + sizes)
+    keep = [k for k, (name, _, _) in enumerate(lay6)
+            if not name.startswith(("L3.", "L4.", "L5.", "L6."))]
+    blob2 = np.concatenate([blob6[offs[k]:offs[k + 1]] for k in keep])
+    assert blob2.size == W.weights_count(hp2)
+    a = ev(pos, sp, hp6, blob6, K=2)
+    b = ev(pos, sp, hp2, blob2, K=2)
+    assert a.energy == b.energy
+    assert np.array_equal(a.forces, b.forces)
+    c = ev(pos, sp, hp6, blob6, K=6)
+    assert c.energy != pytest.approx(a.energy, rel=1e-6)
+
+
+# ------------------------------------------------------------- partitions
+
+def _slab_case():
+    s = W.slab_full_system(40, 6, 6, 31, 32)       # 1440 atoms, 13.6 x 13.6 A cross-section
+    hp = hp_of(2, 8, 2)
+    return s, hp, W.make_weights(hp, 33)
+
+
+def test_partition_root_energies_and_force_sum():
+    """8 slab partitions with a K*r_cut halo: (i) root-atom energies equal the
+    full system's; (ii) energies, forces (ghost rows returned to owners) and
+    virials summed over partitions equal the full-system values."""
+    s, hp, blob = _slab_case()
+    full = oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, hp)
+    E, F, Wv, parts = oracle.evaluate_partitioned(s.positions, s.species, s.cell, blob, hp,
+                                                  K=2, n_parts=8, halo=2 * RC)
+    for res, gi, n_own in parts:
+        assert np.allclose(res.atom_energy[:n_own], full.atom_energy[gi[:n_own]], atol=1e-12)
+    owned = np.concatenate([gi[:n] for _, gi, n in parts])
+    assert np.array_equal(np.sort(owned), np.arange(s.n_atoms))
+    assert E == pytest.approx(full.energy, abs=1e-9)
+    assert np.allclose(F, full.forces, atol=1e-12)
+    assert np.allclose(Wv, full.virial, atol=1e-10)
+
+
+def test_partition_alone_needs_double_halo():
+    """(iii) one partition on its own reproduces its root atoms' forces only
+    if its halo is 2*K*r_cut deep and the energy is summed over the root
+    atoms plus the ghosts within K*r_cut of the slab (the root atoms' forces
+    also carry the gradient of those neighbours' energies).  Summing only
+    root energies, the atoms near the faces miss that gradient."""
+    s, hp, blob = _slab_case()
+    full = oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, hp)
+    Lx = s.cell[0, 0]
+    lo, hi = 3 * Lx / 8, 4 * Lx / 8
+    lp, ls, pbc, n_own, gi = oracle.slab_share(s.positions, s.species, s.cell, 8, 3, 4 * RC)
+    dist = np.maximum(np.maximum(lo - lp[:, 0], lp[:, 0] - hi), 0.0)
+    ghosts = np.arange(n_own, lp.shape[0])
+    inner = ghosts[dist[ghosts] < 2 * RC]
+    outer = ghosts[dist[ghosts] >= 2 * RC]
+    order = np.concatenate([np.arange(n_own), inner, outer])
+    lp, ls, gi = lp[order], ls[order], gi[order]
+    ref = full.forces[gi[:n_own]]
+    wide = oracle.evaluate(lp, ls, s.cell, pbc, blob, hp, K=2, n_owned=n_own + inner.size)
+    assert np.abs(wide.forces[:n_own] - ref).max() < 1e-12
+    roots_only = oracle.evaluate(lp, ls, s.cell, pbc, blob, hp, K=2, n_owned=n_own)
+    assert np.abs(roots_only.forces[:n_own] - ref).max() > 1e-6
+
+
+def test_local_cluster_force():
+    s = W.bulk_system(18, 5, 6)                     # 40.9 A box: 2*K*r_cut = 20 A fits
+    hp = hp_of(2, 8, 2)
+    blob = W.make_weights(hp, 7)
+    full = oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, hp)
+    for a in (0, 2917):
+        lp, ls, n_own, gi, c = oracle.local_cluster(s.positions, s.species, s.cell, a, 4 * RC, 2 * RC)
+        res = oracle.evaluate(lp, ls, np.eye(3), [False] * 3, blob, hp, K=2, n_owned=n_own)
+        assert np.allclose(res.forces[c], full.forces[a], atol=1e-12)
+        assert res.atom_energy[c] == pytest.approx(full.atom_energy[a], abs=1e-12)
