@@ -1,0 +1,178 @@
+/*
+ * mpip.h -- C ABI of libmpip: one energy + forces + virial evaluation of an
+ * equivariant message-passing interatomic potential on one AMD Instinct
+ * MI355X (gfx950) GPU.
+ *
+ * Method (arxiv 2509.21694):
+ *  - depth pruning, Methods "Message Passing Depth Pruning": a weight set
+ *    holds T message-passing layers; an evaluation runs only the first K
+ *    (1 <= K <= T) and reads the energy out from layer K;
+ *  - partitions, Methods "Graph Partitioning" and "Global Output
+ *    Integration": a system may be one partition of a larger structure --
+ *    its first n_owned atoms are the root atoms, the rest are halo copies.
+ *    The energy is summed over root atoms only; forces are -dE/dx for every
+ *    local atom (halo rows hold partial forces, to be added to the atoms
+ *    they copy); the virial decomposes the same way.
+ *
+ * The potential (layer equations, basis, harmonics, coupling tensors) is
+ * the NequIP/MACE-style reading documented with the library: a Bessel
+ * radial basis with polynomial envelope, component-normalised real
+ * spherical harmonics up to l_max <= 2, real Gaunt coupling tensors with
+ * natural parity, a bias-free SiLU radial MLP (n_basis -> hidden -> hidden
+ * -> one channel vector per coupling path), gated non-linearity with
+ * residual updates, and a linear per-species readout.
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented "device" are GPU global-memory addresses on the
+ *    model's device; "host" pointers are CPU memory.  The caller owns every
+ *    buffer it passes; the library never frees or retains them.
+ *  - Asynchronous calls enqueue work on the given HIP stream (NULL = the
+ *    legacy default stream) and return immediately; outputs are valid after
+ *    the stream has been synchronised.
+ *  - Every call returns an mpip_status; no C++ exception crosses the ABI.
+ *    On failure mpip_last_error() describes the cause (thread-local string,
+ *    valid until the next call on the same thread).
+ */
+#ifndef MPIP_H
+#define MPIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPIP_OK = 0,
+  MPIP_EINVAL = -1,        /* bad argument, species out of range, non-finite or coincident atoms */
+  MPIP_ECELL = -2,         /* singular cell, or too many cell-list bins                          */
+  MPIP_ECAPACITY = -3,     /* edge capacity or workspace too small (required size reported)      */
+  MPIP_EDEVICE = -4,       /* HIP runtime error                                                  */
+  MPIP_ENOMEM = -5,        /* device allocation failed (model creation only)                     */
+  MPIP_EUNSUPPORTED = -6   /* valid input outside what this build implements                     */
+} mpip_status;
+
+typedef enum {
+  MPIP_FP32 = 0,           /* all arithmetic in FP32 (FP32 MFMA for the dense contractions)       */
+  MPIP_BF16_MIXED = 1      /* radial MLP and channel mixing as BF16 MFMA with FP32 accumulation;
+                              tensor products, geometry in FP32; displacements and sums in FP64   */
+} mpip_precision;
+
+typedef struct {
+  int32_t n_species;       /* >= 1                                                  */
+  int32_t n_layers;        /* T, number of layers in the weight set, >= 1           */
+  int32_t l_max;           /* 1 or 2                                                */
+  int32_t channels;        /* C: 32, 64 or 128                                      */
+  int32_t n_basis;         /* 8                                                     */
+  int32_t envelope_p;      /* polynomial envelope order, >= 2                        */
+  int32_t radial_hidden;   /* 64                                                    */
+  double r_cut;            /* cutoff radius, Angstrom, > 0                           */
+  double inv_avg_neighbors;/* message normalisation 1/n_avg                          */
+} mpip_hparams;
+
+typedef struct {
+  int64_t n_atoms;         /* N >= 1                                                 */
+  int64_t n_owned;         /* 0 <= n_owned <= N: root atoms are the first n_owned    */
+  const double* positions; /* device [N,3] row-major, Angstrom; may lie outside the cell */
+  const int32_t* species;  /* device [N], values 0..n_species-1                      */
+  double cell[9];          /* host, row-major; rows are lattice vectors              */
+  uint8_t pbc[3];          /* host, 1 = periodic along that lattice vector           */
+} mpip_system;
+
+typedef struct {
+  double* energy;          /* device [1]: sum of root-atom energies, eV              */
+  double* forces;          /* device [N,3]: -dE/dx_i, eV/Angstrom, input atom order  */
+  double* virial;          /* device [9]: W = -sum_e r_e (x) dE/dr_e, eV, row-major  */
+  double* atom_energy;     /* device [N] per-atom energies E_i (input order), or NULL */
+} mpip_outputs;
+
+typedef struct mpip_model mpip_model;
+
+/* Number of float32 values in a weight set for these hyper-parameters.
+ * Blob order: W_emb [S,C]; per layer t=1..T: W_up[l] [C,C] for each input
+ * degree l ({0} at t=1, else 0..l_max), W1 [n_basis,H], W2 [H,H],
+ * W3 [H, P_t*C] (path-major columns; paths (l1,l2,l3) ordered by l1, l2, l3
+ * with l1+l2+l3 even and |l1-l2| <= l3 <= l1+l2), W_down[0] [C, C*(1+l_max)]
+ * (C features then one gate block per l >= 1), W_down[l] [C,C] for
+ * l = 1..l_max; then w_read [C], e0 [S].  Matrices are row-major and map
+ * rows (inputs) to columns (outputs).  Returns 0 for invalid hparams. */
+size_t mpip_weights_count(const mpip_hparams* hp);
+
+/* Validate hparams, build the coupling tables and upload the weights
+ * (host float32 [n]) to `device`.  The model owns its device memory
+ * (weights in FP32 and BF16 operand layouts, coupling tables) until
+ * mpip_model_destroy.  Synchronous.  Errors: EINVAL (bad hparams or n),
+ * ENOMEM, EDEVICE. */
+mpip_status mpip_model_create(const mpip_hparams* hp, const float* weights_host, size_t n,
+                              int32_t device, mpip_model** out);
+mpip_status mpip_model_destroy(mpip_model* model);
+
+/* Workspace bytes needed by mpip_evaluate for this system size, precision,
+ * depth K and edge capacity `max_edges` (directed edges).  Host only. */
+mpip_status mpip_workspace_size(const mpip_model* model, const mpip_system* sys,
+                                mpip_precision prec, int32_t K, int64_t max_edges,
+                                size_t* bytes);
+
+/* One evaluation: cell list, neighbour list, K layers forward, readout, the
+ * hand-written adjoint of all K layers (edge intermediates recomputed), and
+ * forces / virial.  Asynchronous on `stream`; never allocates; the caller's
+ * `workspace` (device, >= mpip_workspace_size bytes for the same max_edges)
+ * must not be used concurrently.  Host-detectable errors are returned at
+ * once.  Data-dependent errors (edge capacity exceeded, species out of range,
+ * non-finite positions, coincident atoms) are recorded in the workspace and
+ * reported by mpip_workspace_status after the stream is synchronised; the
+ * outputs are then undefined.  Orthorhombic cells only (else EUNSUPPORTED). */
+mpip_status mpip_evaluate(mpip_model* model, const mpip_system* sys, mpip_precision prec,
+                          int32_t K, void* stream, void* workspace, size_t workspace_bytes,
+                          int64_t max_edges, const mpip_outputs* out);
+
+/* Synchronise `stream` and read the status word of `workspace` written by
+ * the last mpip_evaluate / mpip_neighbor_list on it.  *n_edges receives the
+ * number of directed edges found (also when it exceeded the capacity). */
+mpip_status mpip_workspace_status(const void* workspace, void* stream, int64_t* n_edges);
+
+/* Neighbour list only (Methods "Graph Partitioning" builds its subgraphs on
+ * this adjacency): all (i, j, S) with |x_j - x_i + S.cell| < r_cut, decided
+ * in FP64 with a fixed operation order, in input atom indices.  Synchronous.
+ * edge_i/edge_j (device int32 [capacity]) and edge_shift (device int32
+ * [capacity,3]) receive the edges in an unspecified order; *n_edges the count.
+ * If the count exceeds `capacity` nothing is written past it and ECAPACITY
+ * is returned with *n_edges set to the required capacity.  The workspace must
+ * hold mpip_workspace_size(.., max_edges = capacity) bytes of any model or
+ * mpip_neighbor_workspace_size bytes. */
+size_t mpip_neighbor_workspace_size(int64_t n_atoms, int64_t capacity);
+mpip_status mpip_neighbor_list(const mpip_system* sys, double r_cut, void* stream,
+                               void* workspace, size_t workspace_bytes, int64_t capacity,
+                               int32_t* edge_i, int32_t* edge_j, int32_t* edge_shift,
+                               int64_t* n_edges);
+
+/* The library's coupling tensor for (l1,l2,l3), derived from Wigner 3j
+ * symbols and the complex-to-real change of basis, Frobenius-normalised.
+ * Host only, no GPU needed.  out: host [(2l1+1)*(2l2+1)*(2l3+1)] row-major
+ * (m1, m2, m3).  EINVAL for l > 2 or a triple without natural parity. */
+mpip_status mpip_coupling_tensor(int32_t l1, int32_t l2, int32_t l3, double* out);
+
+/* Per-phase GPU timing of mpip_evaluate (tracing aid).  When enabled, each
+ * evaluation records HIP events around its kernel phases on the evaluation
+ * stream (no synchronisation); mpip_timing_read synchronises those events,
+ * adds their durations to per-phase totals and returns the totals since the
+ * last enable.  Phase names: "neighbors", "node_gemm", "gates", "outputs",
+ * "edge_fwd_t<k>", "edge_bwd_t<k>" (k = layer).  Host-side only; the model
+ * must not be evaluated concurrently on two streams while enabled. */
+#define MPIP_MAX_PHASES 48
+typedef struct {
+  int32_t n;                          /* number of phases filled            */
+  char name[MPIP_MAX_PHASES][24];     /* NUL-terminated phase names         */
+  double ms[MPIP_MAX_PHASES];         /* summed duration, milliseconds      */
+  int64_t calls[MPIP_MAX_PHASES];     /* number of recorded intervals       */
+} mpip_timing;
+mpip_status mpip_timing_enable(mpip_model* model, int32_t on);
+mpip_status mpip_timing_read(mpip_model* model, mpip_timing* out);
+
+const char* mpip_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPIP_H */

@@ -124,7 +124,7 @@ def evaluate(positions, species, cell, pbc, blob, hp, K: Optional[int] = None,
         p2 = a1 @ lay["W2"]
         a2 = silu(p2)
         W3 = lay["W3"][:, [k for k, _ in live], :]            # [H, P_live, C]
-        R = np.einsum("eh,hpc->epc", a2, W3)
+        R = (a2 @ W3.reshape(W3.shape[0], -1)).reshape(a2.shape[0], W3.shape[1], W3.shape[2])
         return p1, a1, p2, a2, W3, R
 
     # ---------------- forward ----------------
@@ -145,7 +145,7 @@ def evaluate(positions, species, cell, pbc, blob, hp, K: Optional[int] = None,
             for q, (_, (l1, l2, l3)) in enumerate(live):
                 yc = _yc(coupling_tensor(l1, l2, l3), Y[sl, blk(l2)])      # [e, m1, m3]
                 hj = ht[ej[sl]][:, blk(l1), :]                              # [e, m1, c]
-                msg[:, blk(l3), :] += np.einsum("eak,eac->ekc", yc, hj) * R[:, q, None, :]
+                msg[:, blk(l3), :] += np.matmul(yc.transpose(0, 2, 1), hj) * R[:, q, None, :]
             A += segment_sum(ei[sl], msg, N)
         A *= inv_n
         z0 = A[:, 0, :] @ lay["W_down"][0]
@@ -196,12 +196,14 @@ def evaluate(positions, species, cell, pbc, blob, hp, K: Optional[int] = None,
                 hj = ht[ej[sl]][:, blk(l1), :]
                 Ab = Ai[:, blk(l3), :]
                 yc = _yc(Cp, Y[sl, blk(l2)])                              # [e, m1, m3]
-                T = np.einsum("eak,ekc->eac", yc, Ab)                     # dA-weighted Y
+                T = np.matmul(yc, Ab)                                      # [e, m1, c]
                 Rbar[:, q, :] = np.sum(T * hj, axis=1)
                 hjbar[:, blk(l1), :] += R[:, q, None, :] * T
-                Ybar[:, blk(l2)] += np.einsum("abk,eac,ekc,ec->eb", Cp, hj, Ab, R[:, q, :])
+                # P[e, m1, m3] = sum_c R[e, c] ht_j[e, m1, c] dA_i[e, m3, c]
+                P = np.matmul(hj * R[:, q, None, :], Ab.transpose(0, 2, 1))
+                Ybar[:, blk(l2)] += np.einsum("abk,eak->eb", Cp, P)
             htbar += segment_sum(ej[sl], hjbar, N)
-            a2bar = np.einsum("epc,hpc->eh", Rbar, W3)
+            a2bar = Rbar.reshape(ne, -1) @ W3.reshape(W3.shape[0], -1).T
             p2bar = a2bar * dsilu(p2)
             a1bar = p2bar @ lay["W2"].T
             p1bar = a1bar * dsilu(p1)

@@ -1,0 +1,318 @@
+"""Python binding of libmpip (ctypes; argument marshalling only).
+
+Every step of an evaluation runs in the library's HIP kernels on the GPU;
+PyTorch provides device memory and the current HIP stream.  If the built
+library is missing this module raises at import time -- there is no CPU
+fallback.
+
+Method: arxiv 2509.21694 -- depth pruning (evaluate the first K of T layers,
+Methods "Message Passing Depth Pruning") and halo partitions (root atoms
+first, Methods "Graph Partitioning" / "Global Output Integration").
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpip.so")
+
+FP32 = 0
+BF16_MIXED = 1
+PRECISIONS = {"fp32": FP32, "bf16": BF16_MIXED, FP32: FP32, BF16_MIXED: BF16_MIXED}
+
+OK, EINVAL, ECELL, ECAPACITY, EDEVICE, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ECELL", -3: "ECAPACITY", -4: "EDEVICE",
+                -5: "ENOMEM", -6: "EUNSUPPORTED"}
+
+
+class MpipError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class HParamsC(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_layers", ctypes.c_int32), ("l_max", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("n_basis", ctypes.c_int32), ("envelope_p", ctypes.c_int32),
+                ("radial_hidden", ctypes.c_int32), ("r_cut", ctypes.c_double),
+                ("inv_avg_neighbors", ctypes.c_double)]
+
+
+class SystemC(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int64), ("n_owned", ctypes.c_int64), ("positions", ctypes.c_void_p),
+                ("species", ctypes.c_void_p), ("cell", ctypes.c_double * 9), ("pbc", ctypes.c_uint8 * 3)]
+
+
+class OutputsC(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_void_p), ("forces", ctypes.c_void_p), ("virial", ctypes.c_void_p),
+                ("atom_energy", ctypes.c_void_p)]
+
+
+MAX_PHASES = 48
+
+
+class TimingC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("name", (ctypes.c_char * 24) * MAX_PHASES),
+                ("ms", ctypes.c_double * MAX_PHASES), ("calls", ctypes.c_int64 * MAX_PHASES)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2509_21694_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ, V = ctypes.POINTER, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+    lib.mpip_weights_count.argtypes = [P(HParamsC)]
+    lib.mpip_weights_count.restype = SZ
+    lib.mpip_model_create.argtypes = [P(HParamsC), P(ctypes.c_float), SZ, I32, P(V)]
+    lib.mpip_model_create.restype = I32
+    lib.mpip_model_destroy.argtypes = [V]
+    lib.mpip_model_destroy.restype = I32
+    lib.mpip_workspace_size.argtypes = [V, P(SystemC), I32, I32, I64, P(SZ)]
+    lib.mpip_workspace_size.restype = I32
+    lib.mpip_evaluate.argtypes = [V, P(SystemC), I32, I32, V, V, SZ, I64, P(OutputsC)]
+    lib.mpip_evaluate.restype = I32
+    lib.mpip_workspace_status.argtypes = [V, V, P(I64)]
+    lib.mpip_workspace_status.restype = I32
+    lib.mpip_neighbor_workspace_size.argtypes = [I64, I64]
+    lib.mpip_neighbor_workspace_size.restype = SZ
+    lib.mpip_neighbor_list.argtypes = [P(SystemC), ctypes.c_double, V, V, SZ, I64, V, V, V, P(I64)]
+    lib.mpip_neighbor_list.restype = I32
+    lib.mpip_coupling_tensor.argtypes = [I32, I32, I32, P(ctypes.c_double)]
+    lib.mpip_coupling_tensor.restype = I32
+    lib.mpip_timing_enable.argtypes = [V, I32]
+    lib.mpip_timing_enable.restype = I32
+    lib.mpip_timing_read.argtypes = [V, P(TimingC)]
+    lib.mpip_timing_read.restype = I32
+    lib.mpip_last_error.argtypes = []
+    lib.mpip_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ["mpip_weights_count", "mpip_model_create", "mpip_model_destroy", "mpip_workspace_size",
+            "mpip_evaluate", "mpip_workspace_status", "mpip_neighbor_workspace_size",
+            "mpip_neighbor_list", "mpip_coupling_tensor", "mpip_timing_enable", "mpip_timing_read",
+            "mpip_last_error"]
+
+
+def _check(st: int):
+    if st != OK:
+        raise MpipError(st, lib.mpip_last_error().decode())
+
+
+def hparams_c(hp) -> HParamsC:
+    return HParamsC(hp.n_species, hp.n_layers, hp.l_max, hp.channels, hp.n_basis, hp.envelope_p,
+                    hp.radial_hidden, float(hp.r_cut), float(1.0 / hp.avg_neighbors))
+
+
+def weights_count(hp) -> int:
+    return int(lib.mpip_weights_count(ctypes.byref(hparams_c(hp))))
+
+
+def coupling_tensor(l1: int, l2: int, l3: int) -> np.ndarray:
+    out = np.zeros((2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1), dtype=np.float64)
+    _check(lib.mpip_coupling_tensor(l1, l2, l3, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(2 * l1 + 1, 2 * l2 + 1, 2 * l3 + 1)
+
+
+def _system(positions, species, cell, pbc, n_owned) -> SystemC:
+    s = SystemC()
+    s.n_atoms = int(positions.shape[0])
+    s.n_owned = int(positions.shape[0] if n_owned is None else n_owned)
+    s.positions = positions.data_ptr()
+    s.species = species.data_ptr()
+    c = np.asarray(cell, dtype=np.float64).reshape(9)
+    for k in range(9):
+        s.cell[k] = float(c[k])
+    for k in range(3):
+        s.pbc[k] = 1 if bool(np.asarray(pbc)[k]) else 0
+    return s
+
+
+def _stream_ptr(torch, device, stream=None) -> int:
+    st = torch.cuda.current_stream(device) if stream is None else stream
+    return int(st.cuda_stream)
+
+
+def estimate_edges(n_atoms: int, cell, r_cut: float) -> int:
+    """Edge capacity guess from the mean density of the cell (x1.6 + margin)."""
+    vol = abs(float(np.linalg.det(np.asarray(cell, dtype=np.float64))))
+    dens = n_atoms / vol if vol > 0 else 0.1
+    deg = dens * 4.0 / 3.0 * math.pi * r_cut ** 3
+    return int(n_atoms * max(48.0, 1.6 * deg)) + 1024
+
+
+class Model:
+    """A weight set on one GPU.  ``hp`` has the fields of workloads.HParams."""
+
+    def __init__(self, hp, weights: np.ndarray, device: int = 0):
+        import torch
+        self.torch = torch
+        self.hp = hp
+        self.device = torch.device("cuda", device)
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        self._hpc = hparams_c(hp)
+        h = ctypes.c_void_p()
+        _check(lib.mpip_model_create(ctypes.byref(self._hpc), w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     w.size, device, ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+        self._ws_key = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.mpip_model_destroy(h)
+            self._h = None
+
+    def workspace_bytes(self, n_atoms: int, K: int, precision, max_edges: int) -> int:
+        s = SystemC()
+        s.n_atoms = n_atoms
+        s.n_owned = n_atoms
+        out = ctypes.c_size_t()
+        _check(lib.mpip_workspace_size(self._h, ctypes.byref(s), PRECISIONS[precision], K, max_edges,
+                                       ctypes.byref(out)))
+        return int(out.value)
+
+    def workspace(self, n_atoms: int, K: int, precision, max_edges: int):
+        nbytes = self.workspace_bytes(n_atoms, K, precision, max_edges)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        return self._ws
+
+    def evaluate(self, positions, species, cell, pbc=(True, True, True), K: Optional[int] = None,
+                 precision="fp32", n_owned: Optional[int] = None, atom_energy: bool = False,
+                 max_edges: Optional[int] = None, out=None, stream=None, check: bool = True):
+        """Energy / forces / virial of one system.  ``positions``: cuda
+        float64 [N,3]; ``species``: cuda int32 [N].  Returns a dict of cuda
+        tensors (energy [1], forces [N,3], virial [3,3], atom_energy [N])
+        plus ``n_edges`` when ``check`` is set (synchronises the stream)."""
+        torch = self.torch
+        K = self.hp.n_layers if K is None else int(K)
+        N = int(positions.shape[0])
+        assert positions.dtype == torch.float64 and positions.is_cuda and positions.is_contiguous()
+        assert species.dtype == torch.int32 and species.is_cuda and species.is_contiguous()
+        if max_edges is None:
+            max_edges = estimate_edges(N, cell, self.hp.r_cut)
+        prec = PRECISIONS[precision]
+        for attempt in range(2):
+            ws = self.workspace(N, K, prec, max_edges)
+            if out is None:
+                o = {"energy": torch.empty(1, dtype=torch.float64, device=self.device),
+                     "forces": torch.empty((N, 3), dtype=torch.float64, device=self.device),
+                     "virial": torch.empty((3, 3), dtype=torch.float64, device=self.device),
+                     "atom_energy": (torch.empty(N, dtype=torch.float64, device=self.device)
+                                     if atom_energy else None)}
+            else:
+                o = out
+            oc = OutputsC(o["energy"].data_ptr(), o["forces"].data_ptr(), o["virial"].data_ptr(),
+                          o["atom_energy"].data_ptr() if o.get("atom_energy") is not None else None)
+            sysc = _system(positions, species, cell, pbc, n_owned)
+            sp = _stream_ptr(torch, self.device, stream)
+            _check(lib.mpip_evaluate(self._h, ctypes.byref(sysc), prec, K, ctypes.c_void_p(sp),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), max_edges, ctypes.byref(oc)))
+            if not check:
+                return o
+            ne = ctypes.c_int64()
+            st = lib.mpip_workspace_status(ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(sp), ctypes.byref(ne))
+            if st == ECAPACITY and attempt == 0:
+                max_edges = int(ne.value * 1.05) + 1024
+                continue
+            _check(st)
+            o["n_edges"] = int(ne.value)
+            return o
+        raise MpipError(ECAPACITY, "edge capacity")
+
+
+def read_timing(model: "Model") -> dict:
+    """Per-phase totals since timing was enabled: {name: (ms, calls)}."""
+    t = TimingC()
+    _check(lib.mpip_timing_read(model._h, ctypes.byref(t)))
+    return {t.name[k].value.decode(): (float(t.ms[k]), int(t.calls[k])) for k in range(t.n)}
+
+
+def workspace_status(model: "Model", stream=None) -> int:
+    """Synchronise and return the status code of the model's workspace."""
+    ne = ctypes.c_int64()
+    sp = _stream_ptr(model.torch, model.device, stream)
+    return int(lib.mpip_workspace_status(ctypes.c_void_p(model._ws.data_ptr()), ctypes.c_void_p(sp),
+                                         ctypes.byref(ne)))
+
+
+def neighbor_list(positions, cell, pbc, r_cut: float, capacity: Optional[int] = None, stream=None):
+    """Edges (i, j, S) in input indices as cuda int32 tensors (unordered)."""
+    import torch
+    dev = positions.device
+    N = int(positions.shape[0])
+    species = torch.zeros(N, dtype=torch.int32, device=dev)
+    if capacity is None:
+        capacity = estimate_edges(N, cell, r_cut)
+    for attempt in range(2):
+        nbytes = int(lib.mpip_neighbor_workspace_size(N, capacity))
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        ei = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        ej = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        es = torch.empty((max(capacity, 1), 3), dtype=torch.int32, device=dev)
+        sysc = _system(positions, species, cell, pbc, None)
+        ne = ctypes.c_int64()
+        sp = _stream_ptr(torch, dev, stream)
+        st = lib.mpip_neighbor_list(ctypes.byref(sysc), float(r_cut), ctypes.c_void_p(sp),
+                                    ctypes.c_void_p(ws.data_ptr()), nbytes, capacity, ctypes.c_void_p(ei.data_ptr()),
+                                    ctypes.c_void_p(ej.data_ptr()), ctypes.c_void_p(es.data_ptr()), ctypes.byref(ne))
+        if st == ECAPACITY and attempt == 0 and ne.value > capacity:
+            capacity = int(ne.value) + 16
+            continue
+        _check(st)
+        n = int(ne.value)
+        return ei[:n], ej[:n], es[:n]
+    raise MpipError(ECAPACITY, "edge capacity")
+
+
+def _autograd():
+    import torch
+
+    class MPIPEnergy(torch.autograd.Function):
+        """E(positions) with the library's hand-written adjoint as backward:
+        forward runs one full evaluation (energy, forces, virial); backward
+        returns -grad_E * F for the positions (no second GPU pass).  The
+        virial is returned as a second, non-differentiable output."""
+
+        @staticmethod
+        def forward(ctx, positions, model, species, cell, pbc, K, precision, n_owned):
+            o = model.evaluate(positions.detach(), species, cell, pbc, K=K, precision=precision,
+                               n_owned=n_owned)
+            ctx.save_for_backward(o["forces"])
+            ctx.mark_non_differentiable(o["virial"])
+            return o["energy"][0], o["virial"]
+
+        @staticmethod
+        def backward(ctx, g_energy, g_virial):
+            (F,) = ctx.saved_tensors
+            return -g_energy * F, None, None, None, None, None, None, None
+
+    return MPIPEnergy
+
+
+_MPIPEnergy = None
+
+
+def MPIPEnergy():
+    """The torch.autograd.Function class (created lazily, needs torch)."""
+    global _MPIPEnergy
+    if _MPIPEnergy is None:
+        _MPIPEnergy = _autograd()
+    return _MPIPEnergy
+
+
+def energy(positions, model: Model, species, cell, pbc=(True, True, True), K=None, precision="fp32",
+           n_owned=None):
+    """Differentiable energy: E, W = energy(...); E.backward() gives
+    positions.grad = -F."""
+    return MPIPEnergy().apply(positions, model, species, cell, pbc, K, precision, n_owned)

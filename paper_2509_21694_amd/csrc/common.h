@@ -1,0 +1,54 @@
+// Shared device/host definitions of libmpip (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mpip.h"
+
+namespace mpip {
+
+constexpr int kWave = 64;
+constexpr int kTileE = 16;      // edges per MFMA tile (16x16 MFMA shapes)
+constexpr int kHidden = 64;     // radial MLP hidden width (fixed by this build)
+constexpr int kNB = 8;          // radial basis size (fixed by this build)
+constexpr int kMaxNlm = 9;      // (l_max+1)^2 for l_max <= 2
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+// Status word layout in the workspace (int64 each).
+enum { ST_CODE = 0, ST_NEDGES = 1, ST_FLAGS = 2, ST_WORDS = 8 };
+// Data-dependent error flags (bit mask in ST_FLAGS).
+enum { FL_CAPACITY = 1, FL_SPECIES = 2, FL_NONFINITE = 4, FL_COINCIDENT = 8, FL_BINS = 16 };
+
+// Geometry of the cell list, computed on the device.
+struct GridParams {
+  double lo[3];        // origin of bin 0 per dimension (periodic: 0)
+  double len[3];       // periodic: cell length; non-periodic: covered extent
+  double inv_bin[3];   // 1 / bin width
+  int nb[3];           // bins per dimension
+  int img[3];          // periodic dims with fewer than 3 bins: images -img..img
+  int stencil[3];      // 1: use -1..1 neighbour bins, 0: single bin + image loop
+  int nbins;
+  int pad;
+};
+
+// ---- MFMA wrappers (16x16 output tile, 64 lanes) --------------------------
+// Operand lane layout (verified on gfx950): A[row = lane%16][k-slot],
+// B[k-slot][col = lane%16], where the k-slot of register j in lane group
+// g = lane/16 is the same for A and B; D[row = 4*g + r][col = lane%16].
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float silu(float x) { return x / (1.0f + __expf(-x)); }
+__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + __expf(-x)); }
+__device__ __forceinline__ float dsilu(float x) {
+  float s = sigm(x);
+  return s * (1.0f + x * (1.0f - s));
+}
+
+}  // namespace mpip

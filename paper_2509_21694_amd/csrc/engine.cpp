@@ -1,0 +1,723 @@
+// Host engine and C ABI of libmpip: parameter validation, weight upload in
+// the kernels' operand layouts, workspace planning and the launch sequence
+// of one evaluation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cg.h"
+#include "kernels.h"
+
+using namespace mpip;
+
+namespace {
+
+thread_local std::string g_err;
+
+mpip_status fail(mpip_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t _e = (x);                                                                   \
+    if (_e != hipSuccess) return fail(MPIP_EDEVICE, std::string(#x ": ") + hipGetErrorString(_e)); \
+  } while (0)
+
+uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+  uint32_t r = ((u >> 16) & 1u) + 0x7fffu;
+  return (uint16_t)((u + r) >> 16);
+}
+
+int n_paths_stored(int t, int L) { return (int)layer_paths(t, L).size(); }
+
+bool valid_hp(const mpip_hparams* hp, std::string* why) {
+  if (!hp) { *why = "null hparams"; return false; }
+  if (hp->n_species < 1 || hp->n_species > 64) { *why = "n_species must be in 1..64"; return false; }
+  if (hp->n_layers < 1 || hp->n_layers > 16) { *why = "n_layers must be in 1..16"; return false; }
+  if (hp->l_max < 1 || hp->l_max > 2) { *why = "l_max must be 1 or 2"; return false; }
+  if (hp->channels != 32 && hp->channels != 64 && hp->channels != 128) { *why = "channels must be 32, 64 or 128"; return false; }
+  if (hp->n_basis != kNB) { *why = "n_basis must be 8"; return false; }
+  if (hp->radial_hidden != kHidden) { *why = "radial_hidden must be 64"; return false; }
+  if (hp->envelope_p < 2 || hp->envelope_p > 16) { *why = "envelope_p must be in 2..16"; return false; }
+  if (!(hp->r_cut > 0.0) || !std::isfinite(hp->r_cut)) { *why = "r_cut must be positive"; return false; }
+  if (!std::isfinite(hp->inv_avg_neighbors)) { *why = "inv_avg_neighbors must be finite"; return false; }
+  return true;
+}
+
+size_t count_weights(const mpip_hparams& hp) {
+  const size_t C = hp.channels, H = hp.radial_hidden, nb = hp.n_basis, L = hp.l_max, S = hp.n_species;
+  size_t n = S * C;
+  for (int t = 1; t <= hp.n_layers; ++t) {
+    const size_t nin = (t == 1) ? 1 : (L + 1);
+    n += nin * C * C + nb * H + H * H + H * n_paths_stored(t, (int)L) * C + C * C * (1 + L) + L * C * C;
+  }
+  return n + C + S;
+}
+
+// Device buffer list owned by a model.
+struct DevArena {
+  std::vector<void*> ptrs;
+  ~DevArena() {
+    for (void* p : ptrs) hipFree(p);
+  }
+};
+
+}  // namespace
+
+// Event-pair timer of evaluation phases (enabled on request only).
+struct PhaseTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<std::string, size_t>> pending;  // name, index of start event
+  std::vector<std::string> names;
+  std::vector<double> ms;
+  std::vector<int64_t> calls;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(const std::string& name, hipStream_t s) {
+    if (!on) return;
+    pending.push_back({name, used});
+    hipEventRecord(next(), s);
+  }
+  void end(hipStream_t s) {
+    if (!on) return;
+    hipEventRecord(next(), s);
+  }
+  ~PhaseTimer() {
+    for (hipEvent_t e : pool) hipEventDestroy(e);
+  }
+};
+
+struct mpip_model {
+  mpip_hparams hp;
+  int device;
+  PhaseTimer timer;
+  DevArena arena;
+  // per precision (0 = f32, 1 = bf16), per layer
+  std::vector<LayerDev> layers[2];
+  float* emb = nullptr;
+  float* w_read = nullptr;
+  float* e0 = nullptr;
+};
+
+namespace {
+
+template <typename T>
+mpip_status upload(mpip_model* m, const std::vector<T>& v, const void** out) {
+  void* p = nullptr;
+  size_t bytes = v.size() * sizeof(T);
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(MPIP_ENOMEM, "hipMalloc failed for weights");
+  m->arena.ptrs.push_back(p);
+  if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = p;
+  return MPIP_OK;
+}
+
+// Pack a matrix generator f(lane, slot) into operand arrays.
+// bf16: 8 values per lane per chunk; f32: 1 value per lane per chunk.
+struct Packer {
+  std::vector<uint16_t> b;
+  std::vector<float> f;
+};
+
+inline int phi_bf(int kc, int g, int j) { return 16 * (2 * kc + j / 4) + 4 * g + (j % 4); }
+inline int phi_f(int q, int g) { return 16 * (q / 4) + 4 * g + (q % 4); }
+
+}  // namespace
+
+extern "C" {
+
+size_t mpip_weights_count(const mpip_hparams* hp) {
+  std::string why;
+  if (!valid_hp(hp, &why)) return 0;
+  return count_weights(*hp);
+}
+
+const char* mpip_last_error(void) { return g_err.c_str(); }
+
+mpip_status mpip_coupling_tensor(int32_t l1, int32_t l2, int32_t l3, double* out) {
+  if (!out) return fail(MPIP_EINVAL, "null output");
+  if (!coupling_tensor(l1, l2, l3, out)) return fail(MPIP_EINVAL, "not a natural-parity path with l <= 2");
+  return MPIP_OK;
+}
+
+mpip_status mpip_model_destroy(mpip_model* m) {
+  if (!m) return MPIP_OK;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(m->device);
+  delete m;
+  hipSetDevice(cur);
+  return MPIP_OK;
+}
+
+mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, int32_t device, mpip_model** out) {
+  std::string why;
+  if (!out) return fail(MPIP_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!valid_hp(hp, &why)) return fail(MPIP_EINVAL, why);
+  if (!w) return fail(MPIP_EINVAL, "null weights");
+  if (n != count_weights(*hp)) return fail(MPIP_EINVAL, "weight count does not match the hyper-parameters");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(MPIP_EINVAL, "no such device");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  HIPCHK(hipSetDevice(device));
+  mpip_model* m = new mpip_model();
+  m->hp = *hp;
+  m->device = device;
+  const int C = hp->channels, H = hp->radial_hidden, nb = hp->n_basis, L = hp->l_max, S = hp->n_species;
+  const int T = hp->n_layers;
+  size_t off = 0;
+  auto take = [&](size_t k) { const float* p = w + off; off += k; return p; };
+  mpip_status st = MPIP_OK;
+  const float* emb = take((size_t)S * C);
+  struct LayerHost {
+    std::vector<const float*> up;
+    const float *W1, *W2, *W3;
+    std::vector<const float*> down;
+    int P;
+  };
+  std::vector<LayerHost> lh(T);
+  for (int t = 1; t <= T; ++t) {
+    LayerHost& x = lh[t - 1];
+    const int nin = (t == 1) ? 1 : (L + 1);
+    for (int l = 0; l < nin; ++l) x.up.push_back(take((size_t)C * C));
+    x.W1 = take((size_t)nb * H);
+    x.W2 = take((size_t)H * H);
+    x.P = n_paths_stored(t, L);
+    x.W3 = take((size_t)H * x.P * C);
+    x.down.push_back(take((size_t)C * C * (1 + L)));
+    for (int l = 1; l <= L; ++l) x.down.push_back(take((size_t)C * C));
+  }
+  const float* w_read = take(C);
+  const float* e0 = take(S);
+  (void)off;
+  {
+    const void* p;
+    std::vector<float> v(emb, emb + (size_t)S * C);
+    if ((st = upload(m, v, &p)) != MPIP_OK) goto done;
+    m->emb = (float*)p;
+    std::vector<float> r(w_read, w_read + C);
+    if ((st = upload(m, r, &p)) != MPIP_OK) goto done;
+    m->w_read = (float*)p;
+    std::vector<float> e(e0, e0 + S);
+    if ((st = upload(m, e, &p)) != MPIP_OK) goto done;
+    m->e0 = (float*)p;
+  }
+  for (int prec = 0; prec < 2; ++prec) m->layers[prec].resize(T);
+  for (int t = 1; t <= T; ++t) {
+    const LayerHost& x = lh[t - 1];
+    const std::vector<Path> stored = layer_paths(t, L);
+    const int PC = x.P * C;
+    auto W1 = [&](int n_, int h) { return x.W1[n_ * H + h]; };
+    auto W2 = [&](int a, int b) { return x.W2[a * H + b]; };
+    auto W3 = [&](int h, int col) { return x.W3[(size_t)h * PC + col]; };
+    // live path lists: role 0 (t < K): all stored; role 1 (t == K): l3 == 0
+    std::vector<int> live[2];
+    for (int k = 0; k < (int)stored.size(); ++k) {
+      live[0].push_back(k);
+      if (stored[k].l3 == 0) live[1].push_back(k);
+    }
+    for (int prec = 0; prec < 2; ++prec) {
+      LayerDev& d = m->layers[prec][t - 1];
+      const bool bf = prec == 1;
+      // generic packers
+      auto pack = [&](int nchunk_outer, int nchunk_k, auto val, const void** dst) -> mpip_status {
+        // layout [outer][k][lane][8|1]
+        if (bf) {
+          std::vector<uint16_t> v((size_t)nchunk_outer * nchunk_k * 64 * 8);
+          for (int o = 0; o < nchunk_outer; ++o)
+            for (int k = 0; k < nchunk_k; ++k)
+              for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j)
+                  v[(((size_t)o * nchunk_k + k) * 64 + lane) * 8 + j] = f2bf(val(o, k, lane, j));
+          return upload(m, v, dst);
+        } else {
+          std::vector<float> v((size_t)nchunk_outer * nchunk_k * 64);
+          for (int o = 0; o < nchunk_outer; ++o)
+            for (int k = 0; k < nchunk_k; ++k)
+              for (int lane = 0; lane < 64; ++lane)
+                v[((size_t)o * nchunk_k + k) * 64 + lane] = val(o, k, lane, 0);
+          return upload(m, v, dst);
+        }
+      };
+      const int KC64 = bf ? 2 : 16;
+      // w1a: [mt 4][k][lane]: row h = 16mt + lane%16; bf16 k-slot (g,j) -> basis 8g+j; f32 chunk q -> basis 4q+g
+      if ((st = pack(4, bf ? 1 : 2, [&](int mt, int k, int lane, int j) {
+             const int h = 16 * mt + (lane & 15), g = lane >> 4;
+             const int n_ = bf ? (8 * g + j) : (4 * k + g);
+             return n_ < nb ? W1(n_, h) : 0.f;
+           }, &d.w1a)) != MPIP_OK) goto done;
+      if ((st = pack(4, KC64, [&](int mt, int k, int lane, int j) {
+             const int h2 = 16 * mt + (lane & 15), g = lane >> 4;
+             const int h1 = bf ? phi_bf(k, g, j) : phi_f(k, g);
+             return W2(h1, h2);
+           }, &d.w2a)) != MPIP_OK) goto done;
+      if ((st = pack(4, KC64, [&](int mt, int k, int lane, int j) {
+             const int h1 = 16 * mt + (lane & 15), g = lane >> 4;
+             const int h2 = bf ? phi_bf(k, g, j) : phi_f(k, g);
+             return W2(h1, h2);
+           }, &d.w2b)) != MPIP_OK) goto done;
+      if ((st = pack(1, KC64, [&](int, int k, int lane, int j) {
+             const int n_ = lane & 15, g = lane >> 4;
+             const int h1 = bf ? phi_bf(k, g, j) : phi_f(k, g);
+             return n_ < nb ? W1(n_, h1) : 0.f;
+           }, &d.w1b)) != MPIP_OK) goto done;
+      for (int role = 0; role < 2; ++role) {
+        const std::vector<int>& lv = live[role];
+        const int NPl = (int)lv.size();
+        // w3f: [pi][nt][kc][lane]: col c = 16nt + lane%16, k-slot -> hidden
+        if ((st = pack(NPl * (C / 16), KC64, [&](int o, int k, int lane, int j) {
+               const int pi = o / (C / 16), nt = o % (C / 16), g = lane >> 4;
+               const int c = 16 * nt + (lane & 15);
+               const int h = bf ? phi_bf(k, g, j) : phi_f(k, g);
+               return W3(h, lv[pi] * C + c);
+             }, &d.w3f[role])) != MPIP_OK) goto done;
+        const int KCC = bf ? C / 32 : C / 4;
+        // w3b: [pi][mt][kc][lane]: row h = 16mt + lane%16, k-slot -> channel
+        if ((st = pack(NPl * 4, KCC, [&](int o, int k, int lane, int j) {
+               const int pi = o / 4, mt = o % 4, g = lane >> 4;
+               const int h = 16 * mt + (lane & 15);
+               const int c = bf ? (32 * k + 8 * g + j) : (4 * k + g);
+               return W3(h, lv[pi] * C + c);
+             }, &d.w3b[role])) != MPIP_OK) goto done;
+        std::vector<float> cgv;
+        for (int pi = 0; pi < NPl; ++pi) {
+          const Path& pp = stored[lv[pi]];
+          const int nn = (2 * pp.l1 + 1) * (2 * pp.l2 + 1) * (2 * pp.l3 + 1);
+          std::vector<double> tmp(nn);
+          if (!coupling_tensor(pp.l1, pp.l2, pp.l3, tmp.data())) { st = fail(MPIP_EINVAL, "coupling"); goto done; }
+          for (double v : tmp) cgv.push_back((float)v);
+        }
+        const void* cgp;
+        if ((st = upload(m, cgv, &cgp)) != MPIP_OK) goto done;
+        d.cg[role] = (const float*)cgp;
+      }
+      // node matrices, [Nout][K] with k contiguous
+      auto node = [&](const float* Wm, int rows, int cols, bool transpose, const void** dst) -> mpip_status {
+        // Wm is [rows][cols]; transpose: out[c][r] = Wm[r][c]
+        const int NO = transpose ? cols : rows, KK = transpose ? rows : cols;
+        if (bf) {
+          std::vector<uint16_t> v((size_t)NO * KK);
+          for (int a = 0; a < NO; ++a)
+            for (int b = 0; b < KK; ++b) v[(size_t)a * KK + b] = f2bf(transpose ? Wm[(size_t)b * cols + a] : Wm[(size_t)a * cols + b]);
+          return upload(m, v, dst);
+        } else {
+          std::vector<float> v((size_t)NO * KK);
+          for (int a = 0; a < NO; ++a)
+            for (int b = 0; b < KK; ++b) v[(size_t)a * KK + b] = transpose ? Wm[(size_t)b * cols + a] : Wm[(size_t)a * cols + b];
+          return upload(m, v, dst);
+        }
+      };
+      for (int l = 0; l < 3; ++l) { d.up_t[l] = d.up[l] = d.down_t[l] = d.down[l] = nullptr; }
+      for (int l = 0; l < (int)x.up.size(); ++l) {
+        if ((st = node(x.up[l], C, C, true, &d.up_t[l])) != MPIP_OK) goto done;
+        if ((st = node(x.up[l], C, C, false, &d.up[l])) != MPIP_OK) goto done;
+      }
+      if ((st = node(x.down[0], C, C * (1 + L), true, &d.down_t[0])) != MPIP_OK) goto done;
+      if ((st = node(x.down[0], C, C * (1 + L), false, &d.down[0])) != MPIP_OK) goto done;
+      for (int l = 1; l <= L; ++l) {
+        if ((st = node(x.down[l], C, C, true, &d.down_t[l])) != MPIP_OK) goto done;
+        if ((st = node(x.down[l], C, C, false, &d.down[l])) != MPIP_OK) goto done;
+      }
+    }
+  }
+  HIPCHK(hipDeviceSynchronize());
+done:
+  hipSetDevice(cur);
+  if (st != MPIP_OK) {
+    delete m;
+    return st;
+  }
+  *out = m;
+  return MPIP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ workspace
+
+namespace {
+
+struct Plan {
+  size_t total = 0;
+  size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_scan, o_info, o_perm, o_iperm, o_pos,
+      o_info_s, o_spec, o_owned, o_cnt, o_row, o_esrc, o_eshift, o_evec, o_erev, o_g;
+  size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
+  std::vector<size_t> o_ht, o_z0, o_zl;  // per layer 1..K (index t-1)
+  int max_bins;
+  int nblocks_out;
+};
+
+size_t take(size_t& cur, size_t bytes) {
+  size_t o = (cur + 255) & ~(size_t)255;
+  cur = o + bytes;
+  return o;
+}
+
+Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
+  Plan p;
+  size_t cur = 0;
+  p.max_bins = (int)std::min<int64_t>(std::max<int64_t>(4096, 2 * N), 1 << 26);
+  p.o_status = take(cur, sizeof(int64_t) * ST_WORDS);
+  p.o_bounds = take(cur, sizeof(double) * kBoundsParts * 6);
+  p.o_grid = take(cur, sizeof(GridParams));
+  p.o_bcount = take(cur, sizeof(int32_t) * (p.max_bins + 1));
+  p.o_bcursor = take(cur, sizeof(int32_t) * (p.max_bins + 1));
+  p.o_bstart = take(cur, sizeof(int32_t) * (p.max_bins + 1));
+  p.o_scan = take(cur, sizeof(int32_t) * scan_tmp_elems(std::max<int64_t>(N, p.max_bins) + 1));
+  p.o_info = take(cur, sizeof(int4) * N);
+  p.o_perm = take(cur, sizeof(int32_t) * N);
+  p.o_iperm = take(cur, sizeof(int32_t) * N);
+  p.o_pos = take(cur, sizeof(double) * 3 * N);
+  p.o_info_s = take(cur, sizeof(int4) * N);
+  p.o_spec = take(cur, sizeof(int32_t) * N);
+  p.o_owned = take(cur, N);
+  p.o_cnt = take(cur, sizeof(int32_t) * N);
+  p.o_row = take(cur, sizeof(int32_t) * (N + 1));
+  p.o_esrc = take(cur, sizeof(int32_t) * cap);
+  p.o_eshift = take(cur, sizeof(uint32_t) * cap);
+  p.o_evec = take(cur, sizeof(float4) * cap);
+  p.o_erev = take(cur, sizeof(int32_t) * cap);
+  if (hp) {
+    const int64_t C = hp->channels, L = hp->l_max, nlm = (L + 1) * (L + 1), S = hp->n_species;
+    p.o_g = take(cur, sizeof(float4) * cap);
+    p.o_ht1 = take(cur, sizeof(float) * S * C);
+    p.o_h = take(cur, sizeof(float) * N * nlm * C);
+    p.o_A = take(cur, sizeof(float) * N * nlm * C);
+    p.o_hbar = take(cur, sizeof(float) * N * nlm * C);
+    p.o_htbar = take(cur, sizeof(float) * N * nlm * C);
+    for (int t = 1; t <= K; ++t) {
+      p.o_ht.push_back(t >= 2 ? take(cur, sizeof(float) * N * nlm * C) : 0);
+      p.o_z0.push_back(take(cur, sizeof(float) * N * C * (1 + L)));
+      p.o_zl.push_back(t < K ? take(cur, sizeof(float) * N * (nlm - 1) * C) : 0);
+    }
+    p.o_atom_e = take(cur, sizeof(double) * N);
+    p.nblocks_out = (int)((N + 255) / 256);
+    p.o_partials = take(cur, sizeof(double) * 10 * p.nblocks_out);
+  }
+  p.total = cur + 256;
+  return p;
+}
+
+mpip_status check_system(const mpip_system* sys, CellInfo* ci, double rc, int n_species) {
+  if (!sys) return fail(MPIP_EINVAL, "null system");
+  if (sys->n_atoms < 1 || sys->n_atoms > (int64_t)1 << 30) return fail(MPIP_EINVAL, "n_atoms out of range");
+  if (sys->n_owned < 0 || sys->n_owned > sys->n_atoms) return fail(MPIP_EINVAL, "n_owned out of range");
+  if (!sys->positions || !sys->species) return fail(MPIP_EINVAL, "null positions or species");
+  for (int k = 0; k < 9; ++k) {
+    if (!std::isfinite(sys->cell[k])) return fail(MPIP_ECELL, "non-finite cell");
+    ci->cell[k] = sys->cell[k];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      if (r != c && sys->cell[3 * r + c] != 0.0)
+        return fail(MPIP_EUNSUPPORTED, "only orthorhombic cells are supported");
+  for (int d = 0; d < 3; ++d) {
+    ci->pbc[d] = sys->pbc[d] ? 1 : 0;
+    ci->L[d] = sys->cell[4 * d];
+    if (ci->pbc[d] && !(ci->L[d] > 0.0)) return fail(MPIP_ECELL, "periodic cell length must be positive");
+  }
+  ci->rc = rc;
+  ci->n_species = n_species;
+  return MPIP_OK;
+}
+
+NbrBuffers nbr_buffers(char* ws, const Plan& p) {
+  NbrBuffers b;
+  b.status = (int64_t*)(ws + p.o_status);
+  b.bounds = (double*)(ws + p.o_bounds);
+  b.grid = (GridParams*)(ws + p.o_grid);
+  b.max_bins = p.max_bins;
+  b.bin_count = (int32_t*)(ws + p.o_bcount);
+  b.bin_cursor = (int32_t*)(ws + p.o_bcursor);
+  b.bin_start = (int32_t*)(ws + p.o_bstart);
+  b.scan_tmp = (int32_t*)(ws + p.o_scan);
+  b.info = (int4*)(ws + p.o_info);
+  b.perm = (int32_t*)(ws + p.o_perm);
+  b.inv_perm = (int32_t*)(ws + p.o_iperm);
+  b.pos_s = (double*)(ws + p.o_pos);
+  b.info_s = (int4*)(ws + p.o_info_s);
+  b.spec_s = (int32_t*)(ws + p.o_spec);
+  b.owned_s = (uint8_t*)(ws + p.o_owned);
+  b.cnt = (int32_t*)(ws + p.o_cnt);
+  b.row_ptr = (int32_t*)(ws + p.o_row);
+  b.e_src = (int32_t*)(ws + p.o_esrc);
+  b.e_shift = (uint32_t*)(ws + p.o_eshift);
+  b.e_vec = (float4*)(ws + p.o_evec);
+  b.e_rev = (int32_t*)(ws + p.o_erev);
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpip_status mpip_workspace_size(const mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K,
+                                int64_t max_edges, size_t* bytes) {
+  if (!m || !sys || !bytes) return fail(MPIP_EINVAL, "null argument");
+  if (prec != MPIP_FP32 && prec != MPIP_BF16_MIXED) return fail(MPIP_EINVAL, "bad precision");
+  if (K < 1 || K > m->hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
+  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  if (sys->n_atoms < 1) return fail(MPIP_EINVAL, "n_atoms must be >= 1");
+  *bytes = make_plan(sys->n_atoms, max_edges, &m->hp, K).total;
+  return MPIP_OK;
+}
+
+size_t mpip_neighbor_workspace_size(int64_t n_atoms, int64_t capacity) {
+  if (n_atoms < 1 || capacity < 0) return 0;
+  return make_plan(n_atoms, capacity, nullptr, 0).total;
+}
+
+mpip_status mpip_workspace_status(const void* ws, void* stream, int64_t* n_edges) {
+  if (!ws) return fail(MPIP_EINVAL, "null workspace");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  int64_t st[ST_WORDS];
+  HIPCHK(hipMemcpy(st, ws, sizeof(st), hipMemcpyDeviceToHost));
+  if (n_edges) *n_edges = st[ST_NEDGES];
+  const int64_t fl = st[ST_FLAGS];
+  if (fl & FL_CAPACITY) return fail(MPIP_ECAPACITY, "edge capacity exceeded");
+  if (fl & FL_SPECIES) return fail(MPIP_EINVAL, "species out of range");
+  if (fl & FL_NONFINITE) return fail(MPIP_EINVAL, "non-finite position");
+  if (fl & FL_COINCIDENT) return fail(MPIP_EINVAL, "coincident atoms");
+  if (fl) return fail(MPIP_EINVAL, "data error");
+  return MPIP_OK;
+}
+
+mpip_status mpip_neighbor_list(const mpip_system* sys, double r_cut, void* stream, void* ws, size_t ws_bytes,
+                               int64_t capacity, int32_t* oi, int32_t* oj, int32_t* os, int64_t* n_edges) {
+  CellInfo ci;
+  mpip_status st = check_system(sys, &ci, r_cut, 1 << 30);
+  if (st != MPIP_OK) return st;
+  if (!(r_cut > 0.0)) return fail(MPIP_EINVAL, "r_cut must be positive");
+  if (!ws || !n_edges || capacity < 0) return fail(MPIP_EINVAL, "bad workspace or outputs");
+  if (capacity > 0 && (!oi || !oj || !os)) return fail(MPIP_EINVAL, "null edge outputs");
+  Plan p = make_plan(sys->n_atoms, capacity, nullptr, 0);
+  if (ws_bytes < p.total) return fail(MPIP_ECAPACITY, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  NbrBuffers b = nbr_buffers((char*)ws, p);
+  launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
+  build_neighbors(b, *sys, ci, capacity, s);
+  HIPCHK(hipGetLastError());
+  int64_t ne = 0;
+  st = mpip_workspace_status(ws, stream, &ne);
+  *n_edges = ne;
+  if (st != MPIP_OK) return st;
+  export_neighbors(b, sys->n_atoms, capacity, oi, oj, os, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return MPIP_OK;
+}
+
+mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K, void* stream,
+                          void* ws, size_t ws_bytes, int64_t max_edges, const mpip_outputs* out) {
+  if (!m) return fail(MPIP_EINVAL, "null model");
+  const mpip_hparams& hp = m->hp;
+  CellInfo ci;
+  mpip_status st = check_system(sys, &ci, hp.r_cut, hp.n_species);
+  if (st != MPIP_OK) return st;
+  if (prec != MPIP_FP32 && prec != MPIP_BF16_MIXED) return fail(MPIP_EINVAL, "bad precision");
+  if (K < 1 || K > hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
+  if (!out || !out->energy || !out->forces || !out->virial) return fail(MPIP_EINVAL, "null output buffer");
+  if (!ws) return fail(MPIP_EINVAL, "null workspace");
+  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  const int64_t N = sys->n_atoms;
+  Plan p = make_plan(N, max_edges, &hp, K);
+  if (ws_bytes < p.total) return fail(MPIP_ECAPACITY, "workspace too small");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != m->device) HIPCHK(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  NbrBuffers b = nbr_buffers(w, p);
+  const int C = hp.channels, L = hp.l_max, nlm = (L + 1) * (L + 1), S = hp.n_species;
+  const int pi = prec == MPIP_BF16_MIXED ? 1 : 0;
+  const std::vector<LayerDev>& LD = m->layers[pi];
+  float* ht1 = (float*)(w + p.o_ht1);
+  float* h = (float*)(w + p.o_h);
+  float* A = (float*)(w + p.o_A);
+  float* hbar = (float*)(w + p.o_hbar);
+  float* htbar = (float*)(w + p.o_htbar);
+  float4* g = (float4*)(w + p.o_g);
+  double* atom_e = (double*)(w + p.o_atom_e);
+
+  PhaseTimer& T = m->timer;
+  launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
+  T.begin("neighbors", s);
+  build_neighbors(b, *sys, ci, max_edges, s);
+  T.end(s);
+
+  EdgeArgs ea;
+  ea.n = N;
+  ea.row_ptr = b.row_ptr;
+  ea.e_src = b.e_src;
+  ea.e_vec = b.e_vec;
+  ea.spec_s = b.spec_s;
+  ea.capacity = max_edges;
+  ea.status = b.status;
+  ea.rc = (float)hp.r_cut;
+  ea.inv_n = (float)hp.inv_avg_neighbors;
+  ea.envelope_p = hp.envelope_p;
+  ea.g = g;
+  ea.htbar = htbar;
+
+  NodeArgs na;
+  na.n = N; na.C = C; na.L = L; na.nlm = nlm;
+  na.spec_s = b.spec_s; na.owned_s = b.owned_s;
+  na.emb = m->emb; na.w_read = m->w_read; na.e0 = m->e0;
+  na.h = h; na.hbar = hbar; na.atom_e = atom_e;
+
+  auto gemm = [&](const float* x, int64_t xs, int64_t xr, float* y, int64_t ys, int64_t yr, int64_t M, int rpa,
+                  int Kd, int Nout, int ldw, const void* wt, int accumulate) {
+    GemmArgs ga{x, xs, xr, y, ys, yr, M, rpa, Kd, Nout, ldw, wt, accumulate};
+    T.begin("node_gemm", s);
+    launch_gemm(prec, ga, s);
+    T.end(s);
+  };
+  // layer-1 input features depend on species only: ht1 = W_emb @ W_up[1][0]
+  gemm(m->emb, C, 0, ht1, C, 0, S, 1, C, C, C, LD[0].up_t[0], 0);
+
+  auto kind_of = [&](int t) {
+    if (t == 1) return K == 1 ? KIND_ONLY : KIND_FIRST;
+    return t == K ? KIND_LAST : KIND_MID;
+  };
+  const int nz = C * (1 + L);
+  for (int t = 1; t <= K; ++t) {
+    const LayerDev& d = LD[t - 1];
+    const int kind = kind_of(t), role = (t == K) ? 1 : 0;
+    const int nout = (kind == KIND_ONLY || kind == KIND_LAST) ? 1 : nlm;
+    float* ht = (t == 1) ? ht1 : (float*)(w + p.o_ht[t - 1]);
+    if (t >= 2)
+      for (int l = 0; l <= L; ++l)
+        gemm(h + l * l * C, (int64_t)nlm * C, C, ht + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1), 2 * l + 1, C,
+             C, C, d.up_t[l], 0);
+    ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;
+    ea.w3f = d.w3f[role]; ea.w3b = d.w3b[role]; ea.cg = d.cg[role];
+    ea.ht = ht; ea.A = A;
+    T.begin("edge_fwd_t" + std::to_string(t), s);
+    launch_edge_fwd(prec, C, L, kind, ea, s);
+    T.end(s);
+    float* z0 = (float*)(w + p.o_z0[t - 1]);
+    float* zl = t < K ? (float*)(w + p.o_zl[t - 1]) : nullptr;
+    gemm(A, (int64_t)nout * C, 0, z0, nz, 0, N, 1, C, (t == K) ? C : nz, C, d.down_t[0], 0);
+    if (t < K)
+      for (int l = 1; l <= L; ++l)
+        gemm(A + l * l * C, (int64_t)nlm * C, C, zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, N * (2 * l + 1),
+             2 * l + 1, C, C, C, d.down_t[l], 0);
+    na.z0 = z0; na.zl = zl;
+    T.begin("gates", s);
+    launch_gate_fwd(na, t == 1, t == K, s);
+    T.end(s);
+  }
+  T.begin("gates", s);
+  launch_readout(na, s);
+  T.end(s);
+
+  // ---------------- adjoint ----------------
+  T.begin("outputs", s);
+  launch_zero(g, sizeof(float4) * (size_t)max_edges, s);
+  T.end(s);
+  for (int t = K; t >= 1; --t) {
+    const LayerDev& d = LD[t - 1];
+    const int kind = kind_of(t), role = (t == K) ? 1 : 0;
+    const int nout = (kind == KIND_ONLY || kind == KIND_LAST) ? 1 : nlm;
+    float* ht = (t == 1) ? ht1 : (float*)(w + p.o_ht[t - 1]);
+    float* z0 = (float*)(w + p.o_z0[t - 1]);
+    float* zl = t < K ? (float*)(w + p.o_zl[t - 1]) : nullptr;
+    na.z0 = z0; na.zl = zl;
+    T.begin("gates", s);
+    launch_gate_bwd(na, t == K, (t == K && K >= 2) ? 1 : 0, s);
+    T.end(s);
+    // Abar (in A) = zbar @ W_down^T
+    gemm(z0, nz, 0, A, (int64_t)nout * C, 0, N, 1, (t == K) ? C : nz, C, nz, d.down[0], 0);
+    if (t < K)
+      for (int l = 1; l <= L; ++l)
+        gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
+             2 * l + 1, C, C, C, d.down[l], 0);
+    ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;
+    ea.w3f = d.w3f[role]; ea.w3b = d.w3b[role]; ea.cg = d.cg[role];
+    ea.ht = ht; ea.Abar = A;
+    T.begin("edge_bwd_t" + std::to_string(t), s);
+    launch_edge_bwd(prec, C, L, kind, ea, s);
+    T.end(s);
+    if (t >= 2)
+      for (int l = 0; l <= L; ++l)
+        gemm(htbar + l * l * C, (int64_t)nlm * C, C, hbar + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
+             2 * l + 1, C, C, C, d.up[l], 1);
+  }
+  OutArgs oa;
+  oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = g; oa.e_rev = b.e_rev; oa.perm = b.perm;
+  oa.owned_s = b.owned_s; oa.atom_e = atom_e; oa.capacity = max_edges; oa.status = b.status;
+  oa.partials = (double*)(w + p.o_partials); oa.nblocks = p.nblocks_out;
+  oa.forces = out->forces; oa.atom_energy = out->atom_energy; oa.energy = out->energy; oa.virial = out->virial;
+  T.begin("outputs", s);
+  launch_outputs(oa, s);
+  T.end(s);
+  hipError_t e = hipGetLastError();
+  if (cur != m->device) hipSetDevice(cur);
+  if (e != hipSuccess) return fail(MPIP_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return MPIP_OK;
+}
+
+mpip_status mpip_timing_enable(mpip_model* m, int32_t on) {
+  if (!m) return fail(MPIP_EINVAL, "null model");
+  PhaseTimer& T = m->timer;
+  T.on = on != 0;
+  T.used = 0;
+  T.pending.clear();
+  T.names.clear();
+  T.ms.clear();
+  T.calls.clear();
+  return MPIP_OK;
+}
+
+mpip_status mpip_timing_read(mpip_model* m, mpip_timing* out) {
+  if (!m || !out) return fail(MPIP_EINVAL, "null argument");
+  PhaseTimer& T = m->timer;
+  for (const auto& pr : T.pending) {
+    hipEvent_t a = T.pool[pr.second], b = T.pool[pr.second + 1];
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    size_t k = 0;
+    while (k < T.names.size() && T.names[k] != pr.first) ++k;
+    if (k == T.names.size()) {
+      T.names.push_back(pr.first);
+      T.ms.push_back(0.0);
+      T.calls.push_back(0);
+    }
+    T.ms[k] += ms;
+    T.calls[k] += 1;
+  }
+  T.pending.clear();
+  T.used = 0;
+  std::memset(out, 0, sizeof(*out));
+  out->n = (int32_t)std::min<size_t>(T.names.size(), MPIP_MAX_PHASES);
+  for (int k = 0; k < out->n; ++k) {
+    std::strncpy(out->name[k], T.names[k].c_str(), sizeof(out->name[k]) - 1);
+    out->ms[k] = T.ms[k];
+    out->calls[k] = T.calls[k];
+  }
+  return MPIP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,430 @@
+// Cell list and neighbour list (CSR, receiver-sorted) for gfx950.
+//
+// Atoms are binned by their wrapped position, counting-sorted by bin (ties
+// broken by input index, so the order is deterministic), and every later
+// kernel works in this spatially sorted order.  Each atom scans the 27
+// neighbouring bins (or, along periodic directions too thin for three bins,
+// a range of periodic images) and keeps (i, j, S) iff the FP64 test
+//   s_k = (S0*cell[0][k] + S1*cell[1][k]) + S2*cell[2][k]
+//   dx_k = (x_j[k] - x_i[k]) + s_k,  d2 = (dx0*dx0 + dx1*dx1) + dx2*dx2 < rc*rc
+// holds, evaluated on the raw input positions with one rounding per
+// operation (no contraction), so the edge set is reproducible bit for bit.
+#include "kernels.h"
+
+namespace mpip {
+
+// ---------------------------------------------------------------- scans
+
+// Exclusive scan of n int32 values into out[0..n] (out[n] = total).
+// Three launches: per-block sums, one-block scan of the sums, local scans.
+static constexpr int kScanBlock = 256, kScanPer = 4, kScanTile = kScanBlock * kScanPer;
+
+__global__ void k_scan_partials(const int32_t* __restrict__ in, int64_t n, int32_t* __restrict__ sums) {
+  __shared__ int32_t sh[kScanBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int32_t s = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    int64_t idx = base + threadIdx.x * kScanPer + k;
+    if (idx < n) s += in[idx];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kScanBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = sh[0];
+}
+
+__global__ void k_scan_sums(int32_t* __restrict__ sums, int64_t nblocks) {
+  // single block of kScanBlock threads; sequential carry over chunks
+  __shared__ int32_t sh[kScanBlock];
+  int32_t carry = 0;
+  for (int64_t c0 = 0; c0 < nblocks; c0 += kScanBlock) {
+    int64_t idx = c0 + threadIdx.x;
+    int32_t v = idx < nblocks ? sums[idx] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+      int32_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (idx < nblocks) sums[idx] = carry + sh[threadIdx.x] - v;  // exclusive
+    int32_t tot = sh[kScanBlock - 1];
+    __syncthreads();
+    carry += tot;
+  }
+}
+
+__global__ void k_scan_local(const int32_t* __restrict__ in, int64_t n, const int32_t* __restrict__ sums,
+                             int32_t* __restrict__ out) {
+  __shared__ int32_t sh[kScanBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int32_t v[kScanPer];
+  int32_t s = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    int64_t idx = base + threadIdx.x * kScanPer + k;
+    v[k] = idx < n ? in[idx] : 0;
+    s += v[k];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    int32_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int32_t run = sums[blockIdx.x] + sh[threadIdx.x] - s;
+  for (int k = 0; k < kScanPer; ++k) {
+    int64_t idx = base + threadIdx.x * kScanPer + k;
+    if (idx < n) out[idx] = run;
+    run += v[k];
+    if (idx == n - 1) out[n] = run;
+  }
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+void exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s) {
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 0) {
+    hipMemsetAsync(out, 0, sizeof(int32_t), s);
+    return;
+  }
+  k_scan_partials<<<nb, kScanBlock, 0, s>>>(in, n, tmp);
+  k_scan_sums<<<1, kScanBlock, 0, s>>>(tmp, nb);
+  k_scan_local<<<nb, kScanBlock, 0, s>>>(in, n, tmp, out);
+}
+
+// ---------------------------------------------------------------- binning
+
+__global__ void k_bounds(const double* __restrict__ pos, const int32_t* __restrict__ spec, int64_t n,
+                         int n_species, double* __restrict__ part, int64_t* __restrict__ status) {
+  __shared__ double sh[6][256];
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int d = 0; d < 3; ++d) {
+      double x = pos[3 * i + d];
+      if (!isfinite(x)) bad |= FL_NONFINITE;
+      else { mn[d] = fmin(mn[d], x); mx[d] = fmax(mx[d], x); }
+    }
+    int sp = spec[i];
+    if (sp < 0 || sp >= n_species) bad |= FL_SPECIES;
+  }
+  if (bad) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)bad);
+  for (int d = 0; d < 3; ++d) { sh[d][threadIdx.x] = mn[d]; sh[3 + d][threadIdx.x] = mx[d]; }
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + off]);
+        sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + off]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_grid(const double* __restrict__ part, int nparts, CellInfo ci, int max_bins,
+                       GridParams* __restrict__ gp, int64_t* __restrict__ status) {
+  if (threadIdx.x != 0) return;
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (int b = 0; b < nparts; ++b)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = fmin(mn[d], part[b * 6 + d]);
+      mx[d] = fmax(mx[d], part[b * 6 + 3 + d]);
+    }
+  const double wmin = ci.rc * (1.0 + 1e-6);
+  GridParams g;
+  for (int d = 0; d < 3; ++d) {
+    g.img[d] = 0;
+    if (ci.pbc[d]) {
+      double L = ci.L[d];
+      int nb = (int)floor(L / wmin);
+      g.lo[d] = 0.0;
+      g.len[d] = L;
+      if (nb >= 3) {
+        g.nb[d] = nb; g.stencil[d] = 1; g.inv_bin[d] = (double)nb / L;
+      } else {
+        g.nb[d] = 1; g.stencil[d] = 0; g.inv_bin[d] = 0.0;
+        g.img[d] = (int)ceil(ci.rc / L) + 1;
+      }
+    } else {
+      double ext = (mx[d] >= mn[d]) ? (mx[d] - mn[d]) : 0.0;
+      int nb = (int)floor(ext / wmin);
+      if (nb < 1) nb = 1;
+      g.lo[d] = mn[d];
+      g.len[d] = ext;
+      g.nb[d] = nb; g.stencil[d] = 1;
+      g.inv_bin[d] = ext > 0.0 ? (double)nb / ext : 0.0;
+    }
+  }
+  // keep the total bin count within the workspace: widen bins (still >= rc)
+  while ((int64_t)g.nb[0] * g.nb[1] * g.nb[2] > max_bins) {
+    int d = 0;
+    for (int k = 1; k < 3; ++k) if (g.nb[k] > g.nb[d]) d = k;
+    int nb = g.nb[d] / 2;
+    if (ci.pbc[d] && nb < 3) {
+      g.nb[d] = 1; g.stencil[d] = 0; g.inv_bin[d] = 0.0; g.img[d] = (int)ceil(ci.rc / ci.L[d]) + 1;
+    } else {
+      if (nb < 1) nb = 1;
+      g.nb[d] = nb;
+      g.inv_bin[d] = g.len[d] > 0.0 ? (double)nb / g.len[d] : 0.0;
+    }
+  }
+  g.nbins = g.nb[0] * g.nb[1] * g.nb[2];
+  g.pad = 0;
+  *gp = g;
+  (void)status;
+}
+
+// image index n_d (periodic: x = w + n*L with w in [0, L)) and bin id
+__global__ void k_bin_assign(const double* __restrict__ pos, int64_t n, CellInfo ci,
+                             const GridParams* __restrict__ gp, int4* __restrict__ info,
+                             int32_t* __restrict__ bin_count) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  GridParams g = *gp;
+  int nimg[3], b[3];
+  for (int d = 0; d < 3; ++d) {
+    double x = pos[3 * i + d];
+    double w;
+    if (ci.pbc[d]) {
+      double L = ci.L[d];
+      double fl = floor(x / L);
+      w = x - fl * L;
+      nimg[d] = (int)fl;
+    } else {
+      w = x - g.lo[d];
+      nimg[d] = 0;
+    }
+    int bb = (int)floor(w * g.inv_bin[d]);
+    bb = bb < 0 ? 0 : (bb >= g.nb[d] ? g.nb[d] - 1 : bb);
+    b[d] = bb;
+  }
+  int bin = (b[2] * g.nb[1] + b[1]) * g.nb[0] + b[0];
+  info[i] = make_int4(nimg[0], nimg[1], nimg[2], bin);
+  atomicAdd(&bin_count[bin], 1);
+}
+
+__global__ void k_bin_fill(const int4* __restrict__ info, int64_t n, const int32_t* __restrict__ bin_start,
+                           int32_t* __restrict__ cursor, int32_t* __restrict__ bin_atoms) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int bin = info[i].w;
+  int slot = atomicAdd(&cursor[bin], 1);
+  bin_atoms[bin_start[bin] + slot] = (int32_t)i;
+}
+
+// insertion sort of each bin's atoms by input index (deterministic order)
+__global__ void k_bin_sort(const GridParams* __restrict__ gp, const int32_t* __restrict__ bin_start,
+                           int32_t* __restrict__ bin_atoms) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= gp->nbins) return;
+  int s = bin_start[b], e = bin_start[b + 1];
+  for (int k = s + 1; k < e; ++k) {
+    int v = bin_atoms[k];
+    int q = k - 1;
+    while (q >= s && bin_atoms[q] > v) { bin_atoms[q + 1] = bin_atoms[q]; --q; }
+    bin_atoms[q + 1] = v;
+  }
+}
+
+__global__ void k_gather_sorted(const int32_t* __restrict__ perm, int64_t n, const double* __restrict__ pos,
+                                const int32_t* __restrict__ spec, const int4* __restrict__ info,
+                                int64_t n_owned, int n_species, double* __restrict__ pos_s, int4* __restrict__ info_s,
+                                int32_t* __restrict__ spec_s, int32_t* __restrict__ inv_perm,
+                                uint8_t* __restrict__ owned_s) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int o = perm[k];
+  pos_s[3 * k + 0] = pos[3 * (int64_t)o + 0];
+  pos_s[3 * k + 1] = pos[3 * (int64_t)o + 1];
+  pos_s[3 * k + 2] = pos[3 * (int64_t)o + 2];
+  info_s[k] = info[o];
+  int sp = spec[o];  // out-of-range species are flagged by k_bounds; clamp so reads stay in bounds
+  spec_s[k] = sp < 0 ? 0 : (sp >= n_species ? n_species - 1 : sp);
+  inv_perm[o] = (int32_t)k;
+  owned_s[k] = (uint8_t)(o < n_owned ? 1 : 0);
+}
+
+// ---------------------------------------------------------------- neighbours
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ bool pair_test(const double* __restrict__ xi, const double* __restrict__ xj,
+                                          const CellInfo& ci, int S0, int S1, int S2, double rc2,
+                                          double* dxo) {
+  double dx[3];
+  for (int k = 0; k < 3; ++k) {
+    double s = __dadd_rn(__dadd_rn(__dmul_rn((double)S0, ci.cell[0 * 3 + k]),
+                                   __dmul_rn((double)S1, ci.cell[1 * 3 + k])),
+                         __dmul_rn((double)S2, ci.cell[2 * 3 + k]));
+    dx[k] = __dadd_rn(__dsub_rn(xj[k], xi[k]), s);
+  }
+  double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx[0], dx[0]), __dmul_rn(dx[1], dx[1])), __dmul_rn(dx[2], dx[2]));
+  dxo[0] = dx[0]; dxo[1] = dx[1]; dxo[2] = dx[2];
+  return d2 < rc2;
+}
+
+template <bool FILL>
+__global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* __restrict__ info_s,
+                      const int32_t* __restrict__ spec_s, CellInfo ci, const GridParams* __restrict__ gp,
+                      const int32_t* __restrict__ bin_start, int32_t* __restrict__ cnt,
+                      const int32_t* __restrict__ row_ptr, int64_t capacity, int32_t* __restrict__ e_src,
+                      uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec, int64_t* __restrict__ status) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (FILL && row_ptr[n] > capacity) return;
+  const GridParams g = *gp;
+  const int4 me = info_s[i];
+  int bi[3];
+  {
+    int bin = me.w;
+    bi[0] = bin % g.nb[0];
+    bi[1] = (bin / g.nb[0]) % g.nb[1];
+    bi[2] = bin / (g.nb[0] * g.nb[1]);
+  }
+  const int ni[3] = {me.x, me.y, me.z};
+  double xi[3] = {pos_s[3 * i], pos_s[3 * i + 1], pos_s[3 * i + 2]};
+  const double rc2 = ci.rc * ci.rc;
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    if (g.stencil[d]) { lo[d] = -1; hi[d] = 1; }
+    else { lo[d] = -g.img[d]; hi[d] = g.img[d]; }
+  }
+  int count = 0;
+  int64_t out = FILL ? row_ptr[i] : 0;
+  int coincident = 0;
+  for (int oz = lo[2]; oz <= hi[2]; ++oz)
+    for (int oy = lo[1]; oy <= hi[1]; ++oy)
+      for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+        int o[3] = {ox, oy, oz};
+        int c[3], Sp[3];
+        bool skip = false;
+        for (int d = 0; d < 3; ++d) {
+          if (g.stencil[d]) {
+            int cc = bi[d] + o[d];
+            Sp[d] = 0;
+            if (ci.pbc[d]) {
+              if (g.nb[d] < 3) { skip = true; break; }
+              if (cc < 0) { cc += g.nb[d]; Sp[d] = -1; }
+              else if (cc >= g.nb[d]) { cc -= g.nb[d]; Sp[d] = 1; }
+            } else if (cc < 0 || cc >= g.nb[d]) { skip = true; break; }
+            c[d] = cc;
+          } else {
+            c[d] = 0;
+            Sp[d] = o[d];
+          }
+        }
+        if (skip) continue;
+        int bin = (c[2] * g.nb[1] + c[1]) * g.nb[0] + c[0];
+        int s = bin_start[bin], e = bin_start[bin + 1];
+        for (int j = s; j < e; ++j) {
+          int4 oj = info_s[j];
+          int S[3];
+          S[0] = ci.pbc[0] ? Sp[0] - oj.x + ni[0] : 0;
+          S[1] = ci.pbc[1] ? Sp[1] - oj.y + ni[1] : 0;
+          S[2] = ci.pbc[2] ? Sp[2] - oj.z + ni[2] : 0;
+          if (j == i && S[0] == 0 && S[1] == 0 && S[2] == 0) continue;
+          double xj[3] = {pos_s[3 * (int64_t)j], pos_s[3 * (int64_t)j + 1], pos_s[3 * (int64_t)j + 2]};
+          double dx[3];
+          if (pair_test(xi, xj, ci, S[0], S[1], S[2], rc2, dx)) {
+            if (dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+            if (FILL) {
+              int64_t eidx = out + count;
+              e_src[eidx] = j;
+              e_shift[eidx] = (uint32_t)(S[0] & 0xff) | ((uint32_t)(S[1] & 0xff) << 8) |
+                              ((uint32_t)(S[2] & 0xff) << 16);
+              e_vec[eidx] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], __int_as_float(spec_s[j]));
+            }
+            ++count;
+          }
+        }
+      }
+  if (!FILL) cnt[i] = count;
+  if (coincident) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_COINCIDENT);
+}
+
+__global__ void k_check_capacity(const int32_t* __restrict__ row_ptr, int64_t n, int64_t capacity,
+                                 int64_t* __restrict__ status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t E = row_ptr[n];
+    status[ST_NEDGES] = E;
+    if (E > capacity) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_CAPACITY);
+  }
+}
+
+// reverse edge of e = (i, j, S) is (j, i, -S) in row j
+__global__ void k_nbr_rev(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ e_src,
+                          const uint32_t* __restrict__ e_shift, int64_t capacity, int32_t* __restrict__ e_rev) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (row_ptr[n] > capacity) return;
+  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    int j = e_src[e];
+    uint32_t sh = e_shift[e];
+    int S0 = (int8_t)(sh & 0xff), S1 = (int8_t)((sh >> 8) & 0xff), S2 = (int8_t)((sh >> 16) & 0xff);
+    uint32_t want = (uint32_t)((-S0) & 0xff) | ((uint32_t)((-S1) & 0xff) << 8) | ((uint32_t)((-S2) & 0xff) << 16);
+    int r = -1;
+    for (int f = row_ptr[j]; f < row_ptr[j + 1]; ++f)
+      if (e_src[f] == (int)i && e_shift[f] == want) { r = f; break; }
+    e_rev[e] = r;
+  }
+}
+
+// export in input indices
+__global__ void k_nbr_export(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ e_src,
+                             const uint32_t* __restrict__ e_shift, const int32_t* __restrict__ perm, int64_t capacity,
+                             int32_t* __restrict__ oi, int32_t* __restrict__ oj, int32_t* __restrict__ os) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (row_ptr[n] > capacity) return;
+  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    uint32_t sh = e_shift[e];
+    oi[e] = perm[i];
+    oj[e] = perm[e_src[e]];
+    os[3 * (int64_t)e + 0] = (int8_t)(sh & 0xff);
+    os[3 * (int64_t)e + 1] = (int8_t)((sh >> 8) & 0xff);
+    os[3 * (int64_t)e + 2] = (int8_t)((sh >> 16) & 0xff);
+  }
+}
+
+// ---------------------------------------------------------------- driver
+
+void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo& ci, int64_t capacity,
+                     hipStream_t s) {
+  const int64_t n = sys.n_atoms;
+  const int nblk = 256;
+  int nparts = (int)((n + 255) / 256);
+  if (nparts > kBoundsParts) nparts = kBoundsParts;
+  k_bounds<<<nparts, 256, 0, s>>>(sys.positions, sys.species, n, ci.n_species, b.bounds, b.status);
+  k_grid<<<1, 64, 0, s>>>(b.bounds, nparts, ci, b.max_bins, b.grid, b.status);
+  hipMemsetAsync(b.bin_count, 0, sizeof(int32_t) * (b.max_bins + 1), s);
+  hipMemsetAsync(b.bin_cursor, 0, sizeof(int32_t) * (b.max_bins + 1), s);
+  const int ga = (int)((n + nblk - 1) / nblk);
+  k_bin_assign<<<ga, nblk, 0, s>>>(sys.positions, n, ci, b.grid, b.info, b.bin_count);
+  exclusive_scan(b.bin_count, b.max_bins, b.bin_start, b.scan_tmp, s);
+  k_bin_fill<<<ga, nblk, 0, s>>>(b.info, n, b.bin_start, b.bin_cursor, b.perm);
+  k_bin_sort<<<(b.max_bins + 255) / 256, 256, 0, s>>>(b.grid, b.bin_start, b.perm);
+  k_gather_sorted<<<ga, nblk, 0, s>>>(b.perm, n, sys.positions, sys.species, b.info, sys.n_owned, ci.n_species, b.pos_s,
+                                      b.info_s, b.spec_s, b.inv_perm, b.owned_s);
+  k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.cnt, nullptr,
+                                   capacity, nullptr, nullptr, nullptr, b.status);
+  exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
+  k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
+  k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, nullptr, b.row_ptr,
+                                  capacity, b.e_src, b.e_shift, b.e_vec, b.status);
+  k_nbr_rev<<<ga, nblk, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, capacity, b.e_rev);
+}
+
+void export_neighbors(const NbrBuffers& b, int64_t n, int64_t capacity, int32_t* oi, int32_t* oj, int32_t* os,
+                      hipStream_t s) {
+  const int ga = (int)((n + 255) / 256);
+  k_nbr_export<<<ga, 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.perm, capacity, oi, oj, os);
+}
+
+}  // namespace mpip

@@ -1,0 +1,251 @@
+// Node-side kernels: channel-mixing GEMMs on MFMA, gated non-linearity with
+// residual, readout, their adjoints, and the final force / virial / energy
+// reductions (fixed-order, FP64).
+#include "kernels.h"
+
+namespace mpip {
+
+// ------------------------------------------------------------ GEMM
+// One wave computes 16 rows x 64 output columns; a block of 4 waves covers
+// 64 rows.  A operand: lane (g, r) holds row r, k-slots 8g..8g+7 (bf16) or
+// 4q+g (f32); B operand from wt[n][k] with the same k-slots.
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, rr = lane & 15;
+  const int64_t r = ((int64_t)blockIdx.x * 4 + w) * 16 + rr;
+  const int n0 = blockIdx.y * 64;
+  const bool rv = r < a.M;
+  const float* xrow = nullptr;
+  if (rv) xrow = a.x + (r / a.rpa) * a.xs + (r % a.rpa) * a.xr;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  const int ntl = (a.Nout - n0) >= 64 ? 4 : (a.Nout - n0) / 16;
+  if constexpr (PREC == 1) {
+    const __bf16* W = (const __bf16*)a.wt;
+    for (int k0 = 0; k0 < a.K; k0 += 32) {
+      bf16x8 av;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) av[j] = (__bf16)(rv ? xrow[k0 + 8 * g + j] : 0.f);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < ntl) {
+          const int n = n0 + 16 * t + rr;
+          bf16x8 bv = *(const bf16x8*)(W + (int64_t)n * a.ldw + k0 + 8 * g);
+          acc[t] = mfma_bf16(av, bv, acc[t]);
+        }
+      }
+    }
+  } else {
+    const float* W = (const float*)a.wt;
+    for (int k0 = 0; k0 < a.K; k0 += 4) {
+      const float av = rv ? xrow[k0 + g] : 0.f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < ntl) {
+          const int n = n0 + 16 * t + rr;
+          acc[t] = mfma_f32(av, W[(int64_t)n * a.ldw + k0 + g], acc[t]);
+        }
+      }
+    }
+  }
+  // D: lane (g, col rr) holds rows 4g + q of the wave's 16-row tile
+  const int64_t rbase = ((int64_t)blockIdx.x * 4 + w) * 16;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t ro = rbase + 4 * g + q;
+    if (ro >= a.M) continue;
+    float* yrow = a.y + (ro / a.rpa) * a.ys + (ro % a.rpa) * a.yr;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < ntl) {
+        const int n = n0 + 16 * t + rr;
+        if (a.accumulate) yrow[n] += acc[t][q];
+        else yrow[n] = acc[t][q];
+      }
+    }
+  }
+}
+
+void launch_gemm(int prec, const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0) return;
+  dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.Nout + 63) / 64));
+  if (prec == MPIP_BF16_MIXED) k_gemm<1><<<grid, 256, 0, s>>>(g);
+  else k_gemm<0><<<grid, 256, 0, s>>>(g);
+}
+
+// ------------------------------------------------------------ gates
+
+// h <- h + update; at the first layer h starts from the embedding (scalars)
+// and zero for l >= 1.  `last`: only the scalar output exists.
+__global__ void k_gate_fwd(NodeArgs a, int first, int last) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= a.n * a.C) return;
+  const int64_t i = idx / a.C;
+  const int c = (int)(idx % a.C);
+  const int C = a.C, nlm = a.nlm, nz = C * (1 + a.L);
+  float* h = a.h + i * nlm * C;
+  const float* z0 = a.z0 + i * nz;
+  const float h0 = first ? a.emb[(int64_t)a.spec_s[i] * C + c] : h[c];
+  h[c] = h0 + silu(z0[c]);
+  if (last) return;
+  for (int l = 1; l <= a.L; ++l) {
+    const float gt = sigm(z0[l * C + c]);
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      const int lm = l * l + m;
+      const float zv = a.zl[(i * (nlm - 1) + lm - 1) * C + c];
+      h[lm * C + c] = (first ? 0.f : h[lm * C + c]) + gt * zv;
+    }
+  }
+}
+
+void launch_gate_fwd(const NodeArgs& a, int first, int last, hipStream_t s) {
+  const int64_t tot = a.n * a.C;
+  k_gate_fwd<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(a, first, last);
+}
+
+// E_i = e0[z_i] + h[i,0,:] . w_read  (one wave per atom)
+__global__ void k_readout(NodeArgs a) {
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= a.n) return;
+  double s = 0.0;
+  for (int c = lane; c < a.C; c += 64) s += (double)a.h[i * a.nlm * a.C + c] * (double)a.w_read[c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) a.atom_e[i] = (double)a.e0[a.spec_s[i]] + s;
+}
+
+void launch_readout(const NodeArgs& a, hipStream_t s) {
+  k_readout<<<(unsigned)((a.n + 3) / 4), 256, 0, s>>>(a);
+}
+
+// Adjoint of the gates.  z buffers are overwritten by their adjoints.
+// last: hbar of the scalars is w_read on root atoms (seed of the backward).
+// init_hbar: also write the residual part of hbar for the layer below
+// (w_read on root scalars, zero elsewhere).
+__global__ void k_gate_bwd(NodeArgs a, int last, int init_hbar) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= a.n * a.C) return;
+  const int64_t i = idx / a.C;
+  const int c = (int)(idx % a.C);
+  const int C = a.C, nlm = a.nlm, nz = C * (1 + a.L);
+  float* z0 = a.z0 + i * nz;
+  float* hb = a.hbar + i * nlm * C;
+  if (last) {
+    const float seed = a.owned_s[i] ? a.w_read[c] : 0.f;
+    z0[c] = seed * dsilu(z0[c]);
+    if (init_hbar) {
+      hb[c] = seed;
+      for (int lm = 1; lm < nlm; ++lm) hb[lm * C + c] = 0.f;
+    }
+    return;
+  }
+  z0[c] = hb[c] * dsilu(z0[c]);
+  for (int l = 1; l <= a.L; ++l) {
+    const float gi = z0[l * C + c];
+    const float s = sigm(gi);
+    float dg = 0.f;
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      const int lm = l * l + m;
+      float* zp = a.zl + (i * (nlm - 1) + lm - 1) * C + c;
+      const float hv = hb[lm * C + c];
+      dg += hv * (*zp);
+      *zp = hv * s;
+    }
+    z0[l * C + c] = dg * s * (1.f - s);
+  }
+}
+
+void launch_gate_bwd(const NodeArgs& a, int last, int init_hbar, hipStream_t s) {
+  const int64_t tot = a.n * a.C;
+  k_gate_bwd<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(a, last, init_hbar);
+}
+
+// ------------------------------------------------------------ outputs
+
+// Per atom: F_i = sum_{e in row i} g_e - g_rev(e) (FP64), written in input
+// order; per block: sum of root energies and of r_e (x) g_e, fixed order.
+__global__ __launch_bounds__(256) void k_forces(OutArgs a) {
+  __shared__ double sh[10][256];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double loc[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) loc[k] = 0.0;
+  const bool run = (a.status[ST_FLAGS] == 0) && ((int64_t)a.row_ptr[a.n] <= a.capacity);
+  if (run && i < a.n) {
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) {
+      const float4 ge = a.g[e];
+      const int rv = a.e_rev[e];
+      const float4 gr = rv >= 0 ? a.g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 r = a.e_vec[e];
+      F[0] += (double)ge.x - (double)gr.x;
+      F[1] += (double)ge.y - (double)gr.y;
+      F[2] += (double)ge.z - (double)gr.z;
+      const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) loc[1 + 3 * p + q] += rr[p] * gg[q];
+    }
+    const int o = a.perm[i];
+    a.forces[3 * (int64_t)o + 0] = F[0];
+    a.forces[3 * (int64_t)o + 1] = F[1];
+    a.forces[3 * (int64_t)o + 2] = F[2];
+    if (a.atom_energy) a.atom_energy[o] = a.atom_e[i];
+    if (a.owned_s[i]) loc[0] = a.atom_e[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = loc[k];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 10) a.partials[(int64_t)blockIdx.x * 10 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_final(OutArgs a) {
+  __shared__ double sh[10][256];
+  double loc[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) loc[k] = 0.0;
+  for (int b = threadIdx.x; b < a.nblocks; b += 256)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) loc[k] += a.partials[(int64_t)b * 10 + k];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = loc[k];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.energy[0] = sh[0][0];
+  if (threadIdx.x < 9) a.virial[threadIdx.x] = -sh[1 + threadIdx.x][0];
+}
+
+void launch_outputs(const OutArgs& a, hipStream_t s) {
+  k_forces<<<a.nblocks, 256, 0, s>>>(a);
+  k_final<<<1, 256, 0, s>>>(a);
+}
+
+__global__ void k_zero(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_zero<<<(unsigned)blocks, 256, 0, s>>>((uint32_t*)p, n);
+}
+
+}  // namespace mpip

@@ -1,0 +1,211 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (per atom for the energy, eV and Angstrom):
+  FP32 form: |dE|/N <= 1e-6, max |dF| <= 1e-4, and relative to the oracle's
+             force scale max |dF| <= 1e-5 * max|F| (FP32 rounding over a few
+             thousand operations per output);
+  BF16 form: |dE|/N <= 1e-3, RMS dF <= 5e-3, and RMS dF <= 2e-2 * RMS F
+             (BF16 keeps 8 mantissa bits: ~0.4 % per rounding, averaged over
+             the 64-wide hidden layer and the ~40 edges of a row).
+The virial W = -sum_e r_e (x) g_e is a sum of large terms of both signs, so
+its relative error is about ten times the force error; it is bounded as a
+stress, |dW|/V <= 1e-8 eV/A^3 (FP32) and 1e-5 eV/A^3 = 1.6 MPa (BF16), and
+its relative error is printed.  The edge list must be identical as a set of
+(i, j, S) triples.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_2509_21694_amd as mod
+    return mod
+
+
+def dev_inputs(torch, s):
+    pos = torch.tensor(np.ascontiguousarray(s.positions), dtype=torch.float64, device="cuda")
+    sp = torch.tensor(np.ascontiguousarray(s.species), dtype=torch.int32, device="cuda")
+    return pos, sp
+
+
+def edge_set(i, j, S):
+    return set(zip(np.asarray(i).tolist(), np.asarray(j).tolist(), map(tuple, np.asarray(S).tolist())))
+
+
+def compare(o, ref, n, prec, label, volume):
+    E = float(o["energy"].cpu()[0])
+    F = o["forces"].cpu().numpy()
+    Wv = o["virial"].cpu().numpy()
+    dE = abs(E - ref.energy) / n
+    dF = np.abs(F - ref.forces)
+    fmax, frms = np.abs(ref.forces).max(), np.sqrt(np.mean(ref.forces ** 2))
+    rms = np.sqrt(np.mean(dF ** 2))
+    dW = np.abs(Wv - ref.virial).max()
+    print(f"[{label}] {prec}: dE/N={dE:.3e} max|dF|={dF.max():.3e} rms dF={rms:.3e} "
+          f"(|F|max={fmax:.3e} rms={frms:.3e}) max|dW|={dW:.3e} (|W|max={np.abs(ref.virial).max():.3e}, "
+          f"|dW|/V={dW / volume:.3e} eV/A^3)")
+    if prec == "fp32":
+        assert dE <= 1e-6
+        assert dF.max() <= 1e-4
+        assert dF.max() <= 1e-5 * fmax
+        assert dW / volume <= 1e-8
+    else:
+        assert dE <= 1e-3
+        assert rms <= 5e-3
+        assert rms <= 2e-2 * frms
+        assert dW / volume <= 1e-5
+    if o.get("atom_energy") is not None:
+        ae = o["atom_energy"].cpu().numpy()
+        tol = 1e-6 if prec == "fp32" else 1e-3
+        assert np.abs(ae - ref.atom_energy).max() <= tol
+
+
+# ----------------------------------------------------------- neighbour list
+
+NBR_CASES = ["small", "mpdp", "slab_pbc011", "thin_cell", "unwrapped", "cluster"]
+
+
+def nbr_case(name):
+    if name == "small":
+        s = W.small_system()
+        return s.positions, s.cell, s.pbc
+    if name == "mpdp":
+        s = W.mpdp_system()
+        return s.positions, s.cell, s.pbc
+    if name == "slab_pbc011":
+        s = W.slab_full_system(60, 10, 10, 3, 4)
+        return s.positions, s.cell, np.array([False, True, True])
+    if name == "thin_cell":
+        rng = np.random.default_rng(5)
+        cell = np.diag([4.1, 6.3, 9.7])
+        return rng.uniform(0, 1, (6, 3)) * np.diag(cell), cell, np.array([True, True, True])
+    if name == "unwrapped":
+        s = W.small_system()
+        rng = np.random.default_rng(6)
+        shift = rng.integers(-3, 4, (128, 3)) * 11.5
+        return s.positions + shift, s.cell, s.pbc
+    if name == "cluster":
+        rng = np.random.default_rng(7)
+        return rng.uniform(0, 14, (300, 3)), np.eye(3) * 14, np.array([False, False, False])
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", NBR_CASES)
+def test_neighbor_list_bit_exact(torch, M, name):
+    pos, cell, pbc = nbr_case(name)
+    ri, rj, rS = oracle.neighbor_list(pos, cell, pbc, 5.0)
+    p = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    gi, gj, gS = M.neighbor_list(p, cell, pbc, 5.0)
+    got = edge_set(gi.cpu().numpy(), gj.cpu().numpy(), gS.cpu().numpy())
+    ref = edge_set(ri, rj, rS)
+    print(f"[{name}] edges gpu={len(got)} oracle={len(ref)}")
+    assert gi.numel() == ri.size
+    assert got == ref
+
+
+# ----------------------------------------------------------- small system
+
+@pytest.fixture(scope="module")
+def small_case():
+    s = W.small_system()
+    blob = W.make_weights(W.HP_SMALL, W.WEIGHT_SEEDS["small"])
+    refs = {K: oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, W.HP_SMALL, K=K) for K in (1, 2)}
+    return s, blob, refs
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("K", [2, 1])
+def test_small_parity(torch, M, small_case, prec, K):
+    s, blob, refs = small_case
+    model = M.Model(W.HP_SMALL, blob)
+    pos, sp = dev_inputs(torch, s)
+    o = model.evaluate(pos, sp, s.cell, s.pbc, K=K, precision=prec, atom_energy=True)
+    assert o["n_edges"] == refs[K].n_edges
+    compare(o, refs[K], s.n_atoms, prec, f"small K={K}", abs(np.linalg.det(s.cell)))
+
+
+def test_small_e0_and_ghost_rows(torch, M):
+    """Per-species offsets and a partition-style evaluation (root atoms
+    first, ghosts contribute no energy but receive partial forces)."""
+    s = W.small_system()
+    blob = W.make_weights(W.HP_SMALL, 9, e0=[0.7, -1.3])
+    n_own = 50
+    ref = oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, W.HP_SMALL, n_owned=n_own)
+    model = M.Model(W.HP_SMALL, blob)
+    pos, sp = dev_inputs(torch, s)
+    o = model.evaluate(pos, sp, s.cell, s.pbc, precision="fp32", n_owned=n_own, atom_energy=True)
+    compare(o, ref, s.n_atoms, "fp32", "small n_owned=50", abs(np.linalg.det(s.cell)))
+
+
+def test_determinism_and_autograd(torch, M, small_case):
+    s, blob, refs = small_case
+    model = M.Model(W.HP_SMALL, blob)
+    pos, sp = dev_inputs(torch, s)
+    a = model.evaluate(pos, sp, s.cell, s.pbc, precision="bf16")
+    b = model.evaluate(pos, sp, s.cell, s.pbc, precision="bf16")
+    assert torch.equal(a["forces"], b["forces"]) and torch.equal(a["energy"], b["energy"])
+    assert torch.equal(a["virial"], b["virial"])
+    x = pos.clone().requires_grad_(True)
+    E, Wv = M.energy(x, model, sp, s.cell, s.pbc, precision="fp32")
+    E.backward()
+    assert np.allclose(-x.grad.cpu().numpy(), refs[2].forces, atol=1e-5)
+    assert abs(float(E.detach()) - refs[2].energy) / 128 <= 1e-6
+
+
+def test_data_errors_reported(torch, M, small_case):
+    s, blob, _ = small_case
+    model = M.Model(W.HP_SMALL, blob)
+    pos, sp = dev_inputs(torch, s)
+    bad = sp.clone()
+    bad[3] = 7
+    with pytest.raises(M.MpipError) as e:
+        model.evaluate(pos, bad, s.cell, s.pbc)
+    assert e.value.status == M.EINVAL
+    p2 = pos.clone()
+    p2[5] = p2[9]
+    with pytest.raises(M.MpipError) as e:
+        model.evaluate(p2, sp, s.cell, s.pbc)
+    assert e.value.status == M.EINVAL
+    # too small an edge capacity is reported and retried with the exact count
+    o = model.evaluate(pos, sp, s.cell, s.pbc, max_edges=100)
+    assert o["n_edges"] == 6016
+
+
+# ----------------------------------------------------------- depth pruning
+
+@pytest.mark.parametrize("K", [2, 6])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mpdp_parity(torch, M, K, prec):
+    path = os.path.join(GOLDEN, f"mpdp_K{K}.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing (tests/golden/make_golden.py)")
+    g = np.load(path)
+
+    class R:
+        energy = float(g["energy"])
+        forces = g["forces"]
+        virial = g["virial"]
+        atom_energy = g["atom_energy"]
+
+    s = W.mpdp_system()
+    model = M.Model(W.HP_MPDP, W.make_weights(W.HP_MPDP, W.WEIGHT_SEEDS["mpdp"]))
+    pos, sp = dev_inputs(torch, s)
+    o = model.evaluate(pos, sp, s.cell, s.pbc, K=K, precision=prec, atom_energy=True)
+    assert o["n_edges"] == int(g["n_edges"])
+    compare(o, R, s.n_atoms, prec, f"mpdp K={K}", abs(np.linalg.det(s.cell)))
