@@ -127,6 +127,23 @@ mpip_status mpip_evaluate(mpip_model* model, const mpip_system* sys, mpip_precis
                           int32_t K, void* stream, void* workspace, size_t workspace_bytes,
                           int64_t max_edges, const mpip_outputs* out);
 
+/* Batched evaluation of B independent structures (atoms concatenated):
+ * structure b owns atoms atom_ptr[b] .. atom_ptr[b+1]-1 (host int64 [B+1],
+ * atom_ptr[0] = 0), with cell cells[9b..9b+8] and periodicity pbc[3b..3b+2]
+ * (host; orthorhombic; periodic directions thinner than the cutoff are
+ * searched over all images).  positions device [N,3], species device [N].
+ * Outputs (device): energy [B], forces [N,3] (input order), virial [B,9].
+ * Every atom is a root atom.  One pass of each kernel covers all structures
+ * (the neighbour list is block diagonal).  Asynchronous; never allocates;
+ * data-dependent errors via mpip_workspace_status as for mpip_evaluate. */
+mpip_status mpip_batch_workspace_size(const mpip_model* model, int64_t n_atoms_total, int32_t B,
+                                      mpip_precision prec, int32_t K, int64_t max_edges, size_t* bytes);
+mpip_status mpip_evaluate_batch(mpip_model* model, int32_t B, const int64_t* atom_ptr,
+                                const double* positions, const int32_t* species, const double* cells,
+                                const uint8_t* pbc, mpip_precision prec, int32_t K, void* stream,
+                                void* workspace, size_t workspace_bytes, int64_t max_edges,
+                                double* energy, double* forces, double* virial);
+
 /* Synchronise `stream` and read the status word of `workspace` written by
  * the last mpip_evaluate / mpip_neighbor_list on it.  *n_edges receives the
  * number of directed edges found (also when it exceeded the capacity). */
@@ -146,6 +163,33 @@ mpip_status mpip_neighbor_list(const mpip_system* sys, double r_cut, void* strea
                                void* workspace, size_t workspace_bytes, int64_t capacity,
                                int32_t* edge_i, int32_t* edge_j, int32_t* edge_shift,
                                int64_t* n_edges);
+
+/* One partition of a structure (Methods "Graph Partitioning", stage 1
+ * spatial grid and the halo that keeps every root atom's K-hop
+ * neighbourhood).  Atoms are binned along lattice axis `axis` of the
+ * orthorhombic `cell` (host [9]) by b = min(floor((x/L) P), P-1) with x the
+ * coordinate wrapped into [0, L); slab `part` holds the root atoms.  Every
+ * periodic image of every atom whose coordinate lies within `halo` of the
+ * slab (and outside it) is added as a halo atom at its unwrapped position.
+ * Output (device, capacity rows): root atoms first by increasing index (at
+ * their wrapped coordinate), then halo images by increasing image shift and
+ * index; out_index = the input atom each row copies.  The share is
+ * evaluated with pbc[axis] = 0 and n_owned = *n_owned.  Synchronous.  If the
+ * share has more rows than `capacity`, ECAPACITY with *n_local set. */
+size_t mpip_slab_workspace_size(int64_t n_atoms, double axis_length, double halo);
+mpip_status mpip_slab_share(const double* positions, const int32_t* species, int64_t n_atoms,
+                            const double* cell, int32_t axis, int32_t n_parts, int32_t part,
+                            double halo, void* stream, void* workspace, size_t workspace_bytes,
+                            int64_t capacity, double* out_positions, int32_t* out_species,
+                            int32_t* out_index, int64_t* n_local, int64_t* n_owned);
+
+/* Output integration (Methods "Global Output Integration"): dst[index[k]]
+ * += src[k] for rows of 3 doubles (device pointers), e.g. a partition's
+ * force rows (root and halo) into the full structure's forces.
+ * Asynchronous on `stream`; rows with an index outside [0, n_dst) are
+ * skipped; repeated indices are summed atomically. */
+mpip_status mpip_accumulate_rows(const double* src, const int32_t* index, int64_t n_rows, int64_t n_dst,
+                                 double* dst, void* stream);
 
 /* The library's coupling tensor for (l1,l2,l3), derived from Wigner 3j
  * symbols and the complex-to-real change of basis, Frobenius-normalised.

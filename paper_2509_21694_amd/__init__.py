@@ -88,6 +88,18 @@ def _load():
     lib.mpip_timing_enable.restype = I32
     lib.mpip_timing_read.argtypes = [V, P(TimingC)]
     lib.mpip_timing_read.restype = I32
+    lib.mpip_slab_workspace_size.argtypes = [I64, ctypes.c_double, ctypes.c_double]
+    lib.mpip_slab_workspace_size.restype = SZ
+    lib.mpip_slab_share.argtypes = [V, V, I64, P(ctypes.c_double), I32, I32, I32, ctypes.c_double, V, V, SZ, I64,
+                                    V, V, V, P(I64), P(I64)]
+    lib.mpip_slab_share.restype = I32
+    lib.mpip_accumulate_rows.argtypes = [V, V, I64, I64, V, V]
+    lib.mpip_accumulate_rows.restype = I32
+    lib.mpip_batch_workspace_size.argtypes = [V, I64, I32, I32, I32, I64, P(SZ)]
+    lib.mpip_batch_workspace_size.restype = I32
+    lib.mpip_evaluate_batch.argtypes = [V, I32, P(I64), V, V, P(ctypes.c_double), P(ctypes.c_uint8), I32, I32, V, V,
+                                        SZ, I64, V, V, V]
+    lib.mpip_evaluate_batch.restype = I32
     lib.mpip_last_error.argtypes = []
     lib.mpip_last_error.restype = ctypes.c_char_p
     return lib
@@ -98,7 +110,8 @@ lib = _load()
 EXPORTED = ["mpip_weights_count", "mpip_model_create", "mpip_model_destroy", "mpip_workspace_size",
             "mpip_evaluate", "mpip_workspace_status", "mpip_neighbor_workspace_size",
             "mpip_neighbor_list", "mpip_coupling_tensor", "mpip_timing_enable", "mpip_timing_read",
-            "mpip_last_error"]
+            "mpip_slab_workspace_size", "mpip_slab_share", "mpip_accumulate_rows",
+            "mpip_batch_workspace_size", "mpip_evaluate_batch", "mpip_last_error"]
 
 
 def _check(st: int):
@@ -231,6 +244,28 @@ class Model:
         raise MpipError(ECAPACITY, "edge capacity")
 
 
+class Batch:
+    """Device inputs of a batch of independent structures (atoms concatenated)."""
+
+    def __init__(self, structures, device):
+        import torch
+        self.B = len(structures)
+        counts = [int(np.asarray(s.positions).shape[0]) for s in structures]
+        self.atom_ptr = np.ascontiguousarray(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
+        self.n_atoms = int(self.atom_ptr[-1])
+        self.cells = np.ascontiguousarray(np.stack([np.asarray(s.cell, dtype=np.float64).reshape(9)
+                                                    for s in structures]))
+        self.pbc = np.ascontiguousarray(np.stack([np.asarray(s.pbc).astype(np.uint8).reshape(3)
+                                                  for s in structures]))
+        self.positions = torch.tensor(np.concatenate([s.positions for s in structures]), dtype=torch.float64,
+                                      device=device)
+        self.species = torch.tensor(np.concatenate([s.species for s in structures]).astype(np.int32),
+                                    dtype=torch.int32, device=device)
+        vol = np.abs(np.prod(self.cells[:, [0, 4, 8]], axis=1))
+        dens = np.array(counts) / np.maximum(vol, 1e-30)
+        self.edge_estimate = int(np.sum(np.array(counts) * np.maximum(48.0, 1.6 * dens * 4.0 / 3.0 * math.pi * 125.0)))
+
+
 def read_timing(model: "Model") -> dict:
     """Per-phase totals since timing was enabled: {name: (ms, calls)}."""
     t = TimingC()
@@ -244,6 +279,45 @@ def workspace_status(model: "Model", stream=None) -> int:
     sp = _stream_ptr(model.torch, model.device, stream)
     return int(lib.mpip_workspace_status(ctypes.c_void_p(model._ws.data_ptr()), ctypes.c_void_p(sp),
                                          ctypes.byref(ne)))
+
+
+def evaluate_batch(model: "Model", batch: Batch, K=None, precision="fp32", max_edges=None, stream=None,
+                   check: bool = True):
+    """Energies [B], forces [N,3], virials [B,3,3] of a Batch (cuda tensors)."""
+    torch = model.torch
+    K = model.hp.n_layers if K is None else int(K)
+    prec = PRECISIONS[precision]
+    if max_edges is None:
+        max_edges = batch.edge_estimate
+    for attempt in range(2):
+        nb = ctypes.c_size_t()
+        _check(lib.mpip_batch_workspace_size(model._h, batch.n_atoms, batch.B, prec, K, max_edges, ctypes.byref(nb)))
+        if model._ws is None or model._ws.numel() < nb.value:
+            model._ws = None
+            model._ws = torch.empty(nb.value, dtype=torch.uint8, device=model.device)
+        ws = model._ws
+        o = {"energy": torch.empty(batch.B, dtype=torch.float64, device=model.device),
+             "forces": torch.empty((batch.n_atoms, 3), dtype=torch.float64, device=model.device),
+             "virial": torch.empty((batch.B, 3, 3), dtype=torch.float64, device=model.device)}
+        sp = _stream_ptr(torch, model.device, stream)
+        _check(lib.mpip_evaluate_batch(
+            model._h, batch.B, batch.atom_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            ctypes.c_void_p(batch.positions.data_ptr()), ctypes.c_void_p(batch.species.data_ptr()),
+            batch.cells.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            batch.pbc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), prec, K, ctypes.c_void_p(sp),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), max_edges, ctypes.c_void_p(o["energy"].data_ptr()),
+            ctypes.c_void_p(o["forces"].data_ptr()), ctypes.c_void_p(o["virial"].data_ptr())))
+        if not check:
+            return o
+        ne = ctypes.c_int64()
+        st = lib.mpip_workspace_status(ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(sp), ctypes.byref(ne))
+        if st == ECAPACITY and attempt == 0:
+            max_edges = int(ne.value * 1.05) + 1024
+            continue
+        _check(st)
+        o["n_edges"] = int(ne.value)
+        return o
+    raise MpipError(ECAPACITY, "edge capacity")
 
 
 def neighbor_list(positions, cell, pbc, r_cut: float, capacity: Optional[int] = None, stream=None):
@@ -273,6 +347,48 @@ def neighbor_list(positions, cell, pbc, r_cut: float, capacity: Optional[int] = 
         n = int(ne.value)
         return ei[:n], ej[:n], es[:n]
     raise MpipError(ECAPACITY, "edge capacity")
+
+
+def slab_share(positions, species, cell, n_parts: int, part: int, halo: float, axis: int = 0,
+               capacity: Optional[int] = None, stream=None):
+    """One slab partition with its halo, built on the GPU.  Returns
+    (positions [n,3] f64, species [n] i32, input index [n] i32, n_owned) as
+    cuda tensors; root atoms first.  Evaluate it with pbc[axis] = False."""
+    import torch
+    dev = positions.device
+    N = int(positions.shape[0])
+    c = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
+    Lax = float(c[4 * axis])
+    if capacity is None:
+        capacity = int(N / n_parts + 2 * N * halo / Lax) + 1024
+    for attempt in range(2):
+        nbytes = int(lib.mpip_slab_workspace_size(N, Lax, float(halo)))
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        op = torch.empty((capacity, 3), dtype=torch.float64, device=dev)
+        osp = torch.empty(capacity, dtype=torch.int32, device=dev)
+        oix = torch.empty(capacity, dtype=torch.int32, device=dev)
+        nl, no = ctypes.c_int64(), ctypes.c_int64()
+        st = lib.mpip_slab_share(ctypes.c_void_p(positions.data_ptr()), ctypes.c_void_p(species.data_ptr()), N,
+                                 c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), axis, n_parts, part,
+                                 float(halo), ctypes.c_void_p(_stream_ptr(torch, dev, stream)),
+                                 ctypes.c_void_p(ws.data_ptr()), nbytes, capacity, ctypes.c_void_p(op.data_ptr()),
+                                 ctypes.c_void_p(osp.data_ptr()), ctypes.c_void_p(oix.data_ptr()),
+                                 ctypes.byref(nl), ctypes.byref(no))
+        if st == ECAPACITY and attempt == 0 and nl.value > capacity:
+            capacity = int(nl.value)
+            continue
+        _check(st)
+        n = int(nl.value)
+        return op[:n], osp[:n], oix[:n], int(no.value)
+    raise MpipError(ECAPACITY, "share capacity")
+
+
+def accumulate_rows(src, index, dst, stream=None):
+    """dst[index[k]] += src[k] (rows of 3 doubles) on the GPU."""
+    import torch
+    _check(lib.mpip_accumulate_rows(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(index.data_ptr()),
+                                    int(src.shape[0]), int(dst.shape[0]), ctypes.c_void_p(dst.data_ptr()),
+                                    ctypes.c_void_p(_stream_ptr(torch, dst.device, stream))))
 
 
 def _autograd():

@@ -1,0 +1,237 @@
+// Device helpers shared by the edge kernels: compile-time path lists, edge
+// geometry (radial basis, envelope, real harmonics), MFMA operand helpers
+// and the radial-MLP forward in features x edges orientation.
+#pragma once
+#include <utility>
+
+#include "kernels.h"
+
+namespace mpip {
+
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N-1>), fully unrolled
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ------------------------------------------------------------ path lists
+
+struct P3 { int l1, l2, l3; };
+
+constexpr bool natural3(int a, int b, int c) {
+  return ((a + b + c) % 2 == 0) && c >= (a > b ? a - b : b - a) && c <= a + b;
+}
+
+template <int L, int KIND>
+struct PathList {
+  static constexpr int l1max() { return (KIND == KIND_ONLY || KIND == KIND_FIRST) ? 0 : L; }
+  static constexpr bool keep(int a, int b, int c) {
+    if (!natural3(a, b, c)) return false;
+    if (KIND == KIND_ONLY || KIND == KIND_LAST) return c == 0;
+    return true;
+  }
+  static constexpr int count() {
+    int n = 0;
+    for (int a = 0; a <= l1max(); ++a)
+      for (int b = 0; b <= L; ++b)
+        for (int c = 0; c <= L; ++c)
+          if (keep(a, b, c)) ++n;
+    return n;
+  }
+  static constexpr P3 get(int i) {
+    int n = 0;
+    for (int a = 0; a <= l1max(); ++a)
+      for (int b = 0; b <= L; ++b)
+        for (int c = 0; c <= L; ++c)
+          if (keep(a, b, c)) {
+            if (n == i) return P3{a, b, c};
+            ++n;
+          }
+    return P3{0, 0, 0};
+  }
+  static constexpr int yc_off(int i) {
+    int o = 0;
+    for (int k = 0; k < i; ++k) o += (2 * get(k).l1 + 1) * (2 * get(k).l3 + 1);
+    return o;
+  }
+  static constexpr int cg_off(int i) {
+    int o = 0;
+    for (int k = 0; k < i; ++k) o += (2 * get(k).l1 + 1) * (2 * get(k).l2 + 1) * (2 * get(k).l3 + 1);
+    return o;
+  }
+  static constexpr int nyc() { return yc_off(count()); }
+  static constexpr int nin() { return (KIND == KIND_ONLY || KIND == KIND_FIRST) ? 1 : (L + 1) * (L + 1); }
+  static constexpr int nout() { return (KIND == KIND_ONLY || KIND == KIND_LAST) ? 1 : (L + 1) * (L + 1); }
+};
+
+// ------------------------------------------------------------ geometry
+
+struct Geo {
+  float u[3];
+  float d;
+  float Y[kMaxNlm];
+  float basis[kNB];
+  float dbasis[kNB];
+};
+
+__device__ __forceinline__ void edge_geometry(float4 v, bool valid, float rc, int p, Geo& g) {
+  if (!valid) {
+    g.u[0] = g.u[1] = g.u[2] = 0.f;
+    g.d = 1.f;
+#pragma unroll
+    for (int k = 0; k < kMaxNlm; ++k) g.Y[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) g.basis[k] = g.dbasis[k] = 0.f;
+    return;
+  }
+  const float d = sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+  const float inv = 1.0f / d;
+  const float x = v.x * inv, y = v.y * inv, z = v.z * inv;
+  g.u[0] = x; g.u[1] = y; g.u[2] = z; g.d = d;
+  const float s3 = 1.7320508075688772f, s5 = 2.23606797749979f, s15 = 3.872983346207417f;
+  g.Y[0] = 1.f;
+  g.Y[1] = s3 * y; g.Y[2] = s3 * z; g.Y[3] = s3 * x;
+  g.Y[4] = s15 * x * y; g.Y[5] = s15 * y * z; g.Y[6] = 0.5f * s5 * (3.f * z * z - 1.f);
+  g.Y[7] = s15 * x * z; g.Y[8] = 0.5f * s15 * (x * x - y * y);
+  // polynomial envelope of order p
+  const float xr = d / rc;
+  float env = 0.f, denv = 0.f;
+  if (xr < 1.f) {
+    const float a = 0.5f * (p + 1) * (p + 2), b = (float)(p * (p + 2)), c = 0.5f * p * (p + 1);
+    float xp1 = 1.f;  // x^(p-1)
+    for (int k = 0; k < p - 1; ++k) xp1 *= xr;
+    const float xp = xp1 * xr, xq = xp * xr, xs = xq * xr;
+    env = 1.f - a * xp + b * xq - c * xs;
+    denv = (-a * p * xp1 + b * (p + 1) * xp - c * (p + 2) * xq) / rc;
+  }
+  // Bessel basis via the Chebyshev recurrence for sin(n t), cos(n t)
+  const float pref = sqrtf(2.0f / rc);
+  const float th = 3.14159265358979f * d / rc;
+  float s1, c1;
+  sincosf(th, &s1, &c1);
+  float sp = 0.f, cp = 1.f, sn = s1, cn = c1;
+#pragma unroll
+  for (int n = 1; n <= kNB; ++n) {
+    const float kn = n * 3.14159265358979f / rc;
+    const float B = pref * sn * inv;
+    const float dB = pref * (kn * d * cn - sn) * inv * inv;
+    g.basis[n - 1] = env * B;
+    g.dbasis[n - 1] = denv * B + env * dB;
+    const float sx = 2.f * c1 * sn - sp, cx = 2.f * c1 * cn - cp;
+    sp = sn; cp = cn; sn = sx; cn = cx;
+  }
+}
+
+// gu = (dP/du)^T Ybar for the polynomials above
+__device__ __forceinline__ void sh_grad_contract(const float* Yb, const float* u, float* gu) {
+  const float s3 = 1.7320508075688772f, s5 = 2.23606797749979f, s15 = 3.872983346207417f;
+  const float x = u[0], y = u[1], z = u[2];
+  gu[0] = s3 * Yb[3] + s15 * (y * Yb[4] + z * Yb[7] + x * Yb[8]);
+  gu[1] = s3 * Yb[1] + s15 * (x * Yb[4] + z * Yb[5] - y * Yb[8]);
+  gu[2] = s3 * Yb[2] + s15 * (y * Yb[5] + x * Yb[7]) + 3.f * s5 * z * Yb[6];
+}
+
+// ------------------------------------------------------------ MFMA helpers
+
+template <int PREC> struct Op;
+
+template <> struct Op<1> {  // BF16 operands, K = 32 per instruction
+  typedef bf16x8 T;
+  static constexpr int KC64 = 2;   // k-chunks for K = 64
+  __device__ static f32x4 mma(T a, T b, f32x4 c) { return mfma_bf16(a, b, c); }
+  // operand of k-chunk kc from four D tiles (hidden 16*t + 4*g + r)
+  __device__ static T from_tiles(const f32x4* t, int kc) {
+    T v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (__bf16)t[2 * kc + j / 4][j % 4];
+    return v;
+  }
+  __device__ static T load(const void* base, int idx) { return ((const T*)base)[idx]; }
+  // operand of channels 32*kc + 8*g + j from an LDS row
+  __device__ static T from_row(const float* row, int kc, int g) {
+    T v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (__bf16)row[32 * kc + 8 * g + j];
+    return v;
+  }
+  static constexpr int kch(int K) { return K / 32; }
+};
+
+template <> struct Op<0> {  // FP32 operands, K = 4 per instruction
+  typedef float T;
+  static constexpr int KC64 = 16;
+  __device__ static f32x4 mma(T a, T b, f32x4 c) { return mfma_f32(a, b, c); }
+  __device__ static T from_tiles(const f32x4* t, int q) { return t[q / 4][q % 4]; }
+  __device__ static T load(const void* base, int idx) { return ((const T*)base)[idx]; }
+  __device__ static T from_row(const float* row, int q, int g) { return row[4 * q + g]; }
+  static constexpr int kch(int K) { return K / 4; }
+};
+
+// basis operand (K = n_basis = 8 padded): bf16: group 0 holds basis[j];
+// f32: chunk q, group g holds basis[4q + g]
+__device__ __forceinline__ bf16x8 basis_op_bf16(const float* b, int g) {
+  bf16x8 v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = (__bf16)(g == 0 ? b[j] : 0.f);
+  return v;
+}
+
+template <int PREC>
+__device__ __forceinline__ void mlp_forward(const Geo& geo, int lane, const void* w1a, const void* w2a,
+                                            f32x4* p1, f32x4* p2) {
+  typedef Op<PREC> O;
+  const int g = lane >> 4;
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = z;
+    if constexpr (PREC == 1) {
+      acc = O::mma(O::load(w1a, mt * 64 + lane), basis_op_bf16(geo.basis, g), acc);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc = O::mma(O::load(w1a, (mt * 2 + q) * 64 + lane), geo.basis[4 * q + g], acc);
+    }
+    p1[mt] = acc;
+  }
+  f32x4 a1[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a1[mt][r] = silu(p1[mt][r]);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = z;
+#pragma unroll
+    for (int kc = 0; kc < O::KC64; ++kc)
+      acc = O::mma(O::load(w2a, (mt * O::KC64 + kc) * 64 + lane), O::from_tiles(a1, kc), acc);
+    p2[mt] = acc;
+  }
+}
+
+// R_p for one path: D[nt] tiles (edges 4g + r, channels 16 nt + lane%16) -> LDS
+template <int PREC, int C>
+__device__ __forceinline__ void radial_out(const f32x4* a2, int lane, const void* w3f, int p, float* sR,
+                                           int RS) {
+  typedef Op<PREC> O;
+  const int g = lane >> 4, n = lane & 15;
+  typename O::T aop[O::KC64];
+#pragma unroll
+  for (int kc = 0; kc < O::KC64; ++kc) aop[kc] = O::from_tiles(a2, kc);
+#pragma unroll
+  for (int nt = 0; nt < C / 16; ++nt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < O::KC64; ++kc)
+      acc = O::mma(aop[kc], O::load(w3f, ((p * (C / 16) + nt) * O::KC64 + kc) * 64 + lane), acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sR[(4 * g + r) * RS + 16 * nt + n] = acc[r];
+  }
+}
+
+__device__ __forceinline__ int64_t edges_total(const EdgeArgs& a) { return (int64_t)a.row_ptr[a.n]; }
+
+}  // namespace mpip

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -107,6 +108,7 @@ struct PhaseTimer {
 struct mpip_model {
   mpip_hparams hp;
   int device;
+  bool force_generic = false;  // MPIP_FORCE_GENERIC=1 at creation: generic edge kernels only
   PhaseTimer timer;
   DevArena arena;
   // per precision (0 = f32, 1 = bf16), per layer
@@ -183,6 +185,10 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
   HIPCHK(hipSetDevice(device));
   mpip_model* m = new mpip_model();
   m->hp = *hp;
+  {
+    const char* fg = std::getenv("MPIP_FORCE_GENERIC");
+    m->force_generic = fg && fg[0] == '1';
+  }
   m->device = device;
   const int C = hp->channels, H = hp->radial_hidden, nb = hp->n_basis, L = hp->l_max, S = hp->n_species;
   const int T = hp->n_layers;
@@ -339,6 +345,59 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
         if ((st = node(x.down[l], C, C, true, &d.down_t[l])) != MPIP_OK) goto done;
         if ((st = node(x.down[l], C, C, false, &d.down[l])) != MPIP_OK) goto done;
       }
+      // ---- operand layouts of the specialised first / last layer kernels
+      // layer-2 B operand, edges x features: col h2 = 16 nt + lane%16, k-slot -> h1
+      if ((st = pack(4, KC64, [&](int nt, int k, int lane, int j) {
+             const int h2 = 16 * nt + (lane & 15), g = lane >> 4;
+             const int h1 = bf ? phi_bf(k, g, j) : phi_f(k, g);
+             return W2(h1, h2);
+           }, &d.w2f)) != MPIP_OK) goto done;
+      for (int role = 0; role < 2; ++role) {
+        const std::vector<int>& lv = live[role];
+        const int NPl = (int)lv.size();
+        const int CN = C / 16, CB = C / 4;
+        if ((st = pack(NPl * CN, KC64, [&](int o, int k, int lane, int j) {
+               const int pi = o / CN, nt = o % CN, g = lane >> 4;
+               const int c = CN * (lane & 15) + nt;
+               const int h = bf ? phi_bf(k, g, j) : phi_f(k, g);
+               return W3(h, lv[pi] * C + c);
+             }, &d.w3fp[role])) != MPIP_OK) goto done;
+        if ((st = pack(NPl * CN, KC64, [&](int o, int k, int lane, int j) {
+               const int pi = o / CN, mt = o % CN, g = lane >> 4, rho = lane & 15;
+               const int c = CB * (rho / 4) + 4 * mt + (rho % 4);
+               const int h = bf ? phi_bf(k, g, j) : phi_f(k, g);
+               return W3(h, lv[pi] * C + c);
+             }, &d.w3t[role])) != MPIP_OK) goto done;
+        const int KCC = bf ? C / 32 : C / 4;
+        if ((st = pack(NPl * 4, KCC, [&](int o, int k, int lane, int j) {
+               const int pi = o / 4, mt = o % 4, g = lane >> 4;
+               const int h = 16 * mt + (lane & 15);
+               const int c = bf ? (CB * g + 8 * k + j) : (CB * g + k);
+               return W3(h, lv[pi] * C + c);
+             }, &d.w3bp[role])) != MPIP_OK) goto done;
+      }
+      for (int l = 0; l < 3; ++l) d.vt[l] = d.v[l] = nullptr;
+      if (t == 1) {
+        // species table ht1 = W_emb W_up[0] (FP64), then V_l = ht1 (x) W3_l / n_avg
+        std::vector<double> ht1((size_t)S * C, 0.0);
+        for (int sp = 0; sp < S; ++sp)
+          for (int c = 0; c < C; ++c) {
+            double acc = 0.0;
+            for (int cc = 0; cc < C; ++cc) acc += (double)emb[sp * C + cc] * (double)x.up[0][(size_t)cc * C + c];
+            ht1[(size_t)sp * C + c] = acc;
+          }
+        const int KQ = 64 * S;
+        for (int l = 0; l <= L; ++l) {
+          std::vector<float> V((size_t)KQ * C);   // [(s,k)][c]
+          for (int sp = 0; sp < S; ++sp)
+            for (int k = 0; k < H; ++k)
+              for (int c = 0; c < C; ++c)
+                V[((size_t)sp * 64 + k) * C + c] =
+                    (float)(ht1[(size_t)sp * C + c] * (double)W3(k, l * C + c) * hp->inv_avg_neighbors);
+          if ((st = node(V.data(), KQ, C, true, &d.vt[l])) != MPIP_OK) goto done;
+          if ((st = node(V.data(), KQ, C, false, &d.v[l])) != MPIP_OK) goto done;
+        }
+      }
     }
   }
   HIPCHK(hipDeviceSynchronize());
@@ -363,6 +422,7 @@ struct Plan {
   size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_scan, o_info, o_perm, o_iperm, o_pos,
       o_info_s, o_spec, o_owned, o_cnt, o_row, o_esrc, o_eshift, o_evec, o_erev, o_g;
   size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
+  size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
   std::vector<size_t> o_ht, o_z0, o_zl;  // per layer 1..K (index t-1)
   int max_bins;
   int nblocks_out;
@@ -411,6 +471,8 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
       p.o_z0.push_back(take(cur, sizeof(float) * N * C * (1 + L)));
       p.o_zl.push_back(t < K ? take(cur, sizeof(float) * N * (nlm - 1) * C) : 0);
     }
+    if ((C == 64 || C == 128) && S * nlm <= 64 && K >= 2)
+      p.o_qp = take(cur, sizeof(float) * N * nlm * 64 * S);
     p.o_atom_e = take(cur, sizeof(double) * N);
     p.nblocks_out = (int)((N + 255) / 256);
     p.o_partials = take(cur, sizeof(double) * 10 * p.nblocks_out);
@@ -528,27 +590,13 @@ mpip_status mpip_neighbor_list(const mpip_system* sys, double r_cut, void* strea
   return MPIP_OK;
 }
 
-mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K, void* stream,
-                          void* ws, size_t ws_bytes, int64_t max_edges, const mpip_outputs* out) {
-  if (!m) return fail(MPIP_EINVAL, "null model");
+}  // extern "C"
+
+// Layers forward, readout and the adjoint of all layers on a built CSR:
+// leaves dE/dr_e in the workspace (g) and per-atom energies (atom_e).
+static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b, int64_t N, mpip_precision prec,
+                      int32_t K, int64_t max_edges, hipStream_t s) {
   const mpip_hparams& hp = m->hp;
-  CellInfo ci;
-  mpip_status st = check_system(sys, &ci, hp.r_cut, hp.n_species);
-  if (st != MPIP_OK) return st;
-  if (prec != MPIP_FP32 && prec != MPIP_BF16_MIXED) return fail(MPIP_EINVAL, "bad precision");
-  if (K < 1 || K > hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
-  if (!out || !out->energy || !out->forces || !out->virial) return fail(MPIP_EINVAL, "null output buffer");
-  if (!ws) return fail(MPIP_EINVAL, "null workspace");
-  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
-  const int64_t N = sys->n_atoms;
-  Plan p = make_plan(N, max_edges, &hp, K);
-  if (ws_bytes < p.total) return fail(MPIP_ECAPACITY, "workspace too small");
-  int cur = 0;
-  HIPCHK(hipGetDevice(&cur));
-  if (cur != m->device) HIPCHK(hipSetDevice(m->device));
-  hipStream_t s = (hipStream_t)stream;
-  char* w = (char*)ws;
-  NbrBuffers b = nbr_buffers(w, p);
   const int C = hp.channels, L = hp.l_max, nlm = (L + 1) * (L + 1), S = hp.n_species;
   const int pi = prec == MPIP_BF16_MIXED ? 1 : 0;
   const std::vector<LayerDev>& LD = m->layers[pi];
@@ -559,13 +607,7 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
   float* htbar = (float*)(w + p.o_htbar);
   float4* g = (float4*)(w + p.o_g);
   double* atom_e = (double*)(w + p.o_atom_e);
-
   PhaseTimer& T = m->timer;
-  launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
-  T.begin("neighbors", s);
-  build_neighbors(b, *sys, ci, max_edges, s);
-  T.end(s);
-
   EdgeArgs ea;
   ea.n = N;
   ea.row_ptr = b.row_ptr;
@@ -587,8 +629,8 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
   na.h = h; na.hbar = hbar; na.atom_e = atom_e;
 
   auto gemm = [&](const float* x, int64_t xs, int64_t xr, float* y, int64_t ys, int64_t yr, int64_t M, int rpa,
-                  int Kd, int Nout, int ldw, const void* wt, int accumulate) {
-    GemmArgs ga{x, xs, xr, y, ys, yr, M, rpa, Kd, Nout, ldw, wt, accumulate};
+                  int Kd, int Nout, int ldw, const void* wt, int accumulate, int y_bf16 = 0) {
+    GemmArgs ga{x, xs, xr, y, ys, yr, M, rpa, Kd, Nout, ldw, wt, accumulate, y_bf16};
     T.begin("node_gemm", s);
     launch_gemm(prec, ga, s);
     T.end(s);
@@ -600,22 +642,57 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
     if (t == 1) return K == 1 ? KIND_ONLY : KIND_FIRST;
     return t == K ? KIND_LAST : KIND_MID;
   };
+  // specialised kernels: first layer (species factorisation) and last layer
+  const bool fast_cl = !m->force_generic && (C == 64 || C == 128);
+  auto fast_layer = [&](int t) {
+    const int kind = kind_of(t);
+    if (!fast_cl) return false;
+    if (kind == KIND_FIRST) return S * nlm <= 64;
+    return kind == KIND_LAST;
+  };
+  const int KQ = 64 * S;
+  float* qp = p.o_qp ? (float*)(w + p.o_qp) : nullptr;
+  FastArgs fa;
+  fa.n = N; fa.row_ptr = b.row_ptr; fa.e_src = b.e_src; fa.e_vec = b.e_vec; fa.capacity = max_edges;
+  fa.status = b.status; fa.rc = (float)hp.r_cut; fa.envelope_p = hp.envelope_p; fa.n_species = S;
+  fa.inv_n = (float)hp.inv_avg_neighbors; fa.Q = qp; fa.P = qp; fa.g = g; fa.htbar = htbar;
+  auto set_fast = [&](const LayerDev& d, int role) {
+    fa.w1a = d.w1a; fa.w2a = d.w2a; fa.w2b = d.w2b; fa.w1b = d.w1b; fa.w2f = d.w2f;
+    fa.w3f = d.w3fp[role]; fa.w3t = d.w3t[role]; fa.w3b = d.w3bp[role]; fa.cg = d.cg[role];
+  };
+  const int ht_bf16 = prec == MPIP_BF16_MIXED ? 1 : 0;
+
   const int nz = C * (1 + L);
   for (int t = 1; t <= K; ++t) {
     const LayerDev& d = LD[t - 1];
     const int kind = kind_of(t), role = (t == K) ? 1 : 0;
     const int nout = (kind == KIND_ONLY || kind == KIND_LAST) ? 1 : nlm;
+    const bool fast = fast_layer(t);
     float* ht = (t == 1) ? ht1 : (float*)(w + p.o_ht[t - 1]);
     if (t >= 2)
       for (int l = 0; l <= L; ++l)
         gemm(h + l * l * C, (int64_t)nlm * C, C, ht + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1), 2 * l + 1, C,
-             C, C, d.up_t[l], 0);
-    ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;
-    ea.w3f = d.w3f[role]; ea.w3b = d.w3b[role]; ea.cg = d.cg[role];
-    ea.ht = ht; ea.A = A;
+             C, C, d.up_t[l], 0, fast ? ht_bf16 : 0);
     T.begin("edge_fwd_t" + std::to_string(t), s);
-    launch_edge_fwd(prec, C, L, kind, ea, s);
+    if (fast) {
+      set_fast(d, role);
+      if (kind == KIND_FIRST) {
+        launch_l1(prec, L, true, fa, s);
+      } else {
+        fa.ht = ht; fa.A = A;
+        launch_l2(prec, C, L, 0, fa, s);
+      }
+    } else {
+      ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;
+      ea.w3f = d.w3f[role]; ea.w3b = d.w3b[role]; ea.cg = d.cg[role];
+      ea.ht = ht; ea.A = A;
+      launch_edge_fwd(prec, C, L, kind, ea, s);
+    }
     T.end(s);
+    if (fast && kind == KIND_FIRST)
+      for (int l = 0; l <= L; ++l)   // A_l = Q_l V_l
+        gemm(qp + l * l * KQ, (int64_t)nlm * KQ, KQ, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1), 2 * l + 1,
+             KQ, C, KQ, d.vt[l], 0);
     float* z0 = (float*)(w + p.o_z0[t - 1]);
     float* zl = t < K ? (float*)(w + p.o_zl[t - 1]) : nullptr;
     gemm(A, (int64_t)nout * C, 0, z0, nz, 0, N, 1, C, (t == K) ? C : nz, C, d.down_t[0], 0);
@@ -640,6 +717,7 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
     const LayerDev& d = LD[t - 1];
     const int kind = kind_of(t), role = (t == K) ? 1 : 0;
     const int nout = (kind == KIND_ONLY || kind == KIND_LAST) ? 1 : nlm;
+    const bool fast = fast_layer(t);
     float* ht = (t == 1) ? ht1 : (float*)(w + p.o_ht[t - 1]);
     float* z0 = (float*)(w + p.o_z0[t - 1]);
     float* zl = t < K ? (float*)(w + p.o_zl[t - 1]) : nullptr;
@@ -653,17 +731,69 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
       for (int l = 1; l <= L; ++l)
         gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
              2 * l + 1, C, C, C, d.down[l], 0);
-    ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;
-    ea.w3f = d.w3f[role]; ea.w3b = d.w3b[role]; ea.cg = d.cg[role];
-    ea.ht = ht; ea.Abar = A;
+    if (fast && kind == KIND_FIRST)
+      for (int l = 0; l <= L; ++l)   // P_l = Abar_l V_l^T
+        gemm(A + l * l * C, (int64_t)nlm * C, C, qp + l * l * KQ, (int64_t)nlm * KQ, KQ, N * (2 * l + 1), 2 * l + 1,
+             C, KQ, C, d.v[l], 0);
     T.begin("edge_bwd_t" + std::to_string(t), s);
-    launch_edge_bwd(prec, C, L, kind, ea, s);
+    if (fast) {
+      set_fast(d, role);
+      if (kind == KIND_FIRST) {
+        launch_l1(prec, L, false, fa, s);
+      } else {
+        fa.ht = ht; fa.Abar = A;
+        launch_l2(prec, C, L, 1, fa, s);
+        T.end(s);
+        T.begin("edge_pull_t" + std::to_string(t), s);
+        launch_l2(prec, C, L, 2, fa, s);
+      }
+    } else {
+      ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;
+      ea.w3f = d.w3f[role]; ea.w3b = d.w3b[role]; ea.cg = d.cg[role];
+      ea.ht = ht; ea.Abar = A;
+      launch_edge_bwd(prec, C, L, kind, ea, s);
+    }
     T.end(s);
     if (t >= 2)
       for (int l = 0; l <= L; ++l)
         gemm(htbar + l * l * C, (int64_t)nlm * C, C, hbar + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
              2 * l + 1, C, C, C, d.up[l], 1);
   }
+}
+
+extern "C" {
+
+mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K, void* stream,
+                          void* ws, size_t ws_bytes, int64_t max_edges, const mpip_outputs* out) {
+  if (!m) return fail(MPIP_EINVAL, "null model");
+  const mpip_hparams& hp = m->hp;
+  CellInfo ci;
+  mpip_status st = check_system(sys, &ci, hp.r_cut, hp.n_species);
+  if (st != MPIP_OK) return st;
+  if (prec != MPIP_FP32 && prec != MPIP_BF16_MIXED) return fail(MPIP_EINVAL, "bad precision");
+  if (K < 1 || K > hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
+  if (!out || !out->energy || !out->forces || !out->virial) return fail(MPIP_EINVAL, "null output buffer");
+  if (!ws) return fail(MPIP_EINVAL, "null workspace");
+  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  const int64_t N = sys->n_atoms;
+  Plan p = make_plan(N, max_edges, &hp, K);
+  if (ws_bytes < p.total) return fail(MPIP_ECAPACITY, "workspace too small");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != m->device) HIPCHK(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  NbrBuffers b = nbr_buffers(w, p);
+  float4* g = (float4*)(w + p.o_g);
+  double* atom_e = (double*)(w + p.o_atom_e);
+
+  PhaseTimer& T = m->timer;
+  launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
+  T.begin("neighbors", s);
+  build_neighbors(b, *sys, ci, max_edges, s);
+  T.end(s);
+
+  run_model(m, p, w, b, N, prec, K, max_edges, s);
   OutArgs oa;
   oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = g; oa.e_rev = b.e_rev; oa.perm = b.perm;
   oa.owned_s = b.owned_s; oa.atom_e = atom_e; oa.capacity = max_edges; oa.status = b.status;
@@ -717,6 +847,159 @@ mpip_status mpip_timing_read(mpip_model* m, mpip_timing* out) {
     out->ms[k] = T.ms[k];
     out->calls[k] = T.calls[k];
   }
+  return MPIP_OK;
+}
+
+static int slab_nimg(double L, double halo) { return (int)std::ceil(halo / L) + 1; }
+
+size_t mpip_slab_workspace_size(int64_t n, double L, double halo) {
+  if (n < 1 || !(L > 0.0) || !(halo >= 0.0)) return 0;
+  const int ncat = 2 * slab_nimg(L, halo) + 2;
+  size_t cur = 0;
+  take(cur, sizeof(int32_t) * ncat * n);
+  take(cur, sizeof(int32_t) * ncat * (n + 1));
+  take(cur, sizeof(int32_t) * scan_tmp_elems(n + 1));
+  take(cur, sizeof(int64_t) * (ncat + 1));
+  return cur + 256;
+}
+
+mpip_status mpip_slab_share(const double* pos, const int32_t* spec, int64_t n, const double* cell, int32_t axis,
+                            int32_t n_parts, int32_t part, double halo, void* stream, void* ws, size_t ws_bytes,
+                            int64_t capacity, double* out_pos, int32_t* out_spec, int32_t* out_idx,
+                            int64_t* n_local, int64_t* n_owned) {
+  if (!pos || !spec || !cell || !ws || !n_local || !n_owned) return fail(MPIP_EINVAL, "null argument");
+  if (n < 1 || axis < 0 || axis > 2 || n_parts < 1 || part < 0 || part >= n_parts || !(halo >= 0.0))
+    return fail(MPIP_EINVAL, "bad partition arguments");
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      if (r != c && cell[3 * r + c] != 0.0) return fail(MPIP_EUNSUPPORTED, "only orthorhombic cells are supported");
+  const double L = cell[4 * axis];
+  if (!(L > 0.0)) return fail(MPIP_ECELL, "cell length along the axis must be positive");
+  if (capacity > 0 && (!out_pos || !out_spec || !out_idx)) return fail(MPIP_EINVAL, "null outputs");
+  if (ws_bytes < mpip_slab_workspace_size(n, L, halo)) return fail(MPIP_ECAPACITY, "workspace too small");
+  SlabArgs sa;
+  sa.axis = axis; sa.P = n_parts; sa.part = part; sa.nimg = slab_nimg(L, halo); sa.L = L; sa.halo = halo;
+  sa.capacity = capacity;
+  const int ncat = 2 * sa.nimg + 2;
+  size_t cur = 0;
+  char* w = (char*)ws;
+  int32_t* flags = (int32_t*)(w + take(cur, sizeof(int32_t) * ncat * n));
+  int32_t* offs = (int32_t*)(w + take(cur, sizeof(int32_t) * ncat * (n + 1)));
+  int32_t* tmp = (int32_t*)(w + take(cur, sizeof(int32_t) * scan_tmp_elems(n + 1)));
+  int64_t* base = (int64_t*)(w + take(cur, sizeof(int64_t) * (ncat + 1)));
+  hipStream_t s = (hipStream_t)stream;
+  slab_share_launch(pos, spec, n, sa, flags, offs, tmp, s);
+  HIPCHK(hipGetLastError());
+  std::vector<int64_t> hb(ncat + 1, 0);
+  for (int c = 0; c < ncat; ++c) {
+    int32_t tot = 0;
+    HIPCHK(hipMemcpyAsync(&tot, offs + (int64_t)c * (n + 1) + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    hb[c + 1] = hb[c] + tot;
+  }
+  *n_local = hb[ncat];
+  *n_owned = hb[1];
+  if (hb[ncat] > capacity) return fail(MPIP_ECAPACITY, "share larger than capacity");
+  HIPCHK(hipMemcpyAsync(base, hb.data(), sizeof(int64_t) * (ncat + 1), hipMemcpyHostToDevice, s));
+  slab_write_launch(pos, spec, n, sa, flags, offs, base, out_pos, out_spec, out_idx, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return MPIP_OK;
+}
+
+mpip_status mpip_accumulate_rows(const double* src, const int32_t* index, int64_t n_rows, int64_t n_dst,
+                                 double* dst, void* stream) {
+  if (n_rows < 0 || n_dst < 0) return fail(MPIP_EINVAL, "negative size");
+  if (n_rows > 0 && (!src || !index || !dst)) return fail(MPIP_EINVAL, "null argument");
+  accumulate_rows_launch(src, index, n_rows, n_dst, dst, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return MPIP_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+static size_t batch_extra_offset(const Plan& p) { return (p.total + 255) & ~(size_t)255; }
+
+static size_t batch_bytes(const Plan& p, int64_t N, int B) {
+  size_t cur = batch_extra_offset(p);
+  take(cur, sizeof(int32_t) * N);
+  take(cur, sizeof(int64_t) * (B + 1));
+  take(cur, sizeof(BatchCell) * B);
+  return cur + 256;
+}
+
+mpip_status mpip_batch_workspace_size(const mpip_model* m, int64_t n_atoms, int32_t B, mpip_precision prec,
+                                      int32_t K, int64_t max_edges, size_t* bytes) {
+  if (!m || !bytes) return fail(MPIP_EINVAL, "null argument");
+  if (n_atoms < 1 || B < 1 || K < 1 || K > m->hp.n_layers || max_edges < 0) return fail(MPIP_EINVAL, "bad sizes");
+  if (prec != MPIP_FP32 && prec != MPIP_BF16_MIXED) return fail(MPIP_EINVAL, "bad precision");
+  *bytes = batch_bytes(make_plan(n_atoms, max_edges, &m->hp, K), n_atoms, B);
+  return MPIP_OK;
+}
+
+mpip_status mpip_evaluate_batch(mpip_model* m, int32_t B, const int64_t* atom_ptr, const double* positions,
+                                const int32_t* species, const double* cells, const uint8_t* pbc,
+                                mpip_precision prec, int32_t K, void* stream, void* ws, size_t ws_bytes,
+                                int64_t max_edges, double* energy, double* forces, double* virial) {
+  if (!m || !atom_ptr || !positions || !species || !cells || !pbc || !ws || !energy || !forces || !virial)
+    return fail(MPIP_EINVAL, "null argument");
+  const mpip_hparams& hp = m->hp;
+  if (B < 1) return fail(MPIP_EINVAL, "B must be >= 1");
+  if (prec != MPIP_FP32 && prec != MPIP_BF16_MIXED) return fail(MPIP_EINVAL, "bad precision");
+  if (K < 1 || K > hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
+  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  if (atom_ptr[0] != 0) return fail(MPIP_EINVAL, "atom_ptr[0] must be 0");
+  std::vector<BatchCell> hc(B);
+  for (int b = 0; b < B; ++b) {
+    if (atom_ptr[b + 1] <= atom_ptr[b]) return fail(MPIP_EINVAL, "every structure needs at least one atom");
+    BatchCell& c = hc[b];
+    for (int k = 0; k < 9; ++k) {
+      if (!std::isfinite(cells[9 * b + k])) return fail(MPIP_ECELL, "non-finite cell");
+      c.cell[k] = cells[9 * b + k];
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q)
+        if (r != q && c.cell[3 * r + q] != 0.0) return fail(MPIP_EUNSUPPORTED, "only orthorhombic cells are supported");
+    for (int d = 0; d < 3; ++d) {
+      c.pbc[d] = pbc[3 * b + d] ? 1 : 0;
+      c.L[d] = c.cell[4 * d];
+      if (c.pbc[d] && !(c.L[d] > 0.0)) return fail(MPIP_ECELL, "periodic cell length must be positive");
+      c.img[d] = c.pbc[d] ? (int)std::ceil(hp.r_cut / c.L[d]) + 1 : 0;
+      if (c.img[d] > 60) return fail(MPIP_ECELL, "cell too thin for the cutoff");
+    }
+  }
+  const int64_t N = atom_ptr[B];
+  if (N > ((int64_t)1 << 30)) return fail(MPIP_EINVAL, "too many atoms");
+  Plan p = make_plan(N, max_edges, &hp, K);
+  if (ws_bytes < batch_bytes(p, N, B)) return fail(MPIP_ECAPACITY, "workspace too small");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != m->device) HIPCHK(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  NbrBuffers b = nbr_buffers(w, p);
+  size_t off = batch_extra_offset(p);
+  BatchBuffers bb;
+  bb.sidx = (int32_t*)(w + take(off, sizeof(int32_t) * N));
+  int64_t* dptr = (int64_t*)(w + take(off, sizeof(int64_t) * (B + 1)));
+  BatchCell* dcells = (BatchCell*)(w + take(off, sizeof(BatchCell) * B));
+  bb.ptr = dptr;
+  bb.cells = dcells;
+  PhaseTimer& T = m->timer;
+  HIPCHK(hipMemcpyAsync(dptr, atom_ptr, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dcells, hc.data(), sizeof(BatchCell) * B, hipMemcpyHostToDevice, s));
+  launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
+  T.begin("neighbors", s);
+  build_neighbors_batch(b, bb, B, positions, species, N, hp.n_species, hp.r_cut, max_edges, s);
+  T.end(s);
+  run_model(m, p, w, b, N, prec, K, max_edges, s);
+  T.begin("outputs", s);
+  launch_batch_outputs(N, B, b, (const float4*)(w + p.o_g), (const double*)(w + p.o_atom_e), bb, max_edges, forces,
+                       energy, virial, s);
+  T.end(s);
+  hipError_t e = hipGetLastError();
+  if (cur != m->device) hipSetDevice(cur);
+  if (e != hipSuccess) return fail(MPIP_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return MPIP_OK;
 }
 

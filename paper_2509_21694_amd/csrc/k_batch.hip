@@ -1,0 +1,197 @@
+// Batched evaluation of many small independent structures in one pass: the
+// structures' atoms are concatenated and the neighbour list is built per
+// structure, so the CSR is block diagonal and every per-layer kernel runs
+// once over all rows of all structures.  Small periodic cells (thinner than
+// three cutoff bins) are searched over all images |S_k| <= img_k; the
+// membership test is the same FP64 expression as for single structures.
+#include "kernels.h"
+
+namespace mpip {
+
+__global__ void k_batch_index(const int64_t* __restrict__ ptr, int B, int32_t* __restrict__ sidx) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  for (int64_t i = ptr[b] + threadIdx.x; i < ptr[b + 1]; i += blockDim.x) sidx[i] = b;
+}
+
+// per atom: image index n_d = floor(x_d / L_d) along periodic axes (0 otherwise);
+// validity flags as in the single-structure path
+__global__ void k_batch_prep(const double* __restrict__ pos, const int32_t* __restrict__ spec, int64_t n,
+                             const int32_t* __restrict__ sidx, const BatchCell* __restrict__ cells, int n_species,
+                             int4* __restrict__ info, int32_t* __restrict__ spec_s, uint8_t* __restrict__ owned_s,
+                             int32_t* __restrict__ perm, int64_t* __restrict__ status) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BatchCell c = cells[sidx[i]];
+  int nimg[3];
+  int bad = 0;
+  for (int d = 0; d < 3; ++d) {
+    const double x = pos[3 * i + d];
+    if (!isfinite(x)) bad |= FL_NONFINITE;
+    nimg[d] = (c.pbc[d] && isfinite(x)) ? (int)floor(x / c.L[d]) : 0;
+  }
+  int sp = spec[i];
+  if (sp < 0 || sp >= n_species) bad |= FL_SPECIES;
+  spec_s[i] = sp < 0 ? 0 : (sp >= n_species ? n_species - 1 : sp);
+  info[i] = make_int4(nimg[0], nimg[1], nimg[2], 0);
+  owned_s[i] = 1;
+  perm[i] = (int32_t)i;
+  if (bad) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)bad);
+}
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ bool batch_pair(const double* xi, const double* xj, const BatchCell& c, int S0, int S1,
+                                           int S2, double rc2, double* dxo) {
+  double dx[3];
+  for (int k = 0; k < 3; ++k) {
+    const double s = __dadd_rn(__dadd_rn(__dmul_rn((double)S0, c.cell[0 * 3 + k]), __dmul_rn((double)S1, c.cell[1 * 3 + k])),
+                               __dmul_rn((double)S2, c.cell[2 * 3 + k]));
+    dx[k] = __dadd_rn(__dsub_rn(xj[k], xi[k]), s);
+  }
+  const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx[0], dx[0]), __dmul_rn(dx[1], dx[1])), __dmul_rn(dx[2], dx[2]));
+  dxo[0] = dx[0]; dxo[1] = dx[1]; dxo[2] = dx[2];
+  return d2 < rc2;
+}
+
+template <bool FILL>
+__global__ void k_batch_nbr(int64_t n, const double* __restrict__ pos, const int4* __restrict__ info,
+                            const int32_t* __restrict__ spec_s, const int32_t* __restrict__ sidx,
+                            const int64_t* __restrict__ ptr, const BatchCell* __restrict__ cells, double rc,
+                            int32_t* __restrict__ cnt, const int32_t* __restrict__ row_ptr, int64_t capacity,
+                            int32_t* __restrict__ e_src, uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec,
+                            int64_t* __restrict__ status) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (FILL && row_ptr[n] > capacity) return;
+  const int b = sidx[i];
+  const BatchCell c = cells[b];
+  const int64_t j0 = ptr[b], j1 = ptr[b + 1];
+  const int4 me = info[i];
+  const double xi[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+  const double rc2 = rc * rc;
+  int count = 0, coincident = 0;
+  const int64_t out = FILL ? row_ptr[i] : 0;
+  for (int oz = -c.img[2]; oz <= c.img[2]; ++oz)
+    for (int oy = -c.img[1]; oy <= c.img[1]; ++oy)
+      for (int ox = -c.img[0]; ox <= c.img[0]; ++ox)
+        for (int64_t j = j0; j < j1; ++j) {
+          const int4 oj = info[j];
+          const int S0 = c.pbc[0] ? ox - oj.x + me.x : 0;
+          const int S1 = c.pbc[1] ? oy - oj.y + me.y : 0;
+          const int S2 = c.pbc[2] ? oz - oj.z + me.z : 0;
+          if (j == i && S0 == 0 && S1 == 0 && S2 == 0) continue;
+          const double xj[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
+          double dx[3];
+          if (batch_pair(xi, xj, c, S0, S1, S2, rc2, dx)) {
+            if (dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+            if (FILL) {
+              const int64_t e = out + count;
+              e_src[e] = (int32_t)j;
+              e_shift[e] = (uint32_t)(S0 & 0xff) | ((uint32_t)(S1 & 0xff) << 8) | ((uint32_t)(S2 & 0xff) << 16);
+              e_vec[e] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], __int_as_float(spec_s[j]));
+            }
+            ++count;
+          }
+        }
+  if (!FILL) cnt[i] = count;
+  if (coincident) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_COINCIDENT);
+}
+
+__global__ void k_batch_capacity(const int32_t* __restrict__ row_ptr, int64_t n, int64_t capacity,
+                                 int64_t* __restrict__ status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int64_t E = row_ptr[n];
+    status[ST_NEDGES] = E;
+    if (E > capacity) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_CAPACITY);
+  }
+}
+
+// reverse edge of (i, j, S) is (j, i, -S) in row j (same as k_nbr_rev)
+__global__ void k_batch_rev(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ e_src,
+                            const uint32_t* __restrict__ e_shift, int64_t capacity, int32_t* __restrict__ e_rev) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || row_ptr[n] > capacity) return;
+  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    const int j = e_src[e];
+    const uint32_t sh = e_shift[e];
+    const int S0 = (int8_t)(sh & 0xff), S1 = (int8_t)((sh >> 8) & 0xff), S2 = (int8_t)((sh >> 16) & 0xff);
+    const uint32_t want = (uint32_t)((-S0) & 0xff) | ((uint32_t)((-S1) & 0xff) << 8) | ((uint32_t)((-S2) & 0xff) << 16);
+    int r = -1;
+    for (int f = row_ptr[j]; f < row_ptr[j + 1]; ++f)
+      if (e_src[f] == (int)i && e_shift[f] == want) { r = f; break; }
+    e_rev[e] = r;
+  }
+}
+
+void build_neighbors_batch(const NbrBuffers& b, const BatchBuffers& bb, int B, const double* pos,
+                           const int32_t* spec, int64_t n, int n_species, double rc, int64_t capacity, hipStream_t s) {
+  const int ga = (int)((n + 255) / 256);
+  k_batch_index<<<B, 256, 0, s>>>(bb.ptr, B, bb.sidx);
+  k_batch_prep<<<ga, 256, 0, s>>>(pos, spec, n, bb.sidx, bb.cells, n_species, b.info_s, b.spec_s, b.owned_s,
+                                  b.perm, b.status);
+  k_batch_nbr<false><<<ga, 256, 0, s>>>(n, pos, b.info_s, b.spec_s, bb.sidx, bb.ptr, bb.cells, rc, b.cnt, nullptr,
+                                        capacity, nullptr, nullptr, nullptr, b.status);
+  exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
+  k_batch_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
+  k_batch_nbr<true><<<ga, 256, 0, s>>>(n, pos, b.info_s, b.spec_s, bb.sidx, bb.ptr, bb.cells, rc, nullptr,
+                                       b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.status);
+  k_batch_rev<<<ga, 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, capacity, b.e_rev);
+}
+
+// one block per structure: forces of its atoms, its energy and virial (FP64, fixed order)
+__global__ __launch_bounds__(256) void k_batch_out(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                   const float4* __restrict__ e_vec, const float4* __restrict__ g,
+                                                   const int32_t* __restrict__ e_rev, const double* __restrict__ atom_e,
+                                                   const int64_t* __restrict__ ptr, int64_t capacity,
+                                                   const int64_t* __restrict__ status, double* __restrict__ forces,
+                                                   double* __restrict__ energy, double* __restrict__ virial) {
+  __shared__ double sh[10][256];
+  const int b = blockIdx.x;
+  double loc[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) loc[k] = 0.0;
+  const bool run = (status[ST_FLAGS] == 0) && ((int64_t)row_ptr[n] <= capacity);
+  if (run) {
+    for (int64_t i = ptr[b] + threadIdx.x; i < ptr[b + 1]; i += 256) {
+      double F[3] = {0.0, 0.0, 0.0};
+      for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        const float4 ge = g[e];
+        const int rv = e_rev[e];
+        const float4 gr = rv >= 0 ? g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 r = e_vec[e];
+        F[0] += (double)ge.x - (double)gr.x;
+        F[1] += (double)ge.y - (double)gr.y;
+        F[2] += (double)ge.z - (double)gr.z;
+        const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) loc[1 + 3 * p + q] += rr[p] * gg[q];
+      }
+      forces[3 * i + 0] = F[0];
+      forces[3 * i + 1] = F[1];
+      forces[3 * i + 2] = F[2];
+      loc[0] += atom_e[i];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = loc[k];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) energy[b] = sh[0][0];
+  if (threadIdx.x < 9) virial[9 * b + threadIdx.x] = -sh[1 + threadIdx.x][0];
+}
+
+void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g, const double* atom_e,
+                          const BatchBuffers& bb, int64_t capacity, double* forces, double* energy, double* virial,
+                          hipStream_t s) {
+  k_batch_out<<<B, 256, 0, s>>>(n, nb.row_ptr, nb.e_vec, g, nb.e_rev, atom_e, bb.ptr, capacity, nb.status, forces,
+                                energy, virial);
+}
+
+}  // namespace mpip

@@ -358,17 +358,21 @@ __global__ void k_check_capacity(const int32_t* __restrict__ row_ptr, int64_t n,
   }
 }
 
-// reverse edge of e = (i, j, S) is (j, i, -S) in row j
-__global__ void k_nbr_rev(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ e_src,
-                          const uint32_t* __restrict__ e_shift, int64_t capacity, int32_t* __restrict__ e_rev) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// reverse edge of e = (i, j, S) is (j, i, -S) in row j; one wave per row i,
+// one lane per edge of the row (rows longer than 64 loop)
+__global__ __launch_bounds__(256) void k_nbr_rev(int64_t n, const int32_t* __restrict__ row_ptr,
+                                                 const int32_t* __restrict__ e_src,
+                                                 const uint32_t* __restrict__ e_shift, int64_t capacity,
+                                                 int32_t* __restrict__ e_rev) {
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
   if (row_ptr[n] > capacity) return;
-  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-    int j = e_src[e];
-    uint32_t sh = e_shift[e];
-    int S0 = (int8_t)(sh & 0xff), S1 = (int8_t)((sh >> 8) & 0xff), S2 = (int8_t)((sh >> 16) & 0xff);
-    uint32_t want = (uint32_t)((-S0) & 0xff) | ((uint32_t)((-S1) & 0xff) << 8) | ((uint32_t)((-S2) & 0xff) << 16);
+  for (int e = row_ptr[i] + lane; e < row_ptr[i + 1]; e += 64) {
+    const int j = e_src[e];
+    const uint32_t sh = e_shift[e];
+    const int S0 = (int8_t)(sh & 0xff), S1 = (int8_t)((sh >> 8) & 0xff), S2 = (int8_t)((sh >> 16) & 0xff);
+    const uint32_t want = (uint32_t)((-S0) & 0xff) | ((uint32_t)((-S1) & 0xff) << 8) | ((uint32_t)((-S2) & 0xff) << 16);
     int r = -1;
     for (int f = row_ptr[j]; f < row_ptr[j + 1]; ++f)
       if (e_src[f] == (int)i && e_shift[f] == want) { r = f; break; }
@@ -418,7 +422,7 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
   k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
-  k_nbr_rev<<<ga, nblk, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, capacity, b.e_rev);
+  k_nbr_rev<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, capacity, b.e_rev);
 }
 
 void export_neighbors(const NbrBuffers& b, int64_t n, int64_t capacity, int32_t* oi, int32_t* oj, int32_t* os,

@@ -57,20 +57,125 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   for (int q = 0; q < 4; ++q) {
     const int64_t ro = rbase + 4 * g + q;
     if (ro >= a.M) continue;
-    float* yrow = a.y + (ro / a.rpa) * a.ys + (ro % a.rpa) * a.yr;
+    const int64_t yo = (ro / a.rpa) * a.ys + (ro % a.rpa) * a.yr;
+    float* yrow = a.y + yo;
+    __bf16* ybrow = (__bf16*)a.y + yo;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (t < ntl) {
         const int n = n0 + 16 * t + rr;
-        if (a.accumulate) yrow[n] += acc[t][q];
+        if (a.y_bf16) ybrow[n] = (__bf16)acc[t][q];
+        else if (a.accumulate) yrow[n] += acc[t][q];
         else yrow[n] = acc[t][q];
       }
     }
   }
 }
 
+// Weight-stationary GEMM: the block stages its NT x 16 columns of W in LDS
+// once (as MFMA B operands), then its 4 waves stream 16-row tiles of X
+// (grid-stride over row tiles), so W is read from L2 once per block.
+template <int PREC, int NT>
+__global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a, int64_t row_tiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, rr = lane & 15;
+  const int KCH = (PREC == 1) ? a.K / 32 : a.K / 4;
+  const int n0 = blockIdx.y * NT * 16;
+  if constexpr (PREC == 1) {
+    bf16x8* sb = (bf16x8*)smem;
+    const __bf16* W = (const __bf16*)a.wt;
+    for (int idx = threadIdx.x; idx < NT * KCH * 64; idx += 256) {
+      const int l = idx & 63, kc = (idx >> 6) % KCH, nt = (idx >> 6) / KCH;
+      const int n = n0 + 16 * nt + (l & 15);
+      sb[idx] = *(const bf16x8*)(W + (int64_t)n * a.ldw + 32 * kc + 8 * (l >> 4));
+    }
+  } else {
+    float* sb = (float*)smem;
+    const float* W = (const float*)a.wt;
+    for (int idx = threadIdx.x; idx < NT * KCH * 64; idx += 256) {
+      const int l = idx & 63, kc = (idx >> 6) % KCH, nt = (idx >> 6) / KCH;
+      const int n = n0 + 16 * nt + (l & 15);
+      sb[idx] = W[(int64_t)n * a.ldw + 4 * kc + (l >> 4)];
+    }
+  }
+  __syncthreads();
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < row_tiles; tile += (int64_t)gridDim.x * 4) {
+    const int64_t r = tile * 16 + rr;
+    const bool rv = r < a.M;
+    const float* xrow = rv ? a.x + (r / a.rpa) * a.xs + (r % a.rpa) * a.xr : a.x;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if constexpr (PREC == 1) {
+      const bf16x8* sb = (const bf16x8*)smem;
+      for (int kc = 0; kc < KCH; ++kc) {
+        bf16x8 av;
+        if (rv) {
+          const float4 u0 = *(const float4*)(xrow + 32 * kc + 8 * g);
+          const float4 u1 = *(const float4*)(xrow + 32 * kc + 8 * g + 4);
+          av[0] = (__bf16)u0.x; av[1] = (__bf16)u0.y; av[2] = (__bf16)u0.z; av[3] = (__bf16)u0.w;
+          av[4] = (__bf16)u1.x; av[5] = (__bf16)u1.y; av[6] = (__bf16)u1.z; av[7] = (__bf16)u1.w;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) av[j] = (__bf16)0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma_bf16(av, sb[(t * KCH + kc) * 64 + lane], acc[t]);
+      }
+    } else {
+      const float* sb = (const float*)smem;
+      for (int kc = 0; kc < KCH; ++kc) {
+        const float av = rv ? xrow[4 * kc + g] : 0.f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma_f32(av, sb[(t * KCH + kc) * 64 + lane], acc[t]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t ro = tile * 16 + 4 * g + q;
+      if (ro >= a.M) continue;
+      const int64_t yo = (ro / a.rpa) * a.ys + (ro % a.rpa) * a.yr;
+      float* yrow = a.y + yo;
+      __bf16* ybrow = (__bf16*)a.y + yo;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int n = n0 + 16 * t + rr;
+        if (a.y_bf16) ybrow[n] = (__bf16)acc[t][q];
+        else if (a.accumulate) yrow[n] += acc[t][q];
+        else yrow[n] = acc[t][q];
+      }
+    }
+  }
+}
+
+template <int PREC>
+static bool gemm_lds_try(int nt, const GemmArgs& g, hipStream_t s) {
+  const int KCH = (PREC == 1) ? g.K / 32 : g.K / 4;
+  const size_t per = (size_t)KCH * 64 * (PREC == 1 ? 16 : 4);
+  if ((g.Nout / 16) % nt != 0 || per * nt > 64 * 1024) return false;
+  const int64_t row_tiles = (g.M + 15) / 16;
+  int64_t gx = (row_tiles + 3) / 4;
+  if (gx > 1024) gx = 1024;
+  dim3 grid((unsigned)gx, (unsigned)(g.Nout / (16 * nt)));
+  const size_t lds = per * nt;
+  switch (nt) {
+    case 12: k_gemm_lds<PREC, 12><<<grid, 256, lds, s>>>(g, row_tiles); break;
+    case 8: k_gemm_lds<PREC, 8><<<grid, 256, lds, s>>>(g, row_tiles); break;
+    case 4: k_gemm_lds<PREC, 4><<<grid, 256, lds, s>>>(g, row_tiles); break;
+    default: k_gemm_lds<PREC, 2><<<grid, 256, lds, s>>>(g, row_tiles); break;
+  }
+  return true;
+}
+
 void launch_gemm(int prec, const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0) return;
+  const bool aligned = (g.xs % 4 == 0) && (g.xr % 4 == 0) && ((uintptr_t)g.x % 16 == 0);
+  if (aligned && g.M >= 4096) {
+    for (int nt : {12, 8, 4, 2}) {
+      if (prec == MPIP_BF16_MIXED ? gemm_lds_try<1>(nt, g, s) : gemm_lds_try<0>(nt, g, s)) return;
+    }
+  }
   dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.Nout + 63) / 64));
   if (prec == MPIP_BF16_MIXED) k_gemm<1><<<grid, 256, 0, s>>>(g);
   else k_gemm<0><<<grid, 256, 0, s>>>(g);

@@ -68,7 +68,49 @@ struct LayerDev {
   const void* up[3];     // W_up[l]     [C][C]
   const void* down_t[3]; // W_down[l]^T [C(1+L) or C][C]
   const void* down[3];   // W_down[l]   [C][C(1+L) or C]
+  // specialised first / last layer kernels (k_fast.hip)
+  const void* w2f;       // layer-2 B operand, edges x features orientation [nt 4][kc][64]
+  const void* w3fp[2];   // layer-3 B operand, channel of (tile nt, col n) = (C/16) n + nt
+  const void* w3t[2];    // layer-3 A operand, features x edges; channel of row rho in tile mt
+                         //   = (C/4)(rho/4) + 4 mt + rho%4
+  const void* w3bp[2];   // MLP-adjoint A operand; k-slot (g, j) of chunk kc = channel (C/4) g + 8 kc + j
+  // first layer, species factorisation: V_l[(s,k)][c] = ht1[s][c] W3[k][(l,c)] / n_avg
+  const void* vt[3];     // [C][S*64]  (A = Q V)
+  const void* v[3];      // [S*64][C]  (P = dA V^T)
 };
+
+struct FastArgs {
+  int64_t n;
+  const int32_t* row_ptr;
+  const int32_t* e_src;
+  const float4* e_vec;
+  int64_t capacity;
+  const int64_t* status;
+  float rc;
+  int envelope_p;
+  int n_species;
+  float inv_n;
+  const void* w1a;
+  const void* w2a;
+  const void* w2b;
+  const void* w1b;
+  const void* w2f;
+  const void* w3f;       // permuted (w3fp)
+  const void* w3t;
+  const void* w3b;       // permuted (w3bp)
+  const float* cg;
+  float* Q;              // first layer forward: [N][nlm][S*64]
+  const float* P;        // first layer adjoint: [N][nlm][S*64]
+  const void* ht;        // last layer: [N][nlm][C], bf16 (BF16 form) or f32
+  float* A;              // last layer forward: [N][C]
+  const float* Abar;     // last layer adjoint input: [N][C]
+  float* htbar;          // last layer adjoint output: [N][nlm][C]
+  float4* g;
+};
+
+void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s);
+// which: 0 forward, 1 adjoint (dR, dY, MLP), 2 adjoint (sender-side pull)
+void launch_l2(int prec, int C, int L, int which, const FastArgs& a, hipStream_t s);
 
 struct EdgeArgs {
   int64_t n;               // atoms
@@ -108,6 +150,7 @@ struct GemmArgs {
   int K; int Nout; int ldw;
   const void* wt;
   int accumulate;
+  int y_bf16;            // 1: y is bf16 (uint16) storage with the same strides
 };
 void launch_gemm(int prec, const GemmArgs& g, hipStream_t s);
 
@@ -148,6 +191,42 @@ struct OutArgs {
   double* virial;         // out [9]
 };
 void launch_outputs(const OutArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------------ batches
+struct BatchCell {
+  double cell[9];
+  double L[3];
+  int pbc[3];
+  int img[3];     // periodic images searched: -img..img per axis (0 if not periodic)
+};
+struct BatchBuffers {
+  const int64_t* ptr;      // [B+1] atom offsets (device copy)
+  const BatchCell* cells;  // [B]
+  int32_t* sidx;           // [N] structure of each atom
+};
+void build_neighbors_batch(const NbrBuffers& b, const BatchBuffers& bb, int B, const double* pos,
+                           const int32_t* spec, int64_t n, int n_species, double rc, int64_t capacity, hipStream_t s);
+void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g, const double* atom_e,
+                          const BatchBuffers& bb, int64_t capacity, double* forces, double* energy, double* virial,
+                          hipStream_t s);
+
+// ------------------------------------------------------------------ partitions
+struct SlabArgs {
+  int axis;
+  int P;          // number of slabs
+  int part;       // this slab
+  int nimg;       // periodic images -nimg..nimg considered for the halo
+  double L;       // cell length along the axis
+  double halo;    // halo depth
+  int64_t capacity;
+};
+void slab_share_launch(const double* pos, const int32_t* spec, int64_t n, const SlabArgs& sa, int32_t* flags,
+                       int32_t* offs, int32_t* scan_tmp, hipStream_t s);
+void slab_write_launch(const double* pos, const int32_t* spec, int64_t n, const SlabArgs& sa, const int32_t* flags,
+                       const int32_t* offs, const int64_t* base, double* out_pos, int32_t* out_spec,
+                       int32_t* out_idx, hipStream_t s);
+void accumulate_rows_launch(const double* src, const int32_t* index, int64_t n, int64_t n_dst, double* dst,
+                            hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace mpip

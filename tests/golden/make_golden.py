@@ -24,7 +24,9 @@ def save(name, res, extra=None):
          "atom_energy": res.atom_energy, "n_edges": np.int64(res.n_edges)}
     if extra:
         d.update(extra)
-    np.savez_compressed(os.path.join(OUT, name + ".npz"), **d)
+    tmp = os.path.join(OUT, name + ".tmp.npz")
+    np.savez_compressed(tmp, **d)
+    os.replace(tmp, os.path.join(OUT, name + ".npz"))
 
 
 def mpdp(K):

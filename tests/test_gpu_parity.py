@@ -209,3 +209,33 @@ def test_mpdp_parity(torch, M, K, prec):
     o = model.evaluate(pos, sp, s.cell, s.pbc, K=K, precision=prec, atom_energy=True)
     assert o["n_edges"] == int(g["n_edges"])
     compare(o, R, s.n_atoms, prec, f"mpdp K={K}", abs(np.linalg.det(s.cell)))
+
+
+# ----------------------------------------------------------- specialised kernels
+
+FAST_CASES = [(2, 64, 3), (1, 128, 3), (2, 128, 3), (1, 64, 8)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("L,C,S", FAST_CASES)
+def test_fast_kernels_parity(torch, M, L, C, S, prec):
+    """First / last layer specialised kernels (64 and 128 channels) against
+    the oracle on the 128-atom box, and against the generic kernels."""
+    import os as _os
+    s = W.small_system()
+    hp = W.HParams(n_species=S, n_layers=2, l_max=L, channels=C)
+    sp_np = (np.arange(128) * 7 % S).astype(np.int32)
+    blob = W.make_weights(hp, 40 + L + C + S)
+    ref = oracle.evaluate(s.positions, sp_np, s.cell, s.pbc, blob, hp)
+    model = M.Model(hp, blob)
+    _os.environ["MPIP_FORCE_GENERIC"] = "1"
+    try:
+        generic = M.Model(hp, blob)
+    finally:
+        del _os.environ["MPIP_FORCE_GENERIC"]
+    pos = torch.tensor(s.positions, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(sp_np, dtype=torch.int32, device="cuda")
+    o = model.evaluate(pos, sp, s.cell, s.pbc, precision=prec, atom_energy=True)
+    og = generic.evaluate(pos, sp, s.cell, s.pbc, precision=prec, atom_energy=True)
+    compare(o, ref, 128, prec, f"fast L={L} C={C} S={S}", abs(np.linalg.det(s.cell)))
+    compare(og, ref, 128, prec, f"generic L={L} C={C} S={S}", abs(np.linalg.det(s.cell)))
