@@ -629,8 +629,8 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   na.h = h; na.hbar = hbar; na.atom_e = atom_e;
 
   auto gemm = [&](const float* x, int64_t xs, int64_t xr, float* y, int64_t ys, int64_t yr, int64_t M, int rpa,
-                  int Kd, int Nout, int ldw, const void* wt, int accumulate, int y_bf16 = 0) {
-    GemmArgs ga{x, xs, xr, y, ys, yr, M, rpa, Kd, Nout, ldw, wt, accumulate, y_bf16};
+                  int Kd, int Nout, int ldw, const void* wt, int accumulate, int y_bf16 = 0, int x_bf16 = 0) {
+    GemmArgs ga{x, xs, xr, y, ys, yr, M, rpa, Kd, Nout, ldw, wt, accumulate, y_bf16, x_bf16};
     T.begin("node_gemm", s);
     launch_gemm(prec, ga, s);
     T.end(s);
@@ -661,6 +661,10 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
     fa.w3f = d.w3fp[role]; fa.w3t = d.w3t[role]; fa.w3b = d.w3bp[role]; fa.cg = d.cg[role];
   };
   const int ht_bf16 = prec == MPIP_BF16_MIXED ? 1 : 0;
+  // element offset into an array stored in FP32, or in BF16 when bf is set
+  auto at = [](float* base, int64_t elems, int bf) -> float* {
+    return bf ? (float*)((uint16_t*)base + elems) : base + elems;
+  };
 
   const int nz = C * (1 + L);
   for (int t = 1; t <= K; ++t) {
@@ -671,8 +675,8 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
     float* ht = (t == 1) ? ht1 : (float*)(w + p.o_ht[t - 1]);
     if (t >= 2)
       for (int l = 0; l <= L; ++l)
-        gemm(h + l * l * C, (int64_t)nlm * C, C, ht + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1), 2 * l + 1, C,
-             C, C, d.up_t[l], 0, fast ? ht_bf16 : 0);
+        gemm(h + l * l * C, (int64_t)nlm * C, C, at(ht, l * l * C, fast ? ht_bf16 : 0), (int64_t)nlm * C, C,
+             N * (2 * l + 1), 2 * l + 1, C, C, C, d.up_t[l], 0, fast ? ht_bf16 : 0);
     T.begin("edge_fwd_t" + std::to_string(t), s);
     if (fast) {
       set_fast(d, role);
@@ -690,9 +694,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
     }
     T.end(s);
     if (fast && kind == KIND_FIRST)
-      for (int l = 0; l <= L; ++l)   // A_l = Q_l V_l
-        gemm(qp + l * l * KQ, (int64_t)nlm * KQ, KQ, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1), 2 * l + 1,
-             KQ, C, KQ, d.vt[l], 0);
+      for (int l = 0; l <= L; ++l)   // A_l = Q_l V_l (Q in BF16 in the BF16 form)
+        gemm(at(qp, l * l * KQ, ht_bf16), (int64_t)nlm * KQ, KQ, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1), 2 * l + 1,
+             KQ, C, KQ, d.vt[l], 0, 0, ht_bf16);
     float* z0 = (float*)(w + p.o_z0[t - 1]);
     float* zl = t < K ? (float*)(w + p.o_zl[t - 1]) : nullptr;
     gemm(A, (int64_t)nout * C, 0, z0, nz, 0, N, 1, C, (t == K) ? C : nz, C, d.down_t[0], 0);
@@ -732,9 +736,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
              2 * l + 1, C, C, C, d.down[l], 0);
     if (fast && kind == KIND_FIRST)
-      for (int l = 0; l <= L; ++l)   // P_l = Abar_l V_l^T
-        gemm(A + l * l * C, (int64_t)nlm * C, C, qp + l * l * KQ, (int64_t)nlm * KQ, KQ, N * (2 * l + 1), 2 * l + 1,
-             C, KQ, C, d.v[l], 0);
+      for (int l = 0; l <= L; ++l)   // P_l = Abar_l V_l^T (P in BF16 in the BF16 form)
+        gemm(A + l * l * C, (int64_t)nlm * C, C, at(qp, l * l * KQ, ht_bf16), (int64_t)nlm * KQ, KQ, N * (2 * l + 1), 2 * l + 1,
+             C, KQ, C, d.v[l], 0, ht_bf16);
     T.begin("edge_bwd_t" + std::to_string(t), s);
     if (fast) {
       set_fast(d, role);

@@ -253,9 +253,16 @@ __global__ __launch_bounds__(64) void k_l1_fwd(FastArgs a) {
         const int m = 16 * mt + 4 * g + r;
         if (m < MROWS) {
           const int s = m / NLM, lm = m - s * NLM;
-          float* dst = a.Q + ((int64_t)i * NLM + lm) * KQ + s * 64 + el;
+          const int64_t o = ((int64_t)i * NLM + lm) * KQ + s * 64 + el;
+          if constexpr (PREC == 1) {
+            __bf16* dst = (__bf16*)a.Q + o;
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) dst[16 * nt] = q[mt][nt][r];
+            for (int nt = 0; nt < 4; ++nt) dst[16 * nt] = (__bf16)q[mt][nt][r];
+          } else {
+            float* dst = a.Q + o;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) dst[16 * nt] = q[mt][nt][r];
+          }
         }
       }
   }
@@ -274,10 +281,12 @@ __global__ __launch_bounds__(64) void k_l1_bwd(FastArgs a) {
   for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
     const float* Pi = a.P + (int64_t)i * NLM * KQ;
+    const __bf16* Pbi = (const __bf16*)a.P + (int64_t)i * NLM * KQ;
     auto Pval = [&](int m, int k) -> float {
       if (m >= MROWS) return 0.f;
       const int s = m / NLM, lm = m - s * NLM;
-      return Pi[lm * KQ + s * 64 + k];
+      if constexpr (PREC == 1) return (float)Pbi[lm * KQ + s * 64 + k];
+      else return Pi[lm * KQ + s * 64 + k];
     };
     // A operand of dE/da2^T = P^T Ysel^T: rows hidden 16 mt + el, k over (s,lm)
     typename O::T pa[4][KCQ];

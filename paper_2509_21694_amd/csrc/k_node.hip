@@ -18,7 +18,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   const int n0 = blockIdx.y * 64;
   const bool rv = r < a.M;
   const float* xrow = nullptr;
-  if (rv) xrow = a.x + (r / a.rpa) * a.xs + (r % a.rpa) * a.xr;
+  const __bf16* xbrow = nullptr;
+  if (rv) {
+    xrow = a.x + (r / a.rpa) * a.xs + (r % a.rpa) * a.xr;
+    xbrow = (const __bf16*)a.x + (r / a.rpa) * a.xs + (r % a.rpa) * a.xr;
+  }
   f32x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -28,7 +32,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     for (int k0 = 0; k0 < a.K; k0 += 32) {
       bf16x8 av;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) av[j] = (__bf16)(rv ? xrow[k0 + 8 * g + j] : 0.f);
+      for (int j = 0; j < 8; ++j)
+        av[j] = rv ? (a.x_bf16 ? xbrow[k0 + 8 * g + j] : (__bf16)xrow[k0 + 8 * g + j]) : (__bf16)0.f;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         if (t < ntl) {
@@ -103,7 +108,9 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a, int64_t row_tiles)
   for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < row_tiles; tile += (int64_t)gridDim.x * 4) {
     const int64_t r = tile * 16 + rr;
     const bool rv = r < a.M;
-    const float* xrow = rv ? a.x + (r / a.rpa) * a.xs + (r % a.rpa) * a.xr : a.x;
+    const int64_t xo = rv ? (r / a.rpa) * a.xs + (r % a.rpa) * a.xr : 0;
+    const float* xrow = a.x + xo;
+    const __bf16* xbrow = (const __bf16*)a.x + xo;
     f32x4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -111,7 +118,9 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a, int64_t row_tiles)
       const bf16x8* sb = (const bf16x8*)smem;
       for (int kc = 0; kc < KCH; ++kc) {
         bf16x8 av;
-        if (rv) {
+        if (rv && a.x_bf16) {
+          av = *(const bf16x8*)(xbrow + 32 * kc + 8 * g);
+        } else if (rv) {
           const float4 u0 = *(const float4*)(xrow + 32 * kc + 8 * g);
           const float4 u1 = *(const float4*)(xrow + 32 * kc + 8 * g + 4);
           av[0] = (__bf16)u0.x; av[1] = (__bf16)u0.y; av[2] = (__bf16)u0.z; av[3] = (__bf16)u0.w;
@@ -170,7 +179,8 @@ static bool gemm_lds_try(int nt, const GemmArgs& g, hipStream_t s) {
 
 void launch_gemm(int prec, const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0) return;
-  const bool aligned = (g.xs % 4 == 0) && (g.xr % 4 == 0) && ((uintptr_t)g.x % 16 == 0);
+  const int vec = g.x_bf16 ? 8 : 4;   // elements per 16-byte load
+  const bool aligned = (g.xs % vec == 0) && (g.xr % vec == 0) && ((uintptr_t)g.x % 16 == 0);
   if (aligned && g.M >= 4096) {
     for (int nt : {12, 8, 4, 2}) {
       if (prec == MPIP_BF16_MIXED ? gemm_lds_try<1>(nt, g, s) : gemm_lds_try<0>(nt, g, s)) return;

@@ -151,6 +151,7 @@ struct GemmArgs {
   const void* wt;
   int accumulate;
   int y_bf16;            // 1: y is bf16 (uint16) storage with the same strides
+  int x_bf16;            // 1: x is bf16 (uint16) storage with the same strides (BF16 form only)
 };
 void launch_gemm(int prec, const GemmArgs& g, hipStream_t s);
 
