@@ -417,119 +417,272 @@ template <> struct HT<0> {
   }
 };
 
-template <int PREC, int C, int L>
-__global__ __launch_bounds__(64) void k_l2_fwd(FastArgs a) {
+// sum over the 16 lanes of each DPP row (lanes 16g .. 16g+15); every lane of
+// the row receives the total
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false);
+  return v + __int_as_float(o);
+}
+__device__ __forceinline__ float row16_sum(float v) {
+  v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141>(v);   // row_half_mirror
+  v = dpp_add<0x140>(v);   // row_mirror
+  return v;
+}
+
+// LDS written by some lanes of a wave and read by others of the same wave
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Rows of the calling wave.  Workgroups are dispatched to the 8 XCDs in
+// round-robin order, so workgroup b runs on XCD b % 8: each XCD takes a
+// contiguous eighth of the spatially sorted rows and its waves walk that
+// range side by side, so the sender rows they gather stay within one L2.
+// The grid is a multiple of 8 workgroups.
+struct RowWalk {
+  int64_t i, end, step;
+};
+template <int NW>
+__device__ __forceinline__ RowWalk row_walk(int64_t n) {
+  const int b = blockIdx.x, x = b & 7, lb = b >> 3, BX = gridDim.x >> 3;
+  const int64_t r0 = n * x / 8, r1 = n * (x + 1) / 8;
+  return {r0 + (int64_t)lb * NW + (threadIdx.x >> 6), r1, (int64_t)BX * NW};
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void stage_lds(T* dst, const void* src) {
+  const T* s = (const T*)src;
+  for (int t = threadIdx.x; t < NT; t += blockDim.x) dst[t] = s[t];
+}
+
+// one gathered 8-channel piece of a sender row, kept packed until use
+template <int PREC> struct HRaw;
+template <> struct HRaw<1> {
+  uint4 v;
+  __device__ void load(const unsigned short* p) { v = *(const uint4*)p; }
+  __device__ void get(float* o) const {
+    const unsigned u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      o[2 * k] = __uint_as_float(u[k] << 16);
+      o[2 * k + 1] = __uint_as_float(u[k] & 0xffff0000u);
+    }
+  }
+};
+template <> struct HRaw<0> {
+  float4 a, b;
+  __device__ void load(const float* p) {
+    a = *(const float4*)p;
+    b = *(const float4*)(p + 4);
+  }
+  __device__ void get(float* o) const {
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+  }
+};
+
+// what one 8-channel chunk (path l, channels CB*g + 8k ..) reads, fetched
+// one chunk ahead of its use
+template <int PREC, int L>
+struct Chunk {
+  HRaw<PREC> h[2 * L + 1];             // h~_j[l, m, chunk]
+  typename Op<PREC>::T w[2][Op<PREC>::KC64];   // W3 operands of the chunk's two M-tiles (BF16 form)
+  typename Op<PREC>::T wb[4];          // MLP-adjoint operands (adjoint a, BF16 form)
+  float4 a0, a1;                       // dA_i of the chunk's channels (adjoint a)
+};
+
+// The last layer keeps W3 in LDS in the BF16 form (one copy per workgroup,
+// staged once by a persistent grid); the FP32 form reads it from global
+// memory.  Lanes own (channel block g of C/4 channels, edge el); channels go
+// 8 at a time (a "chunk") so only one chunk of R, h~_j and dR is live, and
+// the next chunk's gathers are in flight while the current one computes.
+// Tail lanes of a tile read row 0 with zero harmonics and zero radial
+// weights, so they add exact zeros.
+template <int PREC, int C, int L, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 1))) void k_l2_fwd(FastArgs a) {
   typedef Op<PREC> O;
   typedef typename HT<PREC>::T HTy;
   constexpr int NLM = (L + 1) * (L + 1);
-  constexpr int CN = C / 16;                 // channels per lane: CN * (lane % 16) .. + CN
-  __shared__ float syc[kTileE * NLM];
-  __shared__ int sj[kTileE];
+  constexpr int CB = C / 4, NK = CB / 8, CN = C / 16, NCH = (L + 1) * NK;
+  constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
+  __shared__ typename O::T sW[NWT];
   if (fast_guard(a)) return;
-  const int lane = threadIdx.x, g = lane >> 4, el = lane & 15;
+  if constexpr (PREC == 1) {
+    stage_lds<typename O::T, NWT>(sW, a.w3t);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
   const HTy* ht = (const HTy*)a.ht;
-  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+  const RowWalk rw = row_walk<NW>(a.n);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-    float acc[CN];
+    float acc[CB];
 #pragma unroll
-    for (int t = 0; t < CN; ++t) acc[t] = 0.f;
+    for (int q = 0; q < CB; ++q) acc[q] = 0.f;
     for (int t0 = e0; t0 < e1; t0 += kTileE) {
       const int e = t0 + el;
       const bool valid = e < e1;
+      const int j = valid ? a.e_src[e] : 0;
+      const HTy* hj = ht + (int64_t)j * NLM * C + CB * g;
+      Chunk<PREC, L> cb[2];
+      auto fetch = [&](auto cc, Chunk<PREC, L>& b) {
+        constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) b.h[m].load(hj + (l * l + m) * C + 8 * k);
+        if constexpr (PREC == 1) {
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int kc = 0; kc < O::KC64; ++kc) b.w[hh][kc] = sW[((l * CN + 2 * k + hh) * O::KC64 + kc) * 64 + lane];
+        }
+      };
+      fetch(std::integral_constant<int, 0>{}, cb[0]);
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
-      __syncthreads();
-      if (lane < kTileE) {
-        float yc[NLM];
-        yc_last<L>(a.cg, geo.Y, yc);
-#pragma unroll
-        for (int k = 0; k < NLM; ++k) syc[el * NLM + k] = yc[k];
-        sj[el] = valid ? a.e_src[e] : -1;
-      }
+      float yc[NLM];
+      yc_last<L>(a.cg, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4];
       mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
-      typename O::T aop[O::KC64];
+      typename O::T bop[O::KC64];
 #pragma unroll
-      for (int kc = 0; kc < O::KC64; ++kc) aop[kc] = O::from_tiles(a2, kc);
-      __syncthreads();
+      for (int kc = 0; kc < O::KC64; ++kc) bop[kc] = O::from_tiles(a2, kc);
+      static_for<NCH>([&](auto cc) {
+        constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (c + 1 < NCH) fetch(std::integral_constant<int, c + 1>{}, cb[(c + 1) & 1]);
+        const Chunk<PREC, L>& cur = cb[c & 1];
+        float R8[8];
 #pragma unroll
-      for (int l = 0; l <= L; ++l) {
-        f32x4 R[CN];
-#pragma unroll
-        for (int nt = 0; nt < CN; ++nt) {
+        for (int hh = 0; hh < 2; ++hh) {
           f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int kc = 0; kc < O::KC64; ++kc)
-            d = O::mma(aop[kc], O::load(a.w3f, ((l * CN + nt) * O::KC64 + kc) * 64 + lane), d);
-          R[nt] = d;
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ee = 4 * g + r;
-          if (t0 + ee < e1) {
-            const int j = sj[ee];
-            const HTy* hrow = ht + ((int64_t)j * NLM + l * l) * C + CN * el;
-            float s[CN];
-#pragma unroll
-            for (int t = 0; t < CN; ++t) s[t] = 0.f;
-#pragma unroll
-            for (int m = 0; m < 2 * l + 1; ++m) {
-              const float y = syc[ee * NLM + l * l + m];
-              float hv[CN];
-              HT<PREC>::template loadN<CN>(hrow + m * C, hv);
-#pragma unroll
-              for (int t = 0; t < CN; ++t) s[t] += hv[t] * y;
-            }
-#pragma unroll
-            for (int t = 0; t < CN; ++t) acc[t] += R[t][r] * s[t];
+          for (int kc = 0; kc < O::KC64; ++kc) {
+            typename O::T wv;
+            if constexpr (PREC == 1) wv = cur.w[hh][kc];
+            else wv = O::load(a.w3t, ((l * CN + 2 * k + hh) * O::KC64 + kc) * 64 + lane);
+            d = O::mma(wv, bop[kc], d);
           }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) R8[4 * hh + r] = d[r];
         }
-      }
+        float h[2 * l + 1][8];
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) cur.h[m].get(h[m]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          float s = 0.f;
+#pragma unroll
+          for (int m = 0; m < 2 * l + 1; ++m) s += h[m][q] * yc[l * l + m];
+          acc[8 * k + q] += R8[q] * s;
+        }
+      });
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int t = 0; t < CN; ++t) {
-      float vv = acc[t];
-      vv += __shfl_xor(vv, 16);
-      vv += __shfl_xor(vv, 32);
-      acc[t] = vv;
-    }
-    if (g == 0) {
+    for (int q = 0; q < CB; ++q) acc[q] = row16_sum(acc[q]);
+    if (el == 0) {
+      float* dst = a.A + (int64_t)i * C + CB * g;
 #pragma unroll
-      for (int t = 0; t < CN; ++t) a.A[(int64_t)i * C + CN * el + t] = a.inv_n * acc[t];
+      for (int q = 0; q < CB; q += 4)
+        *(float4*)(dst + q) = make_float4(a.inv_n * acc[q], a.inv_n * acc[q + 1], a.inv_n * acc[q + 2],
+                                          a.inv_n * acc[q + 3]);
     }
   }
 }
 
-// adjoint a: lanes own (channel block g of C/4 channels, edge el)
-template <int PREC, int C, int L>
-__global__ __launch_bounds__(64) void k_l2_bwd_a(FastArgs a) {
+// remaining MLP adjoint as in mlp_backward, with dE/de of edge el returned in
+// registers of lane el (< 16)
+template <int PREC>
+__device__ __forceinline__ void mlp_backward_reg(const f32x4* ab2, const f32x4* p1, const f32x4* p2, int lane,
+                                                 const void* w2b, const void* w1b, float* eb) {
+  typedef Op<PREC> O;
+  f32x4 pb2[4], pb1[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pb2[mt][r] = ab2[mt][r] * dsilu(p2[mt][r]);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < O::KC64; ++kc)
+      acc = O::mma(O::load(w2b, (mt * O::KC64 + kc) * 64 + lane), O::from_tiles(pb2, kc), acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
+  }
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(O::load(w1b, kc * 64 + lane), O::from_tiles(pb1, kc), acc);
+  // D rows n = 4g + r (basis index, g < 2), column = edge: lane el takes rows 0..3 from
+  // itself and rows 4..7 from lane el + 16
+  const int src = (lane & 15) + 16;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    eb[r] = acc[r];
+    eb[4 + r] = __shfl(acc[r], src);
+  }
+}
+
+// adjoint a: per edge dR, dE/dY and the MLP adjoint, in the layout and chunk
+// order of the forward kernel (W3 and its adjoint operands in LDS in the BF16 form)
+template <int PREC, int C, int L, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 2 : 1))) void k_l2_bwd_a(FastArgs a) {
   typedef Op<PREC> O;
   typedef typename HT<PREC>::T HTy;
   constexpr int NLM = (L + 1) * (L + 1);
-  constexpr int CB = C / 4;                  // channels per lane: CB * g .. + CB
-  constexpr int CN = C / 16;                 // M-tiles of the transposed layer-3 product
+  constexpr int CB = C / 4, NK = CB / 8, CN = C / 16, NCH = (L + 1) * NK;
   constexpr int KCC = O::kch(C);             // k-chunks over channels (MLP adjoint)
-  __shared__ float seb[kTileE * kNB];
+  constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
+  constexpr int NWB = (PREC == 1) ? (L + 1) * 4 * KCC * 64 : 1;
+  __shared__ typename O::T sW[NWT];
+  __shared__ typename O::T sWB[NWB];
   if (fast_guard(a)) return;
-  const int lane = threadIdx.x, g = lane >> 4, el = lane & 15;
+  if constexpr (PREC == 1) {
+    stage_lds<typename O::T, NWT>(sW, a.w3t);
+    stage_lds<typename O::T, NWB>(sWB, a.w3b);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
   const HTy* ht = (const HTy*)a.ht;
-  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+  const RowWalk rw = row_walk<NW>(a.n);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-    float Ai[CB];
-#pragma unroll
-    for (int q = 0; q < CB; ++q) Ai[q] = a.inv_n * a.Abar[(int64_t)i * C + CB * g + q];
+    const float* Abi = a.Abar + (int64_t)i * C + CB * g;
     for (int t0 = e0; t0 < e1; t0 += kTileE) {
       const int e = t0 + el;
       const bool valid = e < e1;
+      const int j = valid ? a.e_src[e] : 0;
+      const HTy* hj = ht + (int64_t)j * NLM * C + CB * g;
+      Chunk<PREC, L> cb[2];
+      auto fetch = [&](auto cc, Chunk<PREC, L>& b) {
+        constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) b.h[m].load(hj + (l * l + m) * C + 8 * k);
+        b.a0 = *(const float4*)(Abi + 8 * k);
+        b.a1 = *(const float4*)(Abi + 8 * k + 4);
+        if constexpr (PREC == 1) {
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int kc = 0; kc < O::KC64; ++kc) b.w[hh][kc] = sW[((l * CN + 2 * k + hh) * O::KC64 + kc) * 64 + lane];
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) b.wb[mt] = sWB[((l * 4 + mt) * KCC + k) * 64 + lane];
+        }
+      };
+      fetch(std::integral_constant<int, 0>{}, cb[0]);
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
-      const int j = valid ? a.e_src[e] : 0;
       float yc[NLM];
       yc_last<L>(a.cg, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4], ab2[4];
@@ -544,56 +697,57 @@ __global__ __launch_bounds__(64) void k_l2_bwd_a(FastArgs a) {
       float ycb[NLM];
 #pragma unroll
       for (int k = 0; k < NLM; ++k) ycb[k] = 0.f;
+      static_for<NCH>([&](auto cc) {
+        constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (c + 1 < NCH) fetch(std::integral_constant<int, c + 1>{}, cb[(c + 1) & 1]);
+        const Chunk<PREC, L>& cur = cb[c & 1];
+        float R8[8];
 #pragma unroll
-      for (int l = 0; l <= L; ++l) {
-        // R^T: rows = channels CB*g + 4 mt + r of this lane's edge
-        float R[CB];
-#pragma unroll
-        for (int mt = 0; mt < CN; ++mt) {
+        for (int hh = 0; hh < 2; ++hh) {
           f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int kc = 0; kc < O::KC64; ++kc)
-            d = O::mma(O::load(a.w3t, ((l * CN + mt) * O::KC64 + kc) * 64 + lane), bop[kc], d);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) R[4 * mt + r] = d[r];
-        }
-        float rb[CB];
-        const HTy* hrow = ht + ((int64_t)j * NLM + l * l) * C + CB * g;
-#pragma unroll
-        for (int q = 0; q < CB; ++q) rb[q] = 0.f;
-        if (valid) {
-#pragma unroll
-          for (int q0 = 0; q0 < CB; q0 += 8) {
-            float h[2 * L + 1][8];
-#pragma unroll
-            for (int m = 0; m < 2 * l + 1; ++m) HT<PREC>::template loadN<8>(hrow + m * C + q0, h[m]);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              float s = 0.f;
-#pragma unroll
-              for (int m = 0; m < 2 * l + 1; ++m) s += h[m][q] * yc[l * l + m];
-              rb[q0 + q] = Ai[q0 + q] * s;
-              const float w = R[q0 + q] * Ai[q0 + q];
-#pragma unroll
-              for (int m = 0; m < 2 * l + 1; ++m) ycb[l * l + m] += w * h[m][q];
-            }
+          for (int kc = 0; kc < O::KC64; ++kc) {
+            typename O::T wv;
+            if constexpr (PREC == 1) wv = cur.w[hh][kc];
+            else wv = O::load(a.w3t, ((l * CN + 2 * k + hh) * O::KC64 + kc) * 64 + lane);
+            d = O::mma(wv, bop[kc], d);
           }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) R8[4 * hh + r] = d[r];
         }
-        // MLP adjoint through layer 3: ab2^T += W3_l (hidden x C) x rbar^T
+        const float Ai[8] = {cur.a0.x, cur.a0.y, cur.a0.z, cur.a0.w, cur.a1.x, cur.a1.y, cur.a1.z, cur.a1.w};
+        float h[2 * l + 1][8];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int m = 0; m < 2 * l + 1; ++m) cur.h[m].get(h[m]);
+        float rb[8];
 #pragma unroll
-          for (int kc = 0; kc < KCC; ++kc) {
+        for (int q = 0; q < 8; ++q) {
+          const float ai = a.inv_n * Ai[q];
+          float s = 0.f;
+#pragma unroll
+          for (int m = 0; m < 2 * l + 1; ++m) s += h[m][q] * yc[l * l + m];
+          rb[q] = ai * s;
+          const float w = R8[q] * ai;
+#pragma unroll
+          for (int m = 0; m < 2 * l + 1; ++m) ycb[l * l + m] += w * h[m][q];
+        }
+        // MLP adjoint through layer 3: ab2^T += W3_l (hidden x C) rbar^T over this chunk's channels
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          if constexpr (PREC == 1) {
             typename O::T bv;
-            if constexpr (PREC == 1) {
 #pragma unroll
-              for (int jj = 0; jj < 8; ++jj) bv[jj] = (__bf16)rb[8 * kc + jj];
-            } else {
-              bv = rb[kc];
-            }
-            ab2[mt] = O::mma(O::load(a.w3b, ((l * 4 + mt) * KCC + kc) * 64 + lane), bv, ab2[mt]);
+            for (int jj = 0; jj < 8; ++jj) bv[jj] = (__bf16)rb[jj];
+            ab2[mt] = O::mma(cur.wb[mt], bv, ab2[mt]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              ab2[mt] = O::mma(O::load(a.w3b, ((l * 4 + mt) * KCC + 8 * k + q) * 64 + lane), rb[q], ab2[mt]);
           }
-      }
+        }
+      });
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int k = 0; k < NLM; ++k) {
         float w = ycb[k];
@@ -601,53 +755,73 @@ __global__ __launch_bounds__(64) void k_l2_bwd_a(FastArgs a) {
         w += __shfl_xor(w, 32);
         ycb[k] = w;
       }
-      __syncthreads();
-      mlp_backward<PREC>(ab2, p1, p2, lane, a.w2b, a.w1b, seb);
-      __syncthreads();
+      float eb[kNB];
+      mlp_backward_reg<PREC>(ab2, p1, p2, lane, a.w2b, a.w1b, eb);
       if (lane < kTileE && valid) {
         float Yb[kMaxNlm];
 #pragma unroll
         for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
         yc_last_adj<L>(a.cg, ycb, Yb);
-        add_edge_grad(a.g, e, geo, seb + el * kNB, Yb);
+        add_edge_grad(a.g, e, geo, eb, Yb);
       }
     }
   }
 }
 
-// adjoint b: the sender-side feature adjoint, pulled through the reverse edge
-template <int PREC, int C, int L>
-__global__ __launch_bounds__(64) void k_l2_bwd_b(FastArgs a) {
+// adjoint b: the sender-side feature adjoint pulled through the reverse edge,
+//   htbar_i[lm, c] = sum_e (-1)^l YC_e[lm] R_e[l, c] dA_{j_e}[c] / n_avg,
+// as an MFMA over the 16 edges of a tile: D[lm][c] += YC^T[lm][e] U_l[e][c]
+// with U_l = R_l * dA_j in the edges x channels layout of R (lane (g, n):
+// edges 4g + r, channel (C/16) n + nt), which is directly the B operand.
+template <int PREC, int C, int L, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 1))) void k_l2_bwd_b(FastArgs a) {
   typedef Op<PREC> O;
   constexpr int NLM = (L + 1) * (L + 1);
   constexpr int CN = C / 16;
-  __shared__ float syc[kTileE * NLM];
-  __shared__ int sj[kTileE];
+  constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
+  __shared__ typename O::T sW[NWT];
+  __shared__ float sY[NW][kTileE * 16];
   if (fast_guard(a)) return;
-  const int lane = threadIdx.x, g = lane >> 4, el = lane & 15;
-  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+  if constexpr (PREC == 1) {
+    stage_lds<typename O::T, NWT>(sW, a.w3f);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
+  float* syc = sY[wv];
+  const RowWalk rw = row_walk<NW>(a.n);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-    float hb[NLM][CN];
+    f32x4 hb[CN];
 #pragma unroll
-    for (int k = 0; k < NLM; ++k)
-#pragma unroll
-      for (int t = 0; t < CN; ++t) hb[k][t] = 0.f;
+    for (int t = 0; t < CN; ++t) hb[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int t0 = e0; t0 < e1; t0 += kTileE) {
       const int e = t0 + el;
       const bool valid = e < e1;
+      const int j = valid ? a.e_src[e] : 0;
+      // dA of the senders of this lane's edges 4g + r, channels CN*el .. + CN
+      float Aj[4][CN];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jr = __shfl(j, 4 * g + r);
+        const float* src = a.Abar + (int64_t)jr * C + CN * el;
+#pragma unroll
+        for (int t = 0; t < CN; t += 4) {
+          const float4 w = *(const float4*)(src + t);
+          Aj[r][t] = w.x; Aj[r][t + 1] = w.y; Aj[r][t + 2] = w.z; Aj[r][t + 3] = w.w;
+        }
+      }
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
-      __syncthreads();
-      if (lane < kTileE) {
+      if (g == 0) {
         float yc[NLM];
         yc_last<L>(a.cg, geo.Y, yc);
 #pragma unroll
-        for (int l = 0; l <= L; ++l)
-#pragma unroll
-          for (int m = 0; m < 2 * l + 1; ++m)
-            syc[el * NLM + l * l + m] = (l & 1) ? -yc[l * l + m] : yc[l * l + m];
-        sj[el] = valid ? a.e_src[e] : -1;
+        for (int k = 0; k < 16; ++k) {
+          float val = 0.f;
+          if (k < NLM) val = (k >= 1 && k < 4) ? -yc[k] : yc[k];
+          syc[el * 16 + k] = val;
+        }
       }
       f32x4 p1[4], p2[4], a2[4];
       mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
@@ -658,49 +832,52 @@ __global__ __launch_bounds__(64) void k_l2_bwd_b(FastArgs a) {
       typename O::T aop[O::KC64];
 #pragma unroll
       for (int kc = 0; kc < O::KC64; ++kc) aop[kc] = O::from_tiles(a2, kc);
-      __syncthreads();
-      // gather dA of the 4 senders of this lane's edges (channels CN*el .. + CN)
-      float Aj[4][CN];
+      wave_lds_sync();
+      // YC^T rows lm = el, edges 4g + r (zero for tail edges: their harmonics are zero)
+      float yt[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ee = 4 * g + r;
-        const bool ok = (t0 + ee) < e1;
-        const int jj = ok ? sj[ee] : 0;
+      for (int r = 0; r < 4; ++r) yt[r] = a.inv_n * syc[(4 * g + r) * 16 + el];
+      wave_lds_sync();
+      static_for<L + 1>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        const bool mine = el >= l * l && el < (l + 1) * (l + 1);
+        float ya[4];
 #pragma unroll
-        for (int t = 0; t < CN; ++t) Aj[r][t] = ok ? a.inv_n * a.Abar[(int64_t)jj * C + CN * el + t] : 0.f;
-      }
-#pragma unroll
-      for (int l = 0; l <= L; ++l) {
+        for (int r = 0; r < 4; ++r) ya[r] = mine ? yt[r] : 0.f;
 #pragma unroll
         for (int nt = 0; nt < CN; ++nt) {
           f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int kc = 0; kc < O::KC64; ++kc)
-            d = O::mma(aop[kc], O::load(a.w3f, ((l * CN + nt) * O::KC64 + kc) * 64 + lane), d);
+          for (int kc = 0; kc < O::KC64; ++kc) {
+            typename O::T wv2;
+            if constexpr (PREC == 1) wv2 = sW[((l * CN + nt) * O::KC64 + kc) * 64 + lane];
+            else wv2 = O::load(a.w3f, ((l * CN + nt) * O::KC64 + kc) * 64 + lane);
+            d = O::mma(aop[kc], wv2, d);
+          }
+          float u[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ee = 4 * g + r;
-            const float u = d[r] * Aj[r][nt];
+          for (int r = 0; r < 4; ++r) u[r] = d[r] * Aj[r][nt];
+          if constexpr (PREC == 1) {
+            const s16x4 av = {bfbits(ya[0]), bfbits(ya[1]), bfbits(ya[2]), bfbits(ya[3])};
+            const s16x4 bv = {bfbits(u[0]), bfbits(u[1]), bfbits(u[2]), bfbits(u[3])};
+            hb[nt] = mfma_bf16_k16(av, bv, hb[nt]);
+          } else {
 #pragma unroll
-            for (int m = 0; m < 2 * l + 1; ++m) hb[l * l + m][nt] += u * syc[ee * NLM + l * l + m];
+            for (int r = 0; r < 4; ++r) hb[nt] = mfma_f32(ya[r], u[r], hb[nt]);
           }
         }
-      }
+      });
     }
+    // D rows lm = 4g + r, column el = channels CN*el + nt
 #pragma unroll
-    for (int k = 0; k < NLM; ++k)
+    for (int r = 0; r < 4; ++r) {
+      const int lm = 4 * g + r;
+      if (lm < NLM) {
+        float* dst = a.htbar + ((int64_t)i * NLM + lm) * C + CN * el;
 #pragma unroll
-      for (int t = 0; t < CN; ++t) {
-        float vv = hb[k][t];
-        vv += __shfl_xor(vv, 16);
-        vv += __shfl_xor(vv, 32);
-        hb[k][t] = vv;
+        for (int t = 0; t < CN; t += 4)
+          *(float4*)(dst + t) = make_float4(hb[t][r], hb[t + 1][r], hb[t + 2][r], hb[t + 3][r]);
       }
-    if (g == 0) {
-#pragma unroll
-      for (int k = 0; k < NLM; ++k)
-#pragma unroll
-        for (int t = 0; t < CN; ++t) a.htbar[((int64_t)i * NLM + k) * C + CN * el + t] = hb[k][t];
     }
   }
 }
@@ -737,12 +914,25 @@ void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s) {
   }
 }
 
+// persistent grids: a multiple of 8 workgroups (one row range per XCD), at
+// most `per_xcd` workgroups per XCD and none without rows
+static int l2_grid(int64_t n, int nw, int per_xcd) {
+  const int64_t need = (n / 8 + nw - 1) / nw;
+  const int64_t per = need < 1 ? 1 : (need < per_xcd ? need : per_xcd);
+  return (int)(8 * per);
+}
+
 template <int PREC, int C, int L>
 static void l2_launch(int which, const FastArgs& a, hipStream_t s) {
-  const int gr = fast_grid(a.n);
-  if (which == 0) k_l2_fwd<PREC, C, L><<<gr, 64, 0, s>>>(a);
-  else if (which == 1) k_l2_bwd_a<PREC, C, L><<<gr, 64, 0, s>>>(a);
-  else k_l2_bwd_b<PREC, C, L><<<gr, 64, 0, s>>>(a);
+  // BF16 form: W3 staged in LDS ((L+1) C 128 B for the forward and the pull,
+  // twice that for adjoint a); forward and pull run 3 waves per SIMD (3
+  // workgroups of 4 waves per CU), adjoint a 2 (one workgroup of 8 waves for
+  // 128 channels, two of 4 for 64).  FP32 form: weights from memory.
+  constexpr int NWF = 4, NWA = (PREC == 1 && C == 128) ? 8 : 4;
+  const int pf = PREC == 1 ? 96 : 128, pa = PREC == 1 ? (NWA == 8 ? 32 : 64) : 128;
+  if (which == 0) k_l2_fwd<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
+  else if (which == 1) k_l2_bwd_a<PREC, C, L, NWA><<<l2_grid(a.n, NWA, pa), 64 * NWA, 0, s>>>(a);
+  else k_l2_bwd_b<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
 }
 
 template <int PREC>
