@@ -47,54 +47,85 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def edge_kernel_counts(hp, kind):
-    """Algorithmic work per directed edge of one fused edge kernel (live
-    paths only, no recompute): (mfma_flop, valu_flop, hbm_bytes).
-    kind: 'fwd_first', 'fwd_last', 'bwd_first', 'bwd_last'."""
-    C, L, H, nb = hp.channels, hp.l_max, hp.radial_hidden, hp.n_basis
-    P = L + 1
-    nlm = (L + 1) ** 2
-    mlp = nb * H + H * H + H * P * C
-    if kind == "fwd_first":     # R_e, then A_i[c, lm] += R_l h_z(j) Y_lm / sqrt(2l+1)
-        valu = C * (P + nlm)
-        hbm = 16 + 4                       # edge vector + sender index
-    elif kind == "fwd_last":    # s_l = <ht_j,l , Y_l>, A_i[c] += sum_l R_l s_l
-        valu = C * (nlm + P)
-        hbm = 16 + 4 + nlm * C * 4         # gathered ht_j (FP32)
-    elif kind == "bwd_first":   # dR_l = sum_m dA_i,lm Y_lm h ; dY_lm = sum_c R_l h dA_i,lm
-        valu = C * 2 * (nlm + P)
-        hbm = 16 + 4 + 16
-    else:                       # bwd_last: dR, dY and the sender-side pull through the reverse edge
-        valu = C * 3 * (nlm + P)
-        hbm = 16 + 4 + 16 + nlm * C * 4 + C * 4
-    return 2.0 * mlp, 2.0 * valu, float(hbm)
+def phase_counts(hp, prec):
+    """Algorithmic work of the specialised first/last-layer edge kernels, per
+    directed edge and per atom, for the formulation they implement (live
+    paths only, nothing recomputed is counted): {phase: (mfma_flop/edge,
+    valu_flop/edge, bytes/edge, bytes/atom)}.  Bytes are each array read or
+    written once per launch (unique bytes, not per-edge gathers)."""
+    C, L, H, nb, S = hp.channels, hp.l_max, hp.radial_hidden, hp.n_basis, hp.n_species
+    nlm, P = (L + 1) ** 2, L + 1
+    fb = 2 if prec == "bf16" else 4            # storage of Q/P and h~ in the form
+    mlp12, mlp3 = nb * H + H * H, H * P * C
+    ev, src, grw = 16, 4, 32                   # e_vec, e_src, g read+write
+    return {
+        # Q_i += a2 (x) YC over the row: layers 1-2 of the MLP and the outer product
+        "edge_fwd_t1": (2 * (mlp12 + H * nlm), 0.0, ev, 8 + nlm * 64 * S * fb),
+        # MLP adjoint through layers 2, 1; dE/da2 = P^T Ysel; dE/dYC = P a2
+        "edge_bwd_t1": (2 * (mlp12 + 2 * H * nlm), 0.0, ev + grw, 8 + nlm * 64 * S * fb),
+        # full MLP; s_l = <h~_j,l , YC_l> (nlm FMA/channel) and A += R s (P FMA/channel)
+        "edge_fwd_t2": (2 * (mlp12 + mlp3), 2.0 * C * (nlm + P), ev + src, 8 + nlm * C * fb + C * 4),
+        # MLP adjoint (W3, W2, W1); s (nlm FMA), dYC (nlm FMA), dR and R dA (2P mul) per channel
+        "edge_bwd_t2": (2 * (mlp12 + mlp3), C * (4.0 * nlm + 2 * P), ev + src + grw, 8 + nlm * C * fb + C * 4),
+        # h~bar_i = sum_e YC^T (R dA_j): nlm MAC per channel on MFMA; R dA_j: P mul per channel
+        "edge_pull_t2": (2.0 * nlm * C, 1.0 * P * C, ev + src, 8 + C * 4 + nlm * C * 4),
+    }
+
+
+def kernel_roofline(name, t, hp, prec, n_edges, n_atoms):
+    counts = phase_counts(hp, prec)
+    if name not in counts:
+        return None
+    fm, fv, be, ba = counts[name]
+    peak_m = PEAK["mfma_bf16"] if prec == "bf16" else PEAK["mfma_fp32"]
+    work = {"mfma": fm * n_edges, "alu": fv * n_edges, "hbm": be * n_edges + ba * n_atoms}
+    peak = {"mfma": peak_m, "alu": PEAK["alu_fp32"], "hbm": PEAK["hbm"]}
+    times = {k: work[k] / peak[k] for k in work}
+    bound = max(times, key=times.get)
+    unit = "GB/s" if bound == "hbm" else "TFLOP/s"
+    scale = 1e-9 if bound == "hbm" else 1e-12
+    return {"kernel": name, "bound": bound, "achieved": round(work[bound] / t * scale, 3),
+            "peak": round(peak[bound] * scale, 3), "unit": unit, "frac": round(work[bound] / t / peak[bound], 4),
+            "avg_ms": round(t * 1e3, 4), "work_per_launch": work[bound],
+            "roof_ms": {k: round(v * 1e3, 4) for k, v in times.items()}}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "edge_traffic_bulk1m.md")
+
+
+def measured_traffic(kernel_phase):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, or None when there is none for it or its sources have changed."""
+    from paper_2509_21694_amd.traffic_summary import sources_sha256
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if not ln.startswith("TRAFFIC_JSON: "):
+            continue
+        d = json.loads(ln[len("TRAFFIC_JSON: "):])
+        if d.get("phase") != kernel_phase:
+            continue
+        return d["bytes_per_launch"] if d.get("sources_sha256") == sources_sha256(ROOT) else None
+    return None
 
 
 def roofline_entry(phases, hp, n_edges, prec, n_atoms):
-    """Roofline of the edge kernel with the largest share of the step."""
-    cand = {k: v for k, v in phases.items() if k.startswith("edge_")}
-    name = max(cand, key=lambda k: cand[k][0] / max(1, cand[k][1]))
-    ms_total, calls = cand[name]
-    t = ms_total / calls * 1e-3
-    layer = int(name.split("_t")[-1])
-    kind = ("fwd_" if "fwd" in name else "bwd_") + ("first" if layer == 1 else "last")
-    fm, fv, b = edge_kernel_counts(hp, kind)
-    # node-level bytes are shared by all edges of a row: add them per launch
-    nlm = (hp.l_max + 1) ** 2
-    node_bytes = n_atoms * (nlm * hp.channels * 4 + 8)
-    peak_m = PEAK["mfma_bf16"] if prec == "bf16" else PEAK["mfma_fp32"]
-    times = {"mfma": fm * n_edges / peak_m, "alu": fv * n_edges / PEAK["alu_fp32"],
-             "hbm": (b * n_edges + node_bytes) / PEAK["hbm"]}
-    bound = max(times, key=times.get)
-    work = {"mfma": fm * n_edges, "alu": fv * n_edges, "hbm": b * n_edges + node_bytes}[bound]
-    peak = {"mfma": peak_m, "alu": PEAK["alu_fp32"], "hbm": PEAK["hbm"]}[bound]
-    unit = "GB/s" if bound == "hbm" else "TFLOP/s"
-    scale = 1e-9 if bound == "hbm" else 1e-12
-    achieved = work / t
-    return {"kernel": name, "bound": bound, "achieved": round(achieved * scale, 3),
-            "peak": round(peak * scale, 3), "unit": unit, "frac": round(achieved / peak, 4),
-            "traffic": None, "avg_ms": round(t * 1e3, 4),
-            "work_per_launch": work, "roof_ms": {k: round(v * 1e3, 4) for k, v in times.items()}}
+    """Roofline of the edge kernel with the largest share of the step, plus
+    the same figures for every specialised edge kernel."""
+    per = {}
+    for k, (ms_total, calls) in phases.items():
+        r = kernel_roofline(k, ms_total / calls * 1e-3, hp, prec, n_edges, n_atoms)
+        if r is not None:
+            per[k] = r
+    if not per:
+        return None
+    name = max(per, key=lambda k: phases[k][0])
+    top = dict(per[name])
+    top["traffic"] = measured_traffic(name) if prec == "bf16" else None
+    top["kernels"] = {k: {"bound": v["bound"], "frac": v["frac"], "avg_ms": v["avg_ms"]} for k, v in per.items()}
+    return top
 
 
 def cpu_baseline(s, hp, blob, K, radius):
@@ -133,6 +164,9 @@ def main():
     ap.add_argument("--precisions", default="bf16,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cluster-radius", type=float, default=24.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="copy MIB mebibytes device to device once before the steps (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -153,6 +187,16 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes read and written")
+        del src, dst
 
     base = {}
     if not args.no_cpu_baseline:

@@ -78,36 +78,29 @@ struct Geo {
   float dbasis[kNB];
 };
 
+// Tail lanes of a tile (valid == false) evaluate a unit vector along x and
+// are zeroed at the end, so the code has no divergent branch.
 __device__ __forceinline__ void edge_geometry(float4 v, bool valid, float rc, int p, Geo& g) {
-  if (!valid) {
-    g.u[0] = g.u[1] = g.u[2] = 0.f;
-    g.d = 1.f;
-#pragma unroll
-    for (int k = 0; k < kMaxNlm; ++k) g.Y[k] = 0.f;
-#pragma unroll
-    for (int k = 0; k < kNB; ++k) g.basis[k] = g.dbasis[k] = 0.f;
-    return;
-  }
-  const float d = sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
-  const float inv = 1.0f / d;
-  const float x = v.x * inv, y = v.y * inv, z = v.z * inv;
-  g.u[0] = x; g.u[1] = y; g.u[2] = z; g.d = d;
+  const float vx = valid ? v.x : 1.f, vy = valid ? v.y : 0.f, vz = valid ? v.z : 0.f;
+  const float d = sqrtf(vx * vx + vy * vy + vz * vz);
+  const float inv = __builtin_amdgcn_rcpf(d);
+  const float x = vx * inv, y = vy * inv, z = vz * inv;
+  const float msk = valid ? 1.f : 0.f;
+  g.u[0] = msk * x; g.u[1] = msk * y; g.u[2] = msk * z; g.d = d;
   const float s3 = 1.7320508075688772f, s5 = 2.23606797749979f, s15 = 3.872983346207417f;
-  g.Y[0] = 1.f;
-  g.Y[1] = s3 * y; g.Y[2] = s3 * z; g.Y[3] = s3 * x;
-  g.Y[4] = s15 * x * y; g.Y[5] = s15 * y * z; g.Y[6] = 0.5f * s5 * (3.f * z * z - 1.f);
-  g.Y[7] = s15 * x * z; g.Y[8] = 0.5f * s15 * (x * x - y * y);
-  // polynomial envelope of order p
+  g.Y[0] = msk;
+  g.Y[1] = msk * s3 * y; g.Y[2] = msk * s3 * z; g.Y[3] = msk * s3 * x;
+  g.Y[4] = msk * s15 * x * y; g.Y[5] = msk * s15 * y * z; g.Y[6] = msk * 0.5f * s5 * (3.f * z * z - 1.f);
+  g.Y[7] = msk * s15 * x * z; g.Y[8] = msk * 0.5f * s15 * (x * x - y * y);
+  // polynomial envelope of order p (zero from r_c on)
   const float xr = d / rc;
-  float env = 0.f, denv = 0.f;
-  if (xr < 1.f) {
-    const float a = 0.5f * (p + 1) * (p + 2), b = (float)(p * (p + 2)), c = 0.5f * p * (p + 1);
-    float xp1 = 1.f;  // x^(p-1)
-    for (int k = 0; k < p - 1; ++k) xp1 *= xr;
-    const float xp = xp1 * xr, xq = xp * xr, xs = xq * xr;
-    env = 1.f - a * xp + b * xq - c * xs;
-    denv = (-a * p * xp1 + b * (p + 1) * xp - c * (p + 2) * xq) / rc;
-  }
+  const float a = 0.5f * (p + 1) * (p + 2), b = (float)(p * (p + 2)), c = 0.5f * p * (p + 1);
+  float xp1 = 1.f;  // x^(p-1)
+  for (int k = 0; k < p - 1; ++k) xp1 *= xr;
+  const float xp = xp1 * xr, xq = xp * xr, xs = xq * xr;
+  const float in = (valid && xr < 1.f) ? 1.f : 0.f;
+  const float env = in * (1.f - a * xp + b * xq - c * xs);
+  const float denv = in * (-a * p * xp1 + b * (p + 1) * xp - c * (p + 2) * xq) / rc;
   // Bessel basis via the Chebyshev recurrence for sin(n t), cos(n t)
   const float pref = sqrtf(2.0f / rc);
   const float th = 3.14159265358979f * d / rc;
@@ -151,6 +144,13 @@ template <> struct Op<1> {  // BF16 operands, K = 32 per instruction
     return v;
   }
   __device__ static T load(const void* base, int idx) { return ((const T*)base)[idx]; }
+  // operand tile `tile` (64 lanes) of a packed array in global memory: the
+  // tile base is kept scalar and formed at its use, the lane adds a 32-bit offset
+  __device__ static T ldt(const void* base, int tile, int lane) {
+    const T* b = (const T*)base + (size_t)tile * 64;
+    asm volatile("" : "+s"(b));
+    return *(const T*)((const char*)b + (unsigned)lane * sizeof(T));
+  }
   // operand of channels 32*kc + 8*g + j from an LDS row
   __device__ static T from_row(const float* row, int kc, int g) {
     T v;
@@ -167,6 +167,11 @@ template <> struct Op<0> {  // FP32 operands, K = 4 per instruction
   __device__ static f32x4 mma(T a, T b, f32x4 c) { return mfma_f32(a, b, c); }
   __device__ static T from_tiles(const f32x4* t, int q) { return t[q / 4][q % 4]; }
   __device__ static T load(const void* base, int idx) { return ((const T*)base)[idx]; }
+  __device__ static T ldt(const void* base, int tile, int lane) {
+    const T* b = (const T*)base + (size_t)tile * 64;
+    asm volatile("" : "+s"(b));
+    return *(const T*)((const char*)b + (unsigned)lane * sizeof(T));
+  }
   __device__ static T from_row(const float* row, int q, int g) { return row[4 * q + g]; }
   static constexpr int kch(int K) { return K / 4; }
 };
@@ -180,9 +185,10 @@ __device__ __forceinline__ bf16x8 basis_op_bf16(const float* b, int g) {
   return v;
 }
 
-template <int PREC>
-__device__ __forceinline__ void mlp_forward(const Geo& geo, int lane, const void* w1a, const void* w2a,
-                                            f32x4* p1, f32x4* p2) {
+// W1, W2: operand arrays in global memory or LDS (same packing)
+template <int PREC, typename WT>
+__device__ __forceinline__ void mlp_forward_w(const Geo& geo, int lane, const WT* W1, const WT* W2, f32x4* p1,
+                                              f32x4* p2) {
   typedef Op<PREC> O;
   const int g = lane >> 4;
   const f32x4 z = {0.f, 0.f, 0.f, 0.f};
@@ -190,10 +196,10 @@ __device__ __forceinline__ void mlp_forward(const Geo& geo, int lane, const void
   for (int mt = 0; mt < 4; ++mt) {
     f32x4 acc = z;
     if constexpr (PREC == 1) {
-      acc = O::mma(O::load(w1a, mt * 64 + lane), basis_op_bf16(geo.basis, g), acc);
+      acc = O::mma(W1[mt * 64 + lane], basis_op_bf16(geo.basis, g), acc);
     } else {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc = O::mma(O::load(w1a, (mt * 2 + q) * 64 + lane), geo.basis[4 * q + g], acc);
+      for (int q = 0; q < 2; ++q) acc = O::mma(W1[(mt * 2 + q) * 64 + lane], geo.basis[4 * q + g], acc);
     }
     p1[mt] = acc;
   }
@@ -206,10 +212,16 @@ __device__ __forceinline__ void mlp_forward(const Geo& geo, int lane, const void
   for (int mt = 0; mt < 4; ++mt) {
     f32x4 acc = z;
 #pragma unroll
-    for (int kc = 0; kc < O::KC64; ++kc)
-      acc = O::mma(O::load(w2a, (mt * O::KC64 + kc) * 64 + lane), O::from_tiles(a1, kc), acc);
+    for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(W2[(mt * O::KC64 + kc) * 64 + lane], O::from_tiles(a1, kc), acc);
     p2[mt] = acc;
   }
+}
+
+template <int PREC>
+__device__ __forceinline__ void mlp_forward(const Geo& geo, int lane, const void* w1a, const void* w2a,
+                                            f32x4* p1, f32x4* p2) {
+  typedef typename Op<PREC>::T T;
+  mlp_forward_w<PREC, T>(geo, lane, (const T*)w1a, (const T*)w2a, p1, p2);
 }
 
 // R_p for one path: D[nt] tiles (edges 4g + r, channels 16 nt + lane%16) -> LDS
@@ -226,7 +238,7 @@ __device__ __forceinline__ void radial_out(const f32x4* a2, int lane, const void
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kc = 0; kc < O::KC64; ++kc)
-      acc = O::mma(aop[kc], O::load(w3f, ((p * (C / 16) + nt) * O::KC64 + kc) * 64 + lane), acc);
+      acc = O::mma(aop[kc], O::ldt(w3f, (p * (C / 16) + nt) * O::KC64 + kc, lane), acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r) sR[(4 * g + r) * RS + 16 * nt + n] = acc[r];
   }

@@ -376,7 +376,8 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
                return W3(h, lv[pi] * C + c);
              }, &d.w3bp[role])) != MPIP_OK) goto done;
       }
-      for (int l = 0; l < 3; ++l) d.vt[l] = d.v[l] = nullptr;
+      for (int l = 0; l < 3; ++l)
+        d.vt[l] = d.v[l] = d.vwt[l] = d.vw[l] = d.n1_vwt[l] = d.n1_upt[l] = d.n1_up[l] = d.n1_vw[l] = nullptr;
       if (t == 1) {
         // species table ht1 = W_emb W_up[0] (FP64), then V_l = ht1 (x) W3_l / n_avg
         std::vector<double> ht1((size_t)S * C, 0.0);
@@ -396,6 +397,43 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
                     (float)(ht1[(size_t)sp * C + c] * (double)W3(k, l * C + c) * hp->inv_avg_neighbors);
           if ((st = node(V.data(), KQ, C, true, &d.vt[l])) != MPIP_OK) goto done;
           if ((st = node(V.data(), KQ, C, false, &d.v[l])) != MPIP_OK) goto done;
+          // VW_l = V_l W_down_l (FP64): the messages A_l only feed the down projection
+          const int nz_l = l == 0 ? C * (1 + L) : C;
+          const float* Wd = x.down[l];   // [C][nz_l]
+          std::vector<float> VW((size_t)KQ * nz_l);
+          for (int sp = 0; sp < S; ++sp)
+            for (int k = 0; k < H; ++k)
+              for (int o = 0; o < nz_l; ++o) {
+                double acc = 0.0;
+                for (int c = 0; c < C; ++c)
+                  acc += ht1[(size_t)sp * C + c] * (double)W3(k, l * C + c) * (double)Wd[(size_t)c * nz_l + o];
+                VW[((size_t)sp * 64 + k) * nz_l + o] = (float)(acc * hp->inv_avg_neighbors);
+              }
+          if ((st = node(VW.data(), KQ, nz_l, true, &d.vwt[l])) != MPIP_OK) goto done;
+          if ((st = node(VW.data(), KQ, nz_l, false, &d.vw[l])) != MPIP_OK) goto done;
+          // operands of the fused node kernels between layer 1 and a last layer 2 (BF16 form)
+          d.n1_vwt[l] = d.n1_upt[l] = d.n1_up[l] = d.n1_vw[l] = nullptr;
+          if (bf && T >= 2 && (C == 64 || C == 128) && S <= 4) {
+            const float* Wu = lh[1].up[l];   // layer 2's W_up_l, [C_in][C_out]
+            auto VWq = [&](int q, int f) { return VW[(size_t)q * nz_l + f]; };
+            if ((st = pack(nz_l / 16, KQ / 32, [&](int mt, int kc, int lane, int j) {
+                   return VWq(32 * kc + 8 * (lane >> 4) + j, 16 * mt + (lane & 15));
+                 }, &d.n1_vwt[l])) != MPIP_OK) goto done;
+            if ((st = pack(C / 16, C / 32, [&](int mt, int kc, int lane, int j) {
+                   const int rho = lane & 15;
+                   const int cin = phi_bf(kc, lane >> 4, j), cout = (C / 4) * (rho / 4) + 4 * mt + rho % 4;
+                   return Wu[(size_t)cin * C + cout];
+                 }, &d.n1_upt[l])) != MPIP_OK) goto done;
+            if ((st = pack(C / 16, C / 32, [&](int mt, int kc, int lane, int j) {
+                   const int cin = 16 * mt + (lane & 15), cout = 32 * kc + 8 * (lane >> 4) + j;
+                   return Wu[(size_t)cin * C + cout];
+                 }, &d.n1_up[l])) != MPIP_OK) goto done;
+            if ((st = pack(KQ / 16, nz_l / 32, [&](int mt, int kcg, int lane, int j) {
+                   const int rho = lane & 15, b = kcg / (C / 32), kc = kcg % (C / 32);
+                   const int q = (KQ / 4) * (rho / 4) + 4 * mt + rho % 4;
+                   return VWq(q, b * C + phi_bf(kc, lane >> 4, j));
+                 }, &d.n1_vw[l])) != MPIP_OK) goto done;
+          }
         }
       }
     }
@@ -661,6 +699,16 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
     fa.w3f = d.w3fp[role]; fa.w3t = d.w3t[role]; fa.w3b = d.w3bp[role]; fa.cg = d.cg[role];
   };
   const int ht_bf16 = prec == MPIP_BF16_MIXED ? 1 : 0;
+  // two-layer evaluation with specialised first and last layers (BF16 form):
+  // the node work between them runs in the fused kernels of k_node1.hip
+  const bool node1 = ht_bf16 && K == 2 && fast_layer(1) && fast_layer(2) && LD[0].n1_vwt[0] != nullptr;
+  fa.htbar_bf16 = node1 ? 1 : 0;
+  Node1Args n1;
+  n1.n = N; n1.Q = qp; n1.P = qp; n1.h = h; n1.ht = node1 ? (void*)(w + p.o_ht[1]) : nullptr; n1.htbar = htbar;
+  n1.spec_s = b.spec_s; n1.owned_s = b.owned_s; n1.emb = m->emb; n1.w_read = m->w_read;
+  for (int l = 0; l < 3; ++l) {
+    n1.vwt[l] = LD[0].n1_vwt[l]; n1.upt[l] = LD[0].n1_upt[l]; n1.up[l] = LD[0].n1_up[l]; n1.vw[l] = LD[0].n1_vw[l];
+  }
   // element offset into an array stored in FP32, or in BF16 when bf is set
   auto at = [](float* base, int64_t elems, int bf) -> float* {
     return bf ? (float*)((uint16_t*)base + elems) : base + elems;
@@ -673,7 +721,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
     const int nout = (kind == KIND_ONLY || kind == KIND_LAST) ? 1 : nlm;
     const bool fast = fast_layer(t);
     float* ht = (t == 1) ? ht1 : (float*)(w + p.o_ht[t - 1]);
-    if (t >= 2)
+    if (t >= 2 && !node1)
       for (int l = 0; l <= L; ++l)
         gemm(h + l * l * C, (int64_t)nlm * C, C, at(ht, l * l * C, fast ? ht_bf16 : 0), (int64_t)nlm * C, C,
              N * (2 * l + 1), 2 * l + 1, C, C, C, d.up_t[l], 0, fast ? ht_bf16 : 0);
@@ -693,17 +741,27 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
       launch_edge_fwd(prec, C, L, kind, ea, s);
     }
     T.end(s);
-    if (fast && kind == KIND_FIRST)
-      for (int l = 0; l <= L; ++l)   // A_l = Q_l V_l (Q in BF16 in the BF16 form)
-        gemm(at(qp, l * l * KQ, ht_bf16), (int64_t)nlm * KQ, KQ, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1), 2 * l + 1,
-             KQ, C, KQ, d.vt[l], 0, 0, ht_bf16);
     float* z0 = (float*)(w + p.o_z0[t - 1]);
     float* zl = t < K ? (float*)(w + p.o_zl[t - 1]) : nullptr;
-    gemm(A, (int64_t)nout * C, 0, z0, nz, 0, N, 1, C, (t == K) ? C : nz, C, d.down_t[0], 0);
-    if (t < K)
+    if (node1 && t == 1) {
+      T.begin("node_fused", s);
+      launch_node1(true, C, L, S, n1, s);
+      T.end(s);
+      continue;
+    }
+    if (fast && kind == KIND_FIRST) {
+      // z_l = Q_l (V_l W_down_l) (Q in BF16 in the BF16 form); the messages are never stored
+      gemm(at(qp, 0, ht_bf16), (int64_t)nlm * KQ, 0, z0, nz, 0, N, 1, KQ, nz, KQ, d.vwt[0], 0, 0, ht_bf16);
       for (int l = 1; l <= L; ++l)
-        gemm(A + l * l * C, (int64_t)nlm * C, C, zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, N * (2 * l + 1),
-             2 * l + 1, C, C, C, d.down_t[l], 0);
+        gemm(at(qp, l * l * KQ, ht_bf16), (int64_t)nlm * KQ, KQ, zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C,
+             N * (2 * l + 1), 2 * l + 1, KQ, C, KQ, d.vwt[l], 0, 0, ht_bf16);
+    } else {
+      gemm(A, (int64_t)nout * C, 0, z0, nz, 0, N, 1, C, (t == K) ? C : nz, C, d.down_t[0], 0);
+      if (t < K)
+        for (int l = 1; l <= L; ++l)
+          gemm(A + l * l * C, (int64_t)nlm * C, C, zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, N * (2 * l + 1),
+               2 * l + 1, C, C, C, d.down_t[l], 0);
+    }
     na.z0 = z0; na.zl = zl;
     T.begin("gates", s);
     launch_gate_fwd(na, t == 1, t == K, s);
@@ -726,19 +784,33 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
     float* z0 = (float*)(w + p.o_z0[t - 1]);
     float* zl = t < K ? (float*)(w + p.o_zl[t - 1]) : nullptr;
     na.z0 = z0; na.zl = zl;
+    if (node1 && t == 1) {
+      T.begin("node_fused", s);
+      launch_node1(false, C, L, S, n1, s);
+      T.end(s);
+      T.begin("edge_bwd_t1", s);
+      set_fast(d, role);
+      launch_l1(prec, L, false, fa, s);
+      T.end(s);
+      continue;
+    }
     T.begin("gates", s);
-    launch_gate_bwd(na, t == K, (t == K && K >= 2) ? 1 : 0, s);
+    launch_gate_bwd(na, t == K, (t == K && K >= 2 && !node1) ? 1 : 0, s);
     T.end(s);
-    // Abar (in A) = zbar @ W_down^T
-    gemm(z0, nz, 0, A, (int64_t)nout * C, 0, N, 1, (t == K) ? C : nz, C, nz, d.down[0], 0);
-    if (t < K)
+    if (fast && kind == KIND_FIRST) {
+      // P_l = zbar_l (V_l W_down_l)^T (P in BF16 in the BF16 form)
+      gemm(z0, nz, 0, at(qp, 0, ht_bf16), (int64_t)nlm * KQ, 0, N, 1, nz, KQ, nz, d.vw[0], 0, ht_bf16);
       for (int l = 1; l <= L; ++l)
-        gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
-             2 * l + 1, C, C, C, d.down[l], 0);
-    if (fast && kind == KIND_FIRST)
-      for (int l = 0; l <= L; ++l)   // P_l = Abar_l V_l^T (P in BF16 in the BF16 form)
-        gemm(A + l * l * C, (int64_t)nlm * C, C, at(qp, l * l * KQ, ht_bf16), (int64_t)nlm * KQ, KQ, N * (2 * l + 1), 2 * l + 1,
-             C, KQ, C, d.v[l], 0, ht_bf16);
+        gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, at(qp, l * l * KQ, ht_bf16), (int64_t)nlm * KQ, KQ,
+             N * (2 * l + 1), 2 * l + 1, C, KQ, C, d.vw[l], 0, ht_bf16);
+    } else {
+      // Abar (in A) = zbar @ W_down^T
+      gemm(z0, nz, 0, A, (int64_t)nout * C, 0, N, 1, (t == K) ? C : nz, C, nz, d.down[0], 0);
+      if (t < K)
+        for (int l = 1; l <= L; ++l)
+          gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
+               2 * l + 1, C, C, C, d.down[l], 0);
+    }
     T.begin("edge_bwd_t" + std::to_string(t), s);
     if (fast) {
       set_fast(d, role);
@@ -758,7 +830,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
       launch_edge_bwd(prec, C, L, kind, ea, s);
     }
     T.end(s);
-    if (t >= 2)
+    if (t >= 2 && !node1)
       for (int l = 0; l <= L; ++l)
         gemm(htbar + l * l * C, (int64_t)nlm * C, C, hbar + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
              2 * l + 1, C, C, C, d.up[l], 1);

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
           for (int kc = 0; kc < O::kch(C); ++kc)
-            ab2[mt] = O::mma(O::load(a.w3b, ((pi * 4 + mt) * O::kch(C) + kc) * 64 + lane),
+            ab2[mt] = O::mma(O::ldt(a.w3b, (pi * 4 + mt) * O::kch(C) + kc, lane),
                              O::from_row(sRb + el * RS, kc, g), ab2[mt]);
         }
       });
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kc = 0; kc < O::KC64; ++kc)
-          acc = O::mma(O::load(a.w2b, (mt * O::KC64 + kc) * 64 + lane), O::from_tiles(pb2, kc), acc);
+          acc = O::mma(O::ldt(a.w2b, mt * O::KC64 + kc, lane), O::from_tiles(pb2, kc), acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
       }
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kc = 0; kc < O::KC64; ++kc)
-          acc = O::mma(O::load(a.w1b, kc * 64 + lane), O::from_tiles(pb1, kc), acc);
+          acc = O::mma(O::ldt(a.w1b, kc, lane), O::from_tiles(pb1, kc), acc);
         __syncthreads();
         if (g < 2) {
 #pragma unroll

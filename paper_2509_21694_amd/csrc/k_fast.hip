@@ -120,7 +120,7 @@ __device__ __forceinline__ void add_edge_grad(float4* g, int e, const Geo& geo, 
   float gu[3];
   sh_grad_contract(Yb, geo.u, gu);
   const float ud = gu[0] * geo.u[0] + gu[1] * geo.u[1] + gu[2] * geo.u[2];
-  const float invd = 1.0f / geo.d;
+  const float invd = __builtin_amdgcn_rcpf(geo.d);
   float4 acc = g[e];
   acc.x += dbar * geo.u[0] + (gu[0] - ud * geo.u[0]) * invd;
   acc.y += dbar * geo.u[1] + (gu[1] - ud * geo.u[1]) * invd;
@@ -144,31 +144,122 @@ __device__ __forceinline__ void mlp_backward(const f32x4* ab2, const f32x4* p1, 
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kc = 0; kc < O::KC64; ++kc)
-      acc = O::mma(O::load(w2b, (mt * O::KC64 + kc) * 64 + lane), O::from_tiles(pb2, kc), acc);
+      acc = O::mma(O::ldt(w2b, mt * O::KC64 + kc, lane), O::from_tiles(pb2, kc), acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
   }
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(O::load(w1b, kc * 64 + lane), O::from_tiles(pb1, kc), acc);
+  for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(O::ldt(w1b, kc, lane), O::from_tiles(pb1, kc), acc);
   if (g < 2) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) seb[el * kNB + 4 * g + r] = acc[r];
   }
 }
 
+// sum over the 16 lanes of each DPP row (lanes 16g .. 16g+15); every lane of
+// the row receives the total
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false);
+  return v + __int_as_float(o);
+}
+__device__ __forceinline__ float row16_sum(float v) {
+  v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141>(v);   // row_half_mirror
+  v = dpp_add<0x140>(v);   // row_mirror
+  return v;
+}
+
+// LDS written by some lanes of a wave and read by others of the same wave
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Rows of the calling wave.  Workgroups are dispatched to the 8 XCDs in
+// round-robin order, so workgroup b runs on XCD b % 8: each XCD takes a
+// contiguous eighth of the spatially sorted rows and its waves walk that
+// range side by side, so the sender rows they gather stay within one L2.
+// The grid is a multiple of 8 workgroups.
+struct RowWalk {
+  int64_t i, end, step;
+};
+template <int NW>
+__device__ __forceinline__ RowWalk row_walk(int64_t n) {
+  const int b = blockIdx.x, x = b & 7, lb = b >> 3, BX = gridDim.x >> 3;
+  const int64_t r0 = n * x / 8, r1 = n * (x + 1) / 8;
+  return {r0 + (int64_t)lb * NW + (threadIdx.x >> 6), r1, (int64_t)BX * NW};
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void stage_lds(T* dst, const void* src) {
+  const T* s = (const T*)src;
+  for (int t = threadIdx.x; t < NT; t += blockDim.x) dst[t] = s[t];
+}
+
+// remaining MLP adjoint as in mlp_backward, with dE/de of edge el returned in
+// registers of lane el (< 16)
+// remaining MLP adjoint as in mlp_backward, with dE/de of edge el returned in
+// registers of lane el (< 16); W2B, W1B in global memory or LDS
+template <int PREC, typename WT>
+__device__ __forceinline__ void mlp_backward_reg(const f32x4* ab2, const f32x4* p1, const f32x4* p2, int lane,
+                                                 const WT* W2B, const WT* W1B, float* eb) {
+  typedef Op<PREC> O;
+  f32x4 pb2[4], pb1[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pb2[mt][r] = ab2[mt][r] * dsilu(p2[mt][r]);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < O::KC64; ++kc)
+      acc = O::mma(W2B[(mt * O::KC64 + kc) * 64 + lane], O::from_tiles(pb2, kc), acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
+  }
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(W1B[kc * 64 + lane], O::from_tiles(pb1, kc), acc);
+  // D rows n = 4g + r (basis index, g < 2), column = edge: lane el takes rows 0..3 from
+  // itself and rows 4..7 from lane el + 16
+  const int src = (lane & 15) + 16;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    eb[r] = acc[r];
+    eb[4 + r] = __shfl(acc[r], src);
+  }
+}
+
 // ============================================================ first layer
 
-template <int PREC, int L, int MQ>
-__global__ __launch_bounds__(64) void k_l1_fwd(FastArgs a) {
+// Workgroups of NW waves, each wave walking its own rows (row_walk); the
+// MLP weights sit in LDS in the BF16 form.  The per-tile harmonics table is
+// exchanged between the lanes of a wave through a wave-private LDS slice.
+template <int PREC, int L, int MQ, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 1))) void k_l1_fwd(FastArgs a) {
   typedef Op<PREC> O;
   constexpr int NLM = (L + 1) * (L + 1);
-  __shared__ float syc[kTileE * NLM];
-  __shared__ int ssp[kTileE];
+  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
+  __shared__ typename O::T sM1[NM1], sM2[NM2];
+  __shared__ float sY[NW][kTileE * NLM];
+  __shared__ int sS[NW][kTileE];
   if (fast_guard(a)) return;
-  const int lane = threadIdx.x, g = lane >> 4, el = lane & 15;
+  if constexpr (PREC == 1) {
+    stage_lds<typename O::T, NM1>(sM1, a.w1a);
+    stage_lds<typename O::T, NM2>(sM2, a.w2f);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
+  float* syc = sY[wv];
+  int* ssp = sS[wv];
   const int S = a.n_species, KQ = 64 * S, MROWS = S * NLM;
-  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+  const RowWalk rw = row_walk<NW>(a.n);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
     f32x4 q[MQ][4];
 #pragma unroll
@@ -181,8 +272,7 @@ __global__ __launch_bounds__(64) void k_l1_fwd(FastArgs a) {
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
-      __syncthreads();
-      if (lane < kTileE) {
+      if (g == 0) {
         float yc[NLM];
         yc_first<L>(a.cg, geo.Y, yc);
 #pragma unroll
@@ -190,20 +280,19 @@ __global__ __launch_bounds__(64) void k_l1_fwd(FastArgs a) {
         ssp[el] = valid ? __float_as_int(v.w) : -1;
       }
       // radial MLP layer 1 (features x edges), layer 2 (edges x features)
-      f32x4 p1[4], a1[4], a2[4];
+      f32x4 a1[4], a2[4];
       {
         const f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
           f32x4 acc = z;
           if constexpr (PREC == 1) {
-            acc = O::mma(O::load(a.w1a, mt * 64 + lane), basis_op_bf16(geo.basis, g), acc);
+            acc = O::mma(sM1[mt * 64 + lane], basis_op_bf16(geo.basis, g), acc);
           } else {
 #pragma unroll
             for (int qq = 0; qq < 2; ++qq)
-              acc = O::mma(O::load(a.w1a, (mt * 2 + qq) * 64 + lane), geo.basis[4 * qq + g], acc);
+              acc = O::mma(O::ldt(a.w1a, mt * 2 + qq, lane), geo.basis[4 * qq + g], acc);
           }
-          p1[mt] = acc;
 #pragma unroll
           for (int r = 0; r < 4; ++r) a1[mt][r] = silu(acc[r]);
         }
@@ -211,13 +300,17 @@ __global__ __launch_bounds__(64) void k_l1_fwd(FastArgs a) {
         for (int nt = 0; nt < 4; ++nt) {
           f32x4 acc = z;
 #pragma unroll
-          for (int kc = 0; kc < O::KC64; ++kc)
-            acc = O::mma(O::from_tiles(a1, kc), O::load(a.w2f, (nt * O::KC64 + kc) * 64 + lane), acc);
+          for (int kc = 0; kc < O::KC64; ++kc) {
+            typename O::T w;
+            if constexpr (PREC == 1) w = sM2[(nt * O::KC64 + kc) * 64 + lane];
+            else w = O::ldt(a.w2f, nt * O::KC64 + kc, lane);
+            acc = O::mma(O::from_tiles(a1, kc), w, acc);
+          }
 #pragma unroll
           for (int r = 0; r < 4; ++r) a2[nt][r] = silu(acc[r]);
         }
       }
-      __syncthreads();
+      wave_lds_sync();
       // Q^T[(s,lm), k] += sum_e Ysel[e, (s,lm)] a2[e, k]; a2 tile nt: edges 4g + r, hidden 16 nt + el
 #pragma unroll
       for (int mt = 0; mt < MQ; ++mt) {
@@ -243,7 +336,7 @@ __global__ __launch_bounds__(64) void k_l1_fwd(FastArgs a) {
             for (int r = 0; r < 4; ++r) q[mt][nt] = mfma_f32(ys[r], a2[nt][r], q[mt][nt]);
         }
       }
-      (void)p1;
+      wave_lds_sync();
     }
     // Q_i[lm][s*64 + k]: D rows (s,lm) = 16 mt + 4 g + r, hidden k = 16 nt + el
 #pragma unroll
@@ -268,17 +361,28 @@ __global__ __launch_bounds__(64) void k_l1_fwd(FastArgs a) {
   }
 }
 
-template <int PREC, int L, int MQ>
-__global__ __launch_bounds__(64) void k_l1_bwd(FastArgs a) {
+template <int PREC, int L, int MQ, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 2 : 1))) void k_l1_bwd(FastArgs a) {
   typedef Op<PREC> O;
   constexpr int NLM = (L + 1) * (L + 1);
   constexpr int KCQ = (PREC == 1) ? (MQ + 1) / 2 : 4 * MQ;   // k-chunks over the (s,lm) rows
-  __shared__ float syb[kTileE * 16 * MQ];
-  __shared__ float seb[kTileE * kNB];
+  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
+  constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
+  __shared__ typename O::T sM1[NM1], sM2[NM2], sB2[NB2], sB1[NB1];
+  __shared__ float sYB[NW][kTileE * 16 * MQ];
   if (fast_guard(a)) return;
-  const int lane = threadIdx.x, g = lane >> 4, el = lane & 15;
+  if constexpr (PREC == 1) {
+    stage_lds<typename O::T, NM1>(sM1, a.w1a);
+    stage_lds<typename O::T, NM2>(sM2, a.w2a);
+    stage_lds<typename O::T, NB2>(sB2, a.w2b);
+    stage_lds<typename O::T, NB1>(sB1, a.w1b);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
+  float* syb = sYB[wv];
   const int S = a.n_species, KQ = 64 * S, MROWS = S * NLM;
-  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+  const RowWalk rw = row_walk<NW>(a.n);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
     const float* Pi = a.P + (int64_t)i * NLM * KQ;
     const __bf16* Pbi = (const __bf16*)a.P + (int64_t)i * NLM * KQ;
@@ -325,7 +429,8 @@ __global__ __launch_bounds__(64) void k_l1_bwd(FastArgs a) {
       float yc[NLM];
       yc_first<L>(a.cg, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4], ab2[4];
-      mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
+      if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
+      else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -356,7 +461,6 @@ __global__ __launch_bounds__(64) void k_l1_bwd(FastArgs a) {
         for (int kc = 0; kc < KCQ; ++kc) acc = O::mma(pa[mt][kc], yb[kc], acc);
         ab2[mt] = acc;
       }
-      __syncthreads();
 #pragma unroll
       for (int mq = 0; mq < MQ; ++mq) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -365,8 +469,10 @@ __global__ __launch_bounds__(64) void k_l1_bwd(FastArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) syb[el * (16 * MQ) + 16 * mq + 4 * g + r] = acc[r];
       }
-      mlp_backward<PREC>(ab2, p1, p2, lane, a.w2b, a.w1b, seb);
-      __syncthreads();
+      float eb[kNB];
+      if constexpr (PREC == 1) mlp_backward_reg<PREC>(ab2, p1, p2, lane, sB2, sB1, eb);
+      else mlp_backward_reg<PREC>(ab2, p1, p2, lane, (const typename O::T*)a.w2b, (const typename O::T*)a.w1b, eb);
+      wave_lds_sync();
       if (lane < kTileE && valid) {
         float ycb[NLM], Yb[kMaxNlm];
 #pragma unroll
@@ -374,8 +480,9 @@ __global__ __launch_bounds__(64) void k_l1_bwd(FastArgs a) {
 #pragma unroll
         for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * (16 * MQ) + sp * NLM + k];
         yc_first_adj<L>(a.cg, ycb, Yb);
-        add_edge_grad(a.g, e, geo, seb + el * kNB, Yb);
+        add_edge_grad(a.g, e, geo, eb, Yb);
       }
+      wave_lds_sync();
     }
   }
 }
@@ -416,49 +523,6 @@ template <> struct HT<0> {
     }
   }
 };
-
-// sum over the 16 lanes of each DPP row (lanes 16g .. 16g+15); every lane of
-// the row receives the total
-template <int CTRL>
-__device__ __forceinline__ float dpp_add(float v) {
-  const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false);
-  return v + __int_as_float(o);
-}
-__device__ __forceinline__ float row16_sum(float v) {
-  v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
-  v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
-  v = dpp_add<0x141>(v);   // row_half_mirror
-  v = dpp_add<0x140>(v);   // row_mirror
-  return v;
-}
-
-// LDS written by some lanes of a wave and read by others of the same wave
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Rows of the calling wave.  Workgroups are dispatched to the 8 XCDs in
-// round-robin order, so workgroup b runs on XCD b % 8: each XCD takes a
-// contiguous eighth of the spatially sorted rows and its waves walk that
-// range side by side, so the sender rows they gather stay within one L2.
-// The grid is a multiple of 8 workgroups.
-struct RowWalk {
-  int64_t i, end, step;
-};
-template <int NW>
-__device__ __forceinline__ RowWalk row_walk(int64_t n) {
-  const int b = blockIdx.x, x = b & 7, lb = b >> 3, BX = gridDim.x >> 3;
-  const int64_t r0 = n * x / 8, r1 = n * (x + 1) / 8;
-  return {r0 + (int64_t)lb * NW + (threadIdx.x >> 6), r1, (int64_t)BX * NW};
-}
-
-template <typename T, int NT>
-__device__ __forceinline__ void stage_lds(T* dst, const void* src) {
-  const T* s = (const T*)src;
-  for (int t = threadIdx.x; t < NT; t += blockDim.x) dst[t] = s[t];
-}
 
 // one gathered 8-channel piece of a sender row, kept packed until use
 template <int PREC> struct HRaw;
@@ -510,10 +574,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NLM = (L + 1) * (L + 1);
   constexpr int CB = C / 4, NK = CB / 8, CN = C / 16, NCH = (L + 1) * NK;
   constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
+  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
+  __shared__ typename O::T sM1[NM1], sM2[NM2];
   __shared__ typename O::T sW[NWT];
   if (fast_guard(a)) return;
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3t);
+    stage_lds<typename O::T, NM1>(sM1, a.w1a);
+    stage_lds<typename O::T, NM2>(sM2, a.w2a);
     __syncthreads();
   }
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
@@ -548,7 +616,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       float yc[NLM];
       yc_last<L>(a.cg, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4];
-      mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
+      if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
+      else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -569,7 +638,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
           for (int kc = 0; kc < O::KC64; ++kc) {
             typename O::T wv;
             if constexpr (PREC == 1) wv = cur.w[hh][kc];
-            else wv = O::load(a.w3t, ((l * CN + 2 * k + hh) * O::KC64 + kc) * 64 + lane);
+            else wv = O::ldt(a.w3t, (l * CN + 2 * k + hh) * O::KC64 + kc, lane);
             d = O::mma(wv, bop[kc], d);
           }
 #pragma unroll
@@ -600,39 +669,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   }
 }
 
-// remaining MLP adjoint as in mlp_backward, with dE/de of edge el returned in
-// registers of lane el (< 16)
-template <int PREC>
-__device__ __forceinline__ void mlp_backward_reg(const f32x4* ab2, const f32x4* p1, const f32x4* p2, int lane,
-                                                 const void* w2b, const void* w1b, float* eb) {
-  typedef Op<PREC> O;
-  f32x4 pb2[4], pb1[4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pb2[mt][r] = ab2[mt][r] * dsilu(p2[mt][r]);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kc = 0; kc < O::KC64; ++kc)
-      acc = O::mma(O::load(w2b, (mt * O::KC64 + kc) * 64 + lane), O::from_tiles(pb2, kc), acc);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
-  }
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(O::load(w1b, kc * 64 + lane), O::from_tiles(pb1, kc), acc);
-  // D rows n = 4g + r (basis index, g < 2), column = edge: lane el takes rows 0..3 from
-  // itself and rows 4..7 from lane el + 16
-  const int src = (lane & 15) + 16;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    eb[r] = acc[r];
-    eb[4 + r] = __shfl(acc[r], src);
-  }
-}
-
 // adjoint a: per edge dR, dE/dY and the MLP adjoint, in the layout and chunk
 // order of the forward kernel (W3 and its adjoint operands in LDS in the BF16 form)
 template <int PREC, int C, int L, int NW>
@@ -644,12 +680,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int KCC = O::kch(C);             // k-chunks over channels (MLP adjoint)
   constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
   constexpr int NWB = (PREC == 1) ? (L + 1) * 4 * KCC * 64 : 1;
+  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
+  __shared__ typename O::T sM1[NM1], sM2[NM2];
   __shared__ typename O::T sW[NWT];
   __shared__ typename O::T sWB[NWB];
+  constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
+  __shared__ typename O::T sB2[NB2], sB1[NB1];
   if (fast_guard(a)) return;
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3t);
     stage_lds<typename O::T, NWB>(sWB, a.w3b);
+    stage_lds<typename O::T, NM1>(sM1, a.w1a);
+    stage_lds<typename O::T, NM2>(sM2, a.w2a);
+    stage_lds<typename O::T, NB2>(sB2, a.w2b);
+    stage_lds<typename O::T, NB1>(sB1, a.w1b);
     __syncthreads();
   }
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
@@ -686,7 +730,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       float yc[NLM];
       yc_last<L>(a.cg, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4], ab2[4];
-      mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
+      if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
+      else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -710,7 +755,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
           for (int kc = 0; kc < O::KC64; ++kc) {
             typename O::T wv;
             if constexpr (PREC == 1) wv = cur.w[hh][kc];
-            else wv = O::load(a.w3t, ((l * CN + 2 * k + hh) * O::KC64 + kc) * 64 + lane);
+            else wv = O::ldt(a.w3t, (l * CN + 2 * k + hh) * O::KC64 + kc, lane);
             d = O::mma(wv, bop[kc], d);
           }
 #pragma unroll
@@ -743,7 +788,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
           } else {
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-              ab2[mt] = O::mma(O::load(a.w3b, ((l * 4 + mt) * KCC + 8 * k + q) * 64 + lane), rb[q], ab2[mt]);
+              ab2[mt] = O::mma(O::ldt(a.w3b, (l * 4 + mt) * KCC + 8 * k + q, lane), rb[q], ab2[mt]);
           }
         }
       });
@@ -756,7 +801,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         ycb[k] = w;
       }
       float eb[kNB];
-      mlp_backward_reg<PREC>(ab2, p1, p2, lane, a.w2b, a.w1b, eb);
+      if constexpr (PREC == 1) mlp_backward_reg<PREC>(ab2, p1, p2, lane, sB2, sB1, eb);
+      else mlp_backward_reg<PREC>(ab2, p1, p2, lane, (const typename O::T*)a.w2b, (const typename O::T*)a.w1b, eb);
       if (lane < kTileE && valid) {
         float Yb[kMaxNlm];
 #pragma unroll
@@ -779,11 +825,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NLM = (L + 1) * (L + 1);
   constexpr int CN = C / 16;
   constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
+  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
+  __shared__ typename O::T sM1[NM1], sM2[NM2];
   __shared__ typename O::T sW[NWT];
   __shared__ float sY[NW][kTileE * 16];
   if (fast_guard(a)) return;
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3f);
+    stage_lds<typename O::T, NM1>(sM1, a.w1a);
+    stage_lds<typename O::T, NM2>(sM2, a.w2a);
     __syncthreads();
   }
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
@@ -824,7 +874,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         }
       }
       f32x4 p1[4], p2[4], a2[4];
-      mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
+      if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
+      else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -851,7 +902,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
           for (int kc = 0; kc < O::KC64; ++kc) {
             typename O::T wv2;
             if constexpr (PREC == 1) wv2 = sW[((l * CN + nt) * O::KC64 + kc) * 64 + lane];
-            else wv2 = O::load(a.w3f, ((l * CN + nt) * O::KC64 + kc) * 64 + lane);
+            else wv2 = O::ldt(a.w3f, (l * CN + nt) * O::KC64 + kc, lane);
             d = O::mma(aop[kc], wv2, d);
           }
           float u[4];
@@ -873,10 +924,21 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
     for (int r = 0; r < 4; ++r) {
       const int lm = 4 * g + r;
       if (lm < NLM) {
-        float* dst = a.htbar + ((int64_t)i * NLM + lm) * C + CN * el;
+        const int64_t o = ((int64_t)i * NLM + lm) * C + CN * el;
+        if (PREC == 1 && a.htbar_bf16) {
+          __bf16* dst = (__bf16*)a.htbar + o;
 #pragma unroll
-        for (int t = 0; t < CN; t += 4)
-          *(float4*)(dst + t) = make_float4(hb[t][r], hb[t + 1][r], hb[t + 2][r], hb[t + 3][r]);
+          for (int t = 0; t < CN; t += 4) {
+            typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+            const bf16x4 v = {(__bf16)hb[t][r], (__bf16)hb[t + 1][r], (__bf16)hb[t + 2][r], (__bf16)hb[t + 3][r]};
+            *(bf16x4*)(dst + t) = v;
+          }
+        } else {
+          float* dst = a.htbar + o;
+#pragma unroll
+          for (int t = 0; t < CN; t += 4)
+            *(float4*)(dst + t) = make_float4(hb[t][r], hb[t + 1][r], hb[t + 2][r], hb[t + 3][r]);
+        }
       }
     }
   }
@@ -884,17 +946,23 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 
 // ============================================================ dispatch
 
-static int fast_grid(int64_t n) {
-  int64_t g = n < 262144 ? n : 262144;
-  return (int)(g < 1 ? 1 : g);
+
+// persistent grids: a multiple of 8 workgroups (one row range per XCD), at
+// most `per_xcd` workgroups per XCD and none without rows
+static int l2_grid(int64_t n, int nw, int per_xcd) {
+  const int64_t need = (n / 8 + nw - 1) / nw;
+  const int64_t per = need < 1 ? 1 : (need < per_xcd ? need : per_xcd);
+  return (int)(8 * per);
 }
 
 template <int PREC, int L>
 static void l1_launch(bool fwd, int mq, const FastArgs& a, hipStream_t s) {
-  const int gr = fast_grid(a.n);
-#define MPIP_L1(MQ)                                                       \
-  if (fwd) k_l1_fwd<PREC, L, MQ><<<gr, 64, 0, s>>>(a);                      \
-  else k_l1_bwd<PREC, L, MQ><<<gr, 64, 0, s>>>(a);
+  // 4 waves per workgroup; forward 3 waves per SIMD, adjoint 2
+  constexpr int NW = 4;
+  const int gf = l2_grid(a.n, NW, PREC == 1 ? 96 : 128), gb = l2_grid(a.n, NW, PREC == 1 ? 64 : 128);
+#define MPIP_L1(MQ)                                                        \
+  if (fwd) k_l1_fwd<PREC, L, MQ, NW><<<gf, 64 * NW, 0, s>>>(a);              \
+  else k_l1_bwd<PREC, L, MQ, NW><<<gb, 64 * NW, 0, s>>>(a);
   switch (mq) {
     case 1: MPIP_L1(1) break;
     case 2: MPIP_L1(2) break;
@@ -914,22 +982,15 @@ void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s) {
   }
 }
 
-// persistent grids: a multiple of 8 workgroups (one row range per XCD), at
-// most `per_xcd` workgroups per XCD and none without rows
-static int l2_grid(int64_t n, int nw, int per_xcd) {
-  const int64_t need = (n / 8 + nw - 1) / nw;
-  const int64_t per = need < 1 ? 1 : (need < per_xcd ? need : per_xcd);
-  return (int)(8 * per);
-}
-
 template <int PREC, int C, int L>
 static void l2_launch(int which, const FastArgs& a, hipStream_t s) {
-  // BF16 form: W3 staged in LDS ((L+1) C 128 B for the forward and the pull,
-  // twice that for adjoint a); forward and pull run 3 waves per SIMD (3
-  // workgroups of 4 waves per CU), adjoint a 2 (one workgroup of 8 waves for
-  // 128 channels, two of 4 for 64).  FP32 form: weights from memory.
-  constexpr int NWF = 4, NWA = (PREC == 1 && C == 128) ? 8 : 4;
-  const int pf = PREC == 1 ? 96 : 128, pa = PREC == 1 ? (NWA == 8 ? 32 : 64) : 128;
+  // BF16 form: W3 and the MLP weights staged in LDS (forward and pull:
+  // (L+1) C 128 B + 12 KB; adjoint a: twice the W3 part + 22 KB).  Forward
+  // and pull run 3 waves per SIMD as 2 workgroups of 6 waves per CU; adjoint
+  // a runs 2 waves per SIMD (one workgroup of 8 waves for 128 channels, two
+  // of 4 for 64).  FP32 form: weights from memory.
+  constexpr int NWF = PREC == 1 ? 6 : 4, NWA = (PREC == 1 && C == 128) ? 8 : 4;
+  const int pf = PREC == 1 ? 64 : 128, pa = PREC == 1 ? (NWA == 8 ? 32 : 64) : 128;
   if (which == 0) k_l2_fwd<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
   else if (which == 1) k_l2_bwd_a<PREC, C, L, NWA><<<l2_grid(a.n, NWA, pa), 64 * NWA, 0, s>>>(a);
   else k_l2_bwd_b<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);

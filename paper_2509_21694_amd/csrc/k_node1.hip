@@ -1,0 +1,286 @@
+// Fused node-side kernels between a species-factorised first layer and the
+// last layer of a two-layer evaluation (BF16 form).
+//
+// Forward: z_l = Q_l (V_l W_down_l) (the first layer's down projection
+// folded into the factorised messages), the gates, and the last layer's
+// up projection h~ = h W_up, per tile of 16 atoms with every intermediate
+// in registers; only h_0 (FP32, the residual and readout input) and h~
+// (BF16, the last layer's gathered features) are written.
+// Adjoint: hbar_l = h~bar_l W_up_l^T (+ w_read on root scalars), the gate
+// adjoint with z recomputed from Q, and P_l = zbar_l (V_l W_down_l)^T, in
+// the same tiles; only P (BF16) is written, over Q's rows of the same atoms.
+//
+// Orientation: every product is computed transposed (features x atoms), so a
+// D tile's rows are features and one lane column is one atom; the rows of a
+// D tile become the k operand of the next product through the same
+// permutation as the radial MLP (k-slot (g, j) of chunk kc = row
+// 16 (2 kc + j/4) + 4 g + j%4), so no data leaves the registers between the
+// stages.
+#include <utility>
+
+#include "kernels.h"
+
+namespace mpip {
+
+namespace {
+
+__device__ __forceinline__ bf16x8 tiles_to_op(const f32x4* t, int kc) {
+  bf16x8 v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = (__bf16)t[2 * kc + j / 4][j % 4];
+  return v;
+}
+
+// 8 values of a lane's contiguous output run as one 16-byte BF16 store
+__device__ __forceinline__ void store8_bf16(__bf16* dst, const float* v) {
+  bf16x8 o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o[j] = (__bf16)v[j];
+  *(bf16x8*)dst = o;
+}
+
+// operand tile `tile` of a packed weight array: a uniform base plus a 32-bit
+// lane offset, so the address needs no per-lane 64-bit register
+__device__ __forceinline__ bf16x8 wtile(const bf16x8* W, int tile, int lane) {
+  const bf16x8* b = W + (size_t)tile * 64;
+  asm volatile("" : "+s"(b));   // keep the tile base scalar and computed at its use
+  return *(const bf16x8*)((const char*)b + (unsigned)lane * 16u);
+}
+
+template <typename F, int... Is>
+__device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+
+// D tiles mt = 0..MT-1 of W x B with W given as A-operand tiles
+// W[(mt0 + mt) * KS + k0 + kc] (kc < KC) and B as KC operands; the weights
+// are streamed from memory one M-tile ahead of their use and each finished
+// tile is handed to consume(mt, d), so only two tiles of weights are live.
+template <int MT, int KC, typename F>
+__device__ __forceinline__ void stream_rows(const bf16x8* W, int mt0, int KS, int k0, const bf16x8* B, int lane,
+                                           F&& consume) {
+  bf16x8 wb[2][KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) wb[0][kc] = wtile(W, mt0 * KS + k0 + kc, lane);
+  unroll_impl([&](auto mc) {
+    constexpr int mt = decltype(mc)::value;
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (mt + 1 < MT) {
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) wb[(mt + 1) & 1][kc] = wtile(W, (mt0 + mt + 1) * KS + k0 + kc, lane);
+    }
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) d = mfma_bf16(wb[mt & 1][kc], B[kc], d);
+    consume(mt, d);
+  }, std::make_integer_sequence<int, MT>{});
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+}  // namespace
+
+// a lane's output run, written two D tiles (8 values) at a time as one 16-byte BF16 store
+struct PairStore {
+  float v[4];
+  __device__ __forceinline__ void put(int mt, const f32x4& d, __bf16* base) {
+    if (mt & 1) {
+      const float o[8] = {v[0], v[1], v[2], v[3], d[0], d[1], d[2], d[3]};
+      store8_bf16(base + 4 * (mt - 1), o);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = d[r];
+    }
+  }
+};
+
+template <int C, int L, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_node1_fwd(Node1Args a) {
+  constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, KCQ = KQ / 32, MTC = C / 16, KCC = C / 32;
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  const int64_t a0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (a0 >= a.n) return;
+  const bool av = a0 + n < a.n;
+  const int64_t at = av ? a0 + n : a.n - 1;
+  const bf16x8* Q = (const bf16x8*)a.Q;   // [N][NLM][KQ / 8]
+  const bf16x8* VT0 = (const bf16x8*)a.vwt[0];
+  const int sp = a.spec_s[at];
+  auto qload = [&](int lm, bf16x8* qv) {
+#pragma unroll
+    for (int kc = 0; kc < KCQ; ++kc) qv[kc] = Q[((int64_t)at * NLM + lm) * (KQ / 8) + 4 * kc + g];
+  };
+  // h~ rows of one (l, m): D tile mt, lane (g, n) holds output channel (C/4) g + 4 mt + r
+  auto up_store = [&](int l, int lm, const f32x4* h) {
+    const bf16x8* U = (const bf16x8*)a.upt[l];
+    bf16x8 hb[KCC];
+#pragma unroll
+    for (int kc = 0; kc < KCC; ++kc) hb[kc] = tiles_to_op(h, kc);
+    __bf16* dst = (__bf16*)a.ht + ((int64_t)at * NLM + lm) * C + (C / 4) * g;
+    PairStore ps;
+    stream_rows<MTC, KCC>(U, 0, KCC, 0, hb, lane, [&](int mt, f32x4 d) {
+      if (av) ps.put(mt, d, dst);
+    });
+  };
+  // scalars: h_0 = emb + SiLU(z_0[0:C])
+  {
+    bf16x8 q0[KCQ];
+    qload(0, q0);
+    f32x4 z[MTC];
+    stream_rows<MTC, KCQ>(VT0, 0, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
+      const float4 e = *(const float4*)(a.emb + (int64_t)sp * C + 16 * mt + 4 * g);
+      const float ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[mt][r] = ev[r] + silu(d[r]);
+      if (av) *(float4*)(a.h + (int64_t)at * NLM * C + 16 * mt + 4 * g) = make_float4(z[mt][0], z[mt][1], z[mt][2], z[mt][3]);
+    });
+    up_store(0, 0, z);
+  }
+  // degrees l >= 1: h_lm = sigmoid(z_0[gate block l]) * z_lm
+#pragma unroll
+  for (int l = 1; l <= L; ++l) {
+    f32x4 gt[MTC];
+    {
+      bf16x8 q0[KCQ];
+      qload(0, q0);
+      stream_rows<MTC, KCQ>(VT0, l * MTC, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gt[mt][r] = sigm(d[r]);
+      });
+    }
+    const bf16x8* VT = (const bf16x8*)a.vwt[l];
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      const int lm = l * l + m;
+      bf16x8 ql[KCQ];
+      qload(lm, ql);
+      f32x4 z[MTC];
+      stream_rows<MTC, KCQ>(VT, 0, KCQ, 0, ql, lane, [&](int mt, f32x4 d) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[mt][r] = gt[mt][r] * d[r];
+      });
+      up_store(l, lm, z);
+    }
+  }
+}
+
+template <int C, int L, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_node1_bwd(Node1Args a) {
+  constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, KCQ = KQ / 32, MTC = C / 16, KCC = C / 32;
+  constexpr int MTP = KQ / 16, NZC = (1 + L) * KCC;   // P row tiles; k-chunks of z_0
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  const int64_t a0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (a0 >= a.n) return;
+  const bool av = a0 + n < a.n;
+  const int64_t at = av ? a0 + n : a.n - 1;
+  const bf16x8* Q = (const bf16x8*)a.Q;
+  const bf16x8* HB = (const bf16x8*)a.htbar;   // [N][NLM][C / 8]
+  const bf16x8* VT0 = (const bf16x8*)a.vwt[0];
+  const bf16x8* VW0 = (const bf16x8*)a.vw[0];
+  const bool own = a.owned_s[at] != 0;
+  auto qload = [&](int lm, bf16x8* qv) {
+#pragma unroll
+    for (int kc = 0; kc < KCQ; ++kc) qv[kc] = Q[((int64_t)at * NLM + lm) * (KQ / 8) + 4 * kc + g];
+  };
+  // hbar rows of one (l, m): W_up_l h~bar_lm^T, channel 16 mt + 4 g + r (the positions of z)
+  auto hbar_row = [&](int l, int lm, f32x4* hb) {
+    const bf16x8* U = (const bf16x8*)a.up[l];
+    bf16x8 hv[KCC];
+#pragma unroll
+    for (int kc = 0; kc < KCC; ++kc) hv[kc] = HB[((int64_t)at * NLM + lm) * (C / 8) + 4 * kc + g];
+    stream_rows<MTC, KCC>(U, 0, KCC, 0, hv, lane, [&](int mt, f32x4 d) { hb[mt] = d; });
+  };
+  // P rows: D tile mt, lane (g, n) holds P index (KQ/4) g + 4 mt + r
+  auto pdst = [&](int lm) { return (__bf16*)a.P + ((int64_t)at * NLM + lm) * KQ + (KQ / 4) * g; };
+  // zbar_0 blocks as B operands (scalars, then one gate block per l); P_0 is
+  // formed from them at the end, after the last read of Q_0 (P overwrites Q)
+  bf16x8 z0b[(1 + L) * KCC];
+  // scalars: zbar_0[0:C] = hbar_0 * SiLU'(z_0[0:C]), hbar_0 = w_read (root atoms) + W_up_0 h~bar_0
+  {
+    f32x4 hb[MTC];
+    hbar_row(0, 0, hb);
+    bf16x8 q0[KCQ];
+    qload(0, q0);
+    stream_rows<MTC, KCQ>(VT0, 0, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
+      const float4 w = *(const float4*)(a.w_read + 16 * mt + 4 * g);
+      const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) hb[mt][r] = (hb[mt][r] + (own ? wv[r] : 0.f)) * dsilu(d[r]);
+    });
+#pragma unroll
+    for (int kc = 0; kc < KCC; ++kc) z0b[kc] = tiles_to_op(hb, kc);
+  }
+#pragma unroll
+  for (int l = 1; l <= L; ++l) {
+    f32x4 s[MTC], dg[MTC];
+    {
+      bf16x8 q0[KCQ];
+      qload(0, q0);
+      stream_rows<MTC, KCQ>(VT0, l * MTC, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { s[mt][r] = sigm(d[r]); dg[mt][r] = 0.f; }
+      });
+    }
+    const bf16x8* VT = (const bf16x8*)a.vwt[l];
+    const bf16x8* VW = (const bf16x8*)a.vw[l];
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      const int lm = l * l + m;
+      f32x4 hb[MTC];
+      hbar_row(l, lm, hb);
+      bf16x8 ql[KCQ];
+      qload(lm, ql);
+      // z_lm consumed tile by tile: dgate += hbar z, zbar_lm = hbar sigmoid(gate) (in hb)
+      stream_rows<MTC, KCQ>(VT, 0, KCQ, 0, ql, lane, [&](int mt, f32x4 d) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          dg[mt][r] += hb[mt][r] * d[r];
+          hb[mt][r] *= s[mt][r];
+        }
+      });
+      bf16x8 zb[KCC];
+#pragma unroll
+      for (int kc = 0; kc < KCC; ++kc) zb[kc] = tiles_to_op(hb, kc);
+      __bf16* dst = pdst(lm);
+      PairStore ps;
+      stream_rows<MTP, KCC>(VW, 0, KCC, 0, zb, lane, [&](int mt, f32x4 d) {
+        if (av) ps.put(mt, d, dst);
+      });
+    }
+    // zbar of the gate block l: sum_m hbar_lm z_lm * sigmoid'
+#pragma unroll
+    for (int mt = 0; mt < MTC; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dg[mt][r] *= s[mt][r] * (1.f - s[mt][r]);
+#pragma unroll
+    for (int kc = 0; kc < KCC; ++kc) z0b[l * KCC + kc] = tiles_to_op(dg, kc);
+  }
+  {
+    __bf16* dst = pdst(0);
+    PairStore ps;
+    stream_rows<MTP, NZC>(VW0, 0, NZC, 0, z0b, lane, [&](int mt, f32x4 d) {
+      if (av) ps.put(mt, d, dst);
+    });
+  }
+}
+
+template <int C, int L>
+static void node1_c(bool fwd, int S, const Node1Args& a, hipStream_t s) {
+  const unsigned grid = (unsigned)((a.n + 63) / 64);
+#define MPIP_N1(SS)                                                       \
+  if (fwd) k_node1_fwd<C, L, SS><<<grid, 256, 0, s>>>(a);                 \
+  else k_node1_bwd<C, L, SS><<<grid, 256, 0, s>>>(a);
+  switch (S) {
+    case 1: MPIP_N1(1) break;
+    case 2: MPIP_N1(2) break;
+    case 3: MPIP_N1(3) break;
+    default: MPIP_N1(4) break;
+  }
+#undef MPIP_N1
+}
+
+void launch_node1(bool fwd, int C, int L, int S, const Node1Args& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  if (C == 64 && L == 1) node1_c<64, 1>(fwd, S, a, s);
+  else if (C == 64) node1_c<64, 2>(fwd, S, a, s);
+  else if (L == 1) node1_c<128, 1>(fwd, S, a, s);
+  else node1_c<128, 2>(fwd, S, a, s);
+}
+
+}  // namespace mpip

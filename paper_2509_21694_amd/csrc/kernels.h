@@ -77,7 +77,34 @@ struct LayerDev {
   // first layer, species factorisation: V_l[(s,k)][c] = ht1[s][c] W3[k][(l,c)] / n_avg
   const void* vt[3];     // [C][S*64]  (A = Q V)
   const void* v[3];      // [S*64][C]  (P = dA V^T)
+  // V_l folded with the down projection: z_l = Q_l (V_l W_down_l), P_l = zbar_l (V_l W_down_l)^T
+  const void* vwt[3];    // [Nz_l][S*64]  (Nz_0 = C(1+L), Nz_l = C)
+  const void* vw[3];     // [S*64][Nz_l]
+  // fused node kernels between the first and a last second layer (BF16 form,
+  // k_node1.hip), all as MFMA A operands [row tile][k chunk][64 lanes][8]:
+  const void* n1_vwt[3];   // (V_l W_down_l)^T: rows z features, k = (s, k) in order
+  const void* n1_upt[3];   // next layer's W_up_l^T: rows output channel (C/4)(r/4) + 4 mt + r%4, k permuted
+  const void* n1_up[3];    // next layer's W_up_l: rows channel, k = channel in order
+  const void* n1_vw[3];    // V_l W_down_l: rows (s, k) as (S*16)(r/4) + 4 mt + r%4, k = z feature permuted per C block
 };
+
+struct Node1Args {
+  int64_t n;
+  const void* Q;          // [N][nlm][64 S] bf16 (forward input; adjoint: recompute of z)
+  void* P;                // [N][nlm][64 S] bf16 (adjoint output, may alias Q)
+  float* h;               // [N][nlm][C]: forward writes h_0 (l = 0 rows) only
+  void* ht;               // [N][nlm][C] bf16: next layer's h~ (forward output)
+  const void* htbar;      // [N][nlm][C] bf16: next layer's h~bar (adjoint input)
+  const int32_t* spec_s;
+  const uint8_t* owned_s;
+  const float* emb;       // [S][C]
+  const float* w_read;    // [C]
+  const void* vwt[3];
+  const void* upt[3];
+  const void* up[3];
+  const void* vw[3];
+};
+void launch_node1(bool fwd, int C, int L, int S, const Node1Args& a, hipStream_t s);
 
 struct FastArgs {
   int64_t n;
@@ -105,6 +132,7 @@ struct FastArgs {
   float* A;              // last layer forward: [N][C]
   const float* Abar;     // last layer adjoint input: [N][C]
   float* htbar;          // last layer adjoint output: [N][nlm][C]
+  int htbar_bf16;        // 1: htbar stored as bf16 (same element offsets)
   float4* g;
 };
 
