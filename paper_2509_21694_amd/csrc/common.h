@@ -30,7 +30,8 @@ struct GridParams {
   int img[3];          // periodic dims with fewer than 3 bins: images -img..img
   int stencil[3];      // 1: use -1..1 neighbour bins, 0: single bin + image loop
   int nbins;
-  int pad;
+  int mbits[3];        // bits per dimension of the bins' space-filling-curve rank
+  int nrank;           // size of the rank space, 2^(mbits[0]+mbits[1]+mbits[2])
 };
 
 // ---- MFMA wrappers (16x16 output tile, 64 lanes) --------------------------

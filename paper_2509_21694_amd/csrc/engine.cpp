@@ -457,7 +457,7 @@ namespace {
 
 struct Plan {
   size_t total = 0;
-  size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_scan, o_info, o_perm, o_iperm, o_pos,
+  size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_rcount, o_rstart, o_scan, o_info, o_perm, o_iperm, o_pos,
       o_info_s, o_spec, o_owned, o_cnt, o_row, o_esrc, o_eshift, o_evec, o_erev, o_g;
   size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
   size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
@@ -482,7 +482,9 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
   p.o_bcount = take(cur, sizeof(int32_t) * (p.max_bins + 1));
   p.o_bcursor = take(cur, sizeof(int32_t) * (p.max_bins + 1));
   p.o_bstart = take(cur, sizeof(int32_t) * (p.max_bins + 1));
-  p.o_scan = take(cur, sizeof(int32_t) * scan_tmp_elems(std::max<int64_t>(N, p.max_bins) + 1));
+  p.o_rcount = take(cur, sizeof(int32_t) * (8 * (int64_t)p.max_bins + 1));
+  p.o_rstart = take(cur, sizeof(int32_t) * (8 * (int64_t)p.max_bins + 1));
+  p.o_scan = take(cur, sizeof(int32_t) * scan_tmp_elems(std::max<int64_t>(N, 8 * (int64_t)p.max_bins) + 1));
   p.o_info = take(cur, sizeof(int4) * N);
   p.o_perm = take(cur, sizeof(int32_t) * N);
   p.o_iperm = take(cur, sizeof(int32_t) * N);
@@ -551,6 +553,8 @@ NbrBuffers nbr_buffers(char* ws, const Plan& p) {
   b.bin_count = (int32_t*)(ws + p.o_bcount);
   b.bin_cursor = (int32_t*)(ws + p.o_bcursor);
   b.bin_start = (int32_t*)(ws + p.o_bstart);
+  b.rank_count = (int32_t*)(ws + p.o_rcount);
+  b.rank_start = (int32_t*)(ws + p.o_rstart);
   b.scan_tmp = (int32_t*)(ws + p.o_scan);
   b.info = (int4*)(ws + p.o_info);
   b.perm = (int32_t*)(ws + p.o_perm);

@@ -177,7 +177,14 @@ __global__ void k_grid(const double* __restrict__ part, int nparts, CellInfo ci,
     }
   }
   g.nbins = g.nb[0] * g.nb[1] * g.nb[2];
-  g.pad = 0;
+  int tot = 0;
+  for (int d = 0; d < 3; ++d) {
+    int bits = 0;
+    while ((1 << bits) < g.nb[d]) ++bits;
+    g.mbits[d] = bits;
+    tot += bits;
+  }
+  g.nrank = 1 << tot;
   *gp = g;
   (void)status;
 }
@@ -211,6 +218,41 @@ __global__ void k_bin_assign(const double* __restrict__ pos, int64_t n, CellInfo
   atomicAdd(&bin_count[bin], 1);
 }
 
+// Position of a bin on a Morton (Z-order) curve over the bin grid: the bits of
+// the three bin coordinates interleaved from the lowest level up, a dimension
+// dropping out once its bits are used.  Sorting atoms by this rank makes any
+// contiguous range of rows a compact 3-D region, so the sender rows gathered
+// by rows processed together stay within one L2.
+__device__ __forceinline__ int bin_rank(int bin, const GridParams& g) {
+  const int c[3] = {bin % g.nb[0], (bin / g.nb[0]) % g.nb[1], bin / (g.nb[0] * g.nb[1])};
+  int r = 0, pos = 0;
+  const int kmax = max(g.mbits[0], max(g.mbits[1], g.mbits[2]));
+  for (int k = 0; k < kmax; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (k < g.mbits[d]) {
+        r |= ((c[d] >> k) & 1) << pos;
+        ++pos;
+      }
+  return r;
+}
+
+__global__ void k_rank_count(const GridParams* __restrict__ gp, const int32_t* __restrict__ bin_count,
+                             int32_t* __restrict__ rank_count) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const GridParams g = *gp;
+  if (b >= g.nbins) return;
+  rank_count[bin_rank(b, g)] = bin_count[b];
+}
+
+__global__ void k_bin_start(const GridParams* __restrict__ gp, const int32_t* __restrict__ rank_start,
+                            int32_t* __restrict__ bin_start) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const GridParams g = *gp;
+  if (b >= g.nbins) return;
+  bin_start[b] = rank_start[bin_rank(b, g)];
+}
+
 __global__ void k_bin_fill(const int4* __restrict__ info, int64_t n, const int32_t* __restrict__ bin_start,
                            int32_t* __restrict__ cursor, int32_t* __restrict__ bin_atoms) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -222,10 +264,10 @@ __global__ void k_bin_fill(const int4* __restrict__ info, int64_t n, const int32
 
 // insertion sort of each bin's atoms by input index (deterministic order)
 __global__ void k_bin_sort(const GridParams* __restrict__ gp, const int32_t* __restrict__ bin_start,
-                           int32_t* __restrict__ bin_atoms) {
+                           const int32_t* __restrict__ bin_count, int32_t* __restrict__ bin_atoms) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= gp->nbins) return;
-  int s = bin_start[b], e = bin_start[b + 1];
+  int s = bin_start[b], e = s + bin_count[b];
   for (int k = s + 1; k < e; ++k) {
     int v = bin_atoms[k];
     int q = k - 1;
@@ -273,7 +315,8 @@ __device__ __forceinline__ bool pair_test(const double* __restrict__ xi, const d
 template <bool FILL>
 __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* __restrict__ info_s,
                       const int32_t* __restrict__ spec_s, CellInfo ci, const GridParams* __restrict__ gp,
-                      const int32_t* __restrict__ bin_start, int32_t* __restrict__ cnt,
+                      const int32_t* __restrict__ bin_start, const int32_t* __restrict__ bin_count,
+                      int32_t* __restrict__ cnt,
                       const int32_t* __restrict__ row_ptr, int64_t capacity, int32_t* __restrict__ e_src,
                       uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec, int64_t* __restrict__ status) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -322,7 +365,7 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
         }
         if (skip) continue;
         int bin = (c[2] * g.nb[1] + c[1]) * g.nb[0] + c[0];
-        int s = bin_start[bin], e = bin_start[bin + 1];
+        int s = bin_start[bin], e = s + bin_count[bin];
         for (int j = s; j < e; ++j) {
           int4 oj = info_s[j];
           int S[3];
@@ -411,16 +454,22 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   hipMemsetAsync(b.bin_cursor, 0, sizeof(int32_t) * (b.max_bins + 1), s);
   const int ga = (int)((n + nblk - 1) / nblk);
   k_bin_assign<<<ga, nblk, 0, s>>>(sys.positions, n, ci, b.grid, b.info, b.bin_count);
-  exclusive_scan(b.bin_count, b.max_bins, b.bin_start, b.scan_tmp, s);
+  // bins laid out along a Morton curve: counts in rank order, scan, back to bins
+  const int64_t nr = 8 * (int64_t)b.max_bins;
+  hipMemsetAsync(b.rank_count, 0, sizeof(int32_t) * (nr + 1), s);
+  const unsigned gb = (unsigned)((b.max_bins + 255) / 256);
+  k_rank_count<<<gb, 256, 0, s>>>(b.grid, b.bin_count, b.rank_count);
+  exclusive_scan(b.rank_count, nr, b.rank_start, b.scan_tmp, s);
+  k_bin_start<<<gb, 256, 0, s>>>(b.grid, b.rank_start, b.bin_start);
   k_bin_fill<<<ga, nblk, 0, s>>>(b.info, n, b.bin_start, b.bin_cursor, b.perm);
-  k_bin_sort<<<(b.max_bins + 255) / 256, 256, 0, s>>>(b.grid, b.bin_start, b.perm);
+  k_bin_sort<<<gb, 256, 0, s>>>(b.grid, b.bin_start, b.bin_count, b.perm);
   k_gather_sorted<<<ga, nblk, 0, s>>>(b.perm, n, sys.positions, sys.species, b.info, sys.n_owned, ci.n_species, b.pos_s,
                                       b.info_s, b.spec_s, b.inv_perm, b.owned_s);
-  k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.cnt, nullptr,
+  k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.cnt, nullptr,
                                    capacity, nullptr, nullptr, nullptr, b.status);
   exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
   k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
-  k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, nullptr, b.row_ptr,
+  k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
   k_nbr_rev<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, capacity, b.e_rev);
 }

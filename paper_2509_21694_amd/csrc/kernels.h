@@ -21,8 +21,10 @@ struct NbrBuffers {
   int max_bins;
   int32_t* bin_count;    // [max_bins+1]
   int32_t* bin_cursor;   // [max_bins+1]
-  int32_t* bin_start;    // [max_bins+1]
-  int32_t* scan_tmp;     // [scan_tmp_elems(max(N, max_bins))]
+  int32_t* bin_start;    // [max_bins+1] first sorted slot of each bin (bins laid out in curve order)
+  int32_t* rank_count;   // [8*max_bins+1] bin counts in curve-rank order, then their exclusive scan
+  int32_t* rank_start;   // [8*max_bins+1]
+  int32_t* scan_tmp;     // [scan_tmp_elems(max(N, 8*max_bins))]
   int4* info;            // [N] image index (x,y,z) + bin (w), input order
   int32_t* perm;         // [N] sorted position -> input index
   int32_t* inv_perm;     // [N]
