@@ -364,7 +364,8 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
              }, &d.w3fp[role])) != MPIP_OK) goto done;
         if ((st = pack(NPl * CN, KC64, [&](int o, int k, int lane, int j) {
                const int pi = o / CN, mt = o % CN, g = lane >> 4, rho = lane & 15;
-               const int c = CB * (rho / 4) + 4 * mt + (rho % 4);
+               // chunk k = mt/2 of lane group rho/4: channels 32k + 8(rho/4) + 4(mt%2) + rho%4
+               const int c = 32 * (mt / 2) + 8 * (rho / 4) + 4 * (mt % 2) + (rho % 4);
                const int h = bf ? phi_bf(k, g, j) : phi_f(k, g);
                return W3(h, lv[pi] * C + c);
              }, &d.w3t[role])) != MPIP_OK) goto done;
@@ -372,7 +373,7 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
         if ((st = pack(NPl * 4, KCC, [&](int o, int k, int lane, int j) {
                const int pi = o / 4, mt = o % 4, g = lane >> 4;
                const int h = 16 * mt + (lane & 15);
-               const int c = bf ? (CB * g + 8 * k + j) : (CB * g + k);
+               const int c = bf ? (32 * k + 8 * g + j) : (32 * (k / 8) + 8 * g + k % 8);
                return W3(h, lv[pi] * C + c);
              }, &d.w3bp[role])) != MPIP_OK) goto done;
       }

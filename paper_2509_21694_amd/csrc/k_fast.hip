@@ -550,7 +550,7 @@ template <> struct HRaw<0> {
   }
 };
 
-// what one 8-channel chunk (path l, channels CB*g + 8k ..) reads, fetched
+// what one 8-channel chunk (path l, channels 32k + 8g ..) reads, fetched
 // one chunk ahead of its use
 template <int PREC, int L>
 struct Chunk {
@@ -596,12 +596,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       const int e = t0 + el;
       const bool valid = e < e1;
       const int j = valid ? a.e_src[e] : 0;
-      const HTy* hj = ht + (int64_t)j * NLM * C + CB * g;
+      const HTy* hj = ht + (int64_t)j * NLM * C + 8 * g;
       Chunk<PREC, L> cb[2];
       auto fetch = [&](auto cc, Chunk<PREC, L>& b) {
         constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
 #pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) b.h[m].load(hj + (l * l + m) * C + 8 * k);
+        for (int m = 0; m < 2 * l + 1; ++m) b.h[m].load(hj + (l * l + m) * C + 32 * k);
         if constexpr (PREC == 1) {
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh)
@@ -660,11 +660,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
     for (int q = 0; q < CB; ++q) acc[q] = row16_sum(acc[q]);
     if (el == 0) {
-      float* dst = a.A + (int64_t)i * C + CB * g;
+      // chunk k of lane group g holds channels 32k + 8g .. + 8
 #pragma unroll
-      for (int q = 0; q < CB; q += 4)
-        *(float4*)(dst + q) = make_float4(a.inv_n * acc[q], a.inv_n * acc[q + 1], a.inv_n * acc[q + 2],
-                                          a.inv_n * acc[q + 3]);
+      for (int q = 0; q < CB; q += 4) {
+        float* dst = a.A + (int64_t)i * C + 32 * (q / 8) + 8 * g + q % 8;
+        *(float4*)dst = make_float4(a.inv_n * acc[q], a.inv_n * acc[q + 1], a.inv_n * acc[q + 2], a.inv_n * acc[q + 3]);
+      }
     }
   }
 }
@@ -701,19 +702,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   const RowWalk rw = row_walk<NW>(a.n);
   for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-    const float* Abi = a.Abar + (int64_t)i * C + CB * g;
+    const float* Abi = a.Abar + (int64_t)i * C + 8 * g;
     for (int t0 = e0; t0 < e1; t0 += kTileE) {
       const int e = t0 + el;
       const bool valid = e < e1;
       const int j = valid ? a.e_src[e] : 0;
-      const HTy* hj = ht + (int64_t)j * NLM * C + CB * g;
+      const HTy* hj = ht + (int64_t)j * NLM * C + 8 * g;
       Chunk<PREC, L> cb[2];
       auto fetch = [&](auto cc, Chunk<PREC, L>& b) {
         constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
 #pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) b.h[m].load(hj + (l * l + m) * C + 8 * k);
-        b.a0 = *(const float4*)(Abi + 8 * k);
-        b.a1 = *(const float4*)(Abi + 8 * k + 4);
+        for (int m = 0; m < 2 * l + 1; ++m) b.h[m].load(hj + (l * l + m) * C + 32 * k);
+        b.a0 = *(const float4*)(Abi + 32 * k);
+        b.a1 = *(const float4*)(Abi + 32 * k + 4);
         if constexpr (PREC == 1) {
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh)

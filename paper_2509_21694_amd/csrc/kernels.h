@@ -74,8 +74,8 @@ struct LayerDev {
   const void* w2f;       // layer-2 B operand, edges x features orientation [nt 4][kc][64]
   const void* w3fp[2];   // layer-3 B operand, channel of (tile nt, col n) = (C/16) n + nt
   const void* w3t[2];    // layer-3 A operand, features x edges; channel of row rho in tile mt
-                         //   = (C/4)(rho/4) + 4 mt + rho%4
-  const void* w3bp[2];   // MLP-adjoint A operand; k-slot (g, j) of chunk kc = channel (C/4) g + 8 kc + j
+                         //   = 32 (mt/2) + 8 (rho/4) + 4 (mt%2) + rho%4
+  const void* w3bp[2];   // MLP-adjoint A operand; k-slot (g, j) of chunk kc = channel 32 kc + 8 g + j
   // first layer, species factorisation: V_l[(s,k)][c] = ht1[s][c] W3[k][(l,c)] / n_avg
   const void* vt[3];     // [C][S*64]  (A = Q V)
   const void* v[3];      // [S*64][C]  (P = dA V^T)
