@@ -459,7 +459,7 @@ namespace {
 struct Plan {
   size_t total = 0;
   size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_rcount, o_rstart, o_scan, o_info, o_perm, o_iperm, o_pos,
-      o_info_s, o_spec, o_owned, o_cnt, o_row, o_esrc, o_eshift, o_evec, o_erev, o_g;
+      o_info_s, o_spec, o_owned, o_cnt, o_row, o_esrc, o_eshift, o_evec, o_erev, o_edst, o_g;
   size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
   size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
   std::vector<size_t> o_ht, o_z0, o_zl;  // per layer 1..K (index t-1)
@@ -499,6 +499,7 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
   p.o_eshift = take(cur, sizeof(uint32_t) * cap);
   p.o_evec = take(cur, sizeof(float4) * cap);
   p.o_erev = take(cur, sizeof(int32_t) * cap);
+  p.o_edst = take(cur, sizeof(int32_t) * cap);
   if (hp) {
     const int64_t C = hp->channels, L = hp->l_max, nlm = (L + 1) * (L + 1), S = hp->n_species;
     p.o_g = take(cur, sizeof(float4) * cap);
@@ -570,6 +571,7 @@ NbrBuffers nbr_buffers(char* ws, const Plan& p) {
   b.e_shift = (uint32_t*)(ws + p.o_eshift);
   b.e_vec = (float4*)(ws + p.o_evec);
   b.e_rev = (int32_t*)(ws + p.o_erev);
+  b.e_dst = (int32_t*)(ws + p.o_edst);
   return b;
 }
 
@@ -696,7 +698,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   const int KQ = 64 * S;
   float* qp = p.o_qp ? (float*)(w + p.o_qp) : nullptr;
   FastArgs fa;
-  fa.n = N; fa.row_ptr = b.row_ptr; fa.e_src = b.e_src; fa.e_vec = b.e_vec; fa.capacity = max_edges;
+  fa.n = N; fa.row_ptr = b.row_ptr; fa.e_src = b.e_src; fa.e_dst = b.e_dst; fa.e_vec = b.e_vec; fa.capacity = max_edges;
   fa.status = b.status; fa.rc = (float)hp.r_cut; fa.envelope_p = hp.envelope_p; fa.n_species = S;
   fa.inv_n = (float)hp.inv_avg_neighbors; fa.Q = qp; fa.P = qp; fa.g = g; fa.htbar = htbar;
   auto set_fast = [&](const LayerDev& d, int role) {
@@ -779,6 +781,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   // ---------------- adjoint ----------------
   T.begin("outputs", s);
   launch_zero(g, sizeof(float4) * (size_t)max_edges, s);
+  if (fast_layer(K) && kind_of(K) == KIND_LAST) edge_receivers(b, N, max_edges, s);
   T.end(s);
   for (int t = K; t >= 1; --t) {
     const LayerDev& d = LD[t - 1];

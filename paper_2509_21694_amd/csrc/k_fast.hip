@@ -699,14 +699,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   }
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
   const HTy* ht = (const HTy*)a.ht;
-  const RowWalk rw = row_walk<NW>(a.n);
-  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-    const float* Abi = a.Abar + (int64_t)i * C + 8 * g;
-    for (int t0 = e0; t0 < e1; t0 += kTileE) {
-      const int e = t0 + el;
-      const bool valid = e < e1;
+  // edge-parallel: tiles of 16 consecutive edges regardless of rows (no
+  // per-row padding); each lane reads dA of its own edge's receiver
+  const int64_t E = a.row_ptr[a.n];
+  const RowWalk tw = row_walk<NW>((E + kTileE - 1) / kTileE);
+  for (int64_t t = tw.i; t < tw.end; t += tw.step) {
+    {
+      const int e = (int)(t * kTileE) + el;
+      const bool valid = e < E;
       const int j = valid ? a.e_src[e] : 0;
+      const int i = valid ? a.e_dst[e] : 0;
+      const float* Abi = a.Abar + (int64_t)i * C + 8 * g;
       const HTy* hj = ht + (int64_t)j * NLM * C + 8 * g;
       Chunk<PREC, L> cb[2];
       auto fetch = [&](auto cc, Chunk<PREC, L>& b) {

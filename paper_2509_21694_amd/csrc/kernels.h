@@ -38,6 +38,7 @@ struct NbrBuffers {
   uint32_t* e_shift;     // [cap] S packed as three int8
   float4* e_vec;         // [cap] r_e (FP32 of the FP64 difference), species of sender in .w bits
   int32_t* e_rev;        // [cap]
+  int32_t* e_dst;        // [cap] receiver (sorted index) of each edge, for edge-parallel passes
 };
 
 int64_t scan_tmp_elems(int64_t n);
@@ -46,6 +47,7 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
                      hipStream_t s);
 void export_neighbors(const NbrBuffers& b, int64_t n, int64_t capacity, int32_t* oi, int32_t* oj, int32_t* os,
                       hipStream_t s);
+void edge_receivers(const NbrBuffers& b, int64_t n, int64_t capacity, hipStream_t s);
 
 // ------------------------------------------------------------------ layers
 
@@ -112,6 +114,7 @@ struct FastArgs {
   int64_t n;
   const int32_t* row_ptr;
   const int32_t* e_src;
+  const int32_t* e_dst;  // receiver of each edge (edge-parallel adjoint a)
   const float4* e_vec;
   int64_t capacity;
   const int64_t* status;
