@@ -316,7 +316,7 @@ template <bool FILL>
 __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* __restrict__ info_s,
                       const int32_t* __restrict__ spec_s, CellInfo ci, const GridParams* __restrict__ gp,
                       const int32_t* __restrict__ bin_start, const int32_t* __restrict__ bin_count,
-                      int32_t* __restrict__ cnt,
+                      int32_t* __restrict__ blk, int32_t* __restrict__ cnt,
                       const int32_t* __restrict__ row_ptr, int64_t capacity, int32_t* __restrict__ e_src,
                       uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec, int64_t* __restrict__ status) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -342,10 +342,13 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
   int count = 0;
   int64_t out = FILL ? row_ptr[i] : 0;
   int coincident = 0;
+  const bool stencil3 = g.stencil[0] && g.stencil[1] && g.stencil[2];
   for (int oz = lo[2]; oz <= hi[2]; ++oz)
     for (int oy = lo[1]; oy <= hi[1]; ++oy)
       for (int ox = lo[0]; ox <= hi[0]; ++ox) {
         int o[3] = {ox, oy, oz};
+        // with a 27-bin stencil, the row's edges come in blocks by stencil offset
+        if (FILL && stencil3) blk[28 * i + ((oz + 1) * 3 + (oy + 1)) * 3 + (ox + 1)] = count;
         int c[3], Sp[3];
         bool skip = false;
         for (int d = 0; d < 3; ++d) {
@@ -389,6 +392,7 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
         }
       }
   if (!FILL) cnt[i] = count;
+  if (FILL && stencil3) blk[28 * i + 27] = count;
   if (coincident) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_COINCIDENT);
 }
 
@@ -405,19 +409,43 @@ __global__ void k_check_capacity(const int32_t* __restrict__ row_ptr, int64_t n,
 // one lane per edge of the row (rows longer than 64 loop)
 __global__ __launch_bounds__(256) void k_nbr_rev(int64_t n, const int32_t* __restrict__ row_ptr,
                                                  const int32_t* __restrict__ e_src,
-                                                 const uint32_t* __restrict__ e_shift, int64_t capacity,
-                                                 int32_t* __restrict__ e_rev) {
+                                                 const uint32_t* __restrict__ e_shift, const int4* __restrict__ info_s,
+                                                 const GridParams* __restrict__ gp, const int32_t* __restrict__ blk,
+                                                 int64_t capacity, int32_t* __restrict__ e_rev) {
   const int64_t i = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
   if (row_ptr[n] > capacity) return;
+  const GridParams g = *gp;
+  const bool stencil3 = g.stencil[0] && g.stencil[1] && g.stencil[2];
+  int bi[3];
+  {
+    const int bin = info_s[i].w;
+    bi[0] = bin % g.nb[0]; bi[1] = (bin / g.nb[0]) % g.nb[1]; bi[2] = bin / (g.nb[0] * g.nb[1]);
+  }
   for (int e = row_ptr[i] + lane; e < row_ptr[i + 1]; e += 64) {
     const int j = e_src[e];
     const uint32_t sh = e_shift[e];
     const int S0 = (int8_t)(sh & 0xff), S1 = (int8_t)((sh >> 8) & 0xff), S2 = (int8_t)((sh >> 16) & 0xff);
     const uint32_t want = (uint32_t)((-S0) & 0xff) | ((uint32_t)((-S1) & 0xff) << 8) | ((uint32_t)((-S2) & 0xff) << 16);
+    int f0 = row_ptr[j], f1 = row_ptr[j + 1];
+    if (stencil3) {
+      // the reverse edge sits in row j's block of stencil offset -o, o = bin(j) - bin(i)
+      const int bin = info_s[j].w;
+      const int bj[3] = {bin % g.nb[0], (bin / g.nb[0]) % g.nb[1], bin / (g.nb[0] * g.nb[1])};
+      int k = 0;
+#pragma unroll
+      for (int d = 2; d >= 0; --d) {
+        int o = bj[d] - bi[d];
+        if (o > 1) o -= g.nb[d];        // periodic wrap (nb >= 3 with a stencil)
+        else if (o < -1) o += g.nb[d];
+        k = 3 * k + (1 - o);
+      }
+      f1 = f0 + blk[28 * (int64_t)j + k + 1];
+      f0 = f0 + blk[28 * (int64_t)j + k];
+    }
     int r = -1;
-    for (int f = row_ptr[j]; f < row_ptr[j + 1]; ++f)
+    for (int f = f0; f < f1; ++f)
       if (e_src[f] == (int)i && e_shift[f] == want) { r = f; break; }
     e_rev[e] = r;
   }
@@ -465,13 +493,14 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   k_bin_sort<<<gb, 256, 0, s>>>(b.grid, b.bin_start, b.bin_count, b.perm);
   k_gather_sorted<<<ga, nblk, 0, s>>>(b.perm, n, sys.positions, sys.species, b.info, sys.n_owned, ci.n_species, b.pos_s,
                                       b.info_s, b.spec_s, b.inv_perm, b.owned_s);
-  k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.cnt, nullptr,
+  k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt, nullptr,
                                    capacity, nullptr, nullptr, nullptr, b.status);
   exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
   k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
-  k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.row_ptr,
+  k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
-  k_nbr_rev<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, capacity, b.e_rev);
+  k_nbr_rev<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.info_s, b.grid, b.blk,
+                                                     capacity, b.e_rev);
 }
 
 // receiver of every edge, one wave per row

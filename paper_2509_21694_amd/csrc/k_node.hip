@@ -282,35 +282,46 @@ void launch_gate_bwd(const NodeArgs& a, int last, int init_hbar, hipStream_t s) 
 
 // Per atom: F_i = sum_{e in row i} g_e - g_rev(e) (FP64), written in input
 // order; per block: sum of root energies and of r_e (x) g_e, fixed order.
+// One wave per row (lanes over the row's edges, a butterfly sum per row);
+// each lane keeps its virial partial sums over all rows of its wave.
 __global__ __launch_bounds__(256) void k_forces(OutArgs a) {
   __shared__ double sh[10][256];
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double loc[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) loc[k] = 0.0;
   const bool run = (a.status[ST_FLAGS] == 0) && ((int64_t)a.row_ptr[a.n] <= a.capacity);
-  if (run && i < a.n) {
-    double F[3] = {0.0, 0.0, 0.0};
-    for (int e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) {
-      const float4 ge = a.g[e];
-      const int rv = a.e_rev[e];
-      const float4 gr = rv >= 0 ? a.g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
-      const float4 r = a.e_vec[e];
-      F[0] += (double)ge.x - (double)gr.x;
-      F[1] += (double)ge.y - (double)gr.y;
-      F[2] += (double)ge.z - (double)gr.z;
-      const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
+  if (run) {
+    const int64_t r0 = (int64_t)blockIdx.x * 256 + w * 64;
+    for (int64_t i = r0; i < r0 + 64 && i < a.n; ++i) {
+      double F[3] = {0.0, 0.0, 0.0};
+      for (int e = a.row_ptr[i] + lane; e < a.row_ptr[i + 1]; e += 64) {
+        const float4 ge = a.g[e];
+        const int rv = a.e_rev[e];
+        const float4 gr = rv >= 0 ? a.g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 r = a.e_vec[e];
+        F[0] += (double)ge.x - (double)gr.x;
+        F[1] += (double)ge.y - (double)gr.y;
+        F[2] += (double)ge.z - (double)gr.z;
+        const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
 #pragma unroll
-      for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < 3; ++p)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) loc[1 + 3 * p + q] += rr[p] * gg[q];
+          for (int q = 0; q < 3; ++q) loc[1 + 3 * p + q] += rr[p] * gg[q];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[d] += __shfl_xor(F[d], off);
+      if (lane == 0) {
+        const int o = a.perm[i];
+        a.forces[3 * (int64_t)o + 0] = F[0];
+        a.forces[3 * (int64_t)o + 1] = F[1];
+        a.forces[3 * (int64_t)o + 2] = F[2];
+        if (a.atom_energy) a.atom_energy[o] = a.atom_e[i];
+        if (a.owned_s[i]) loc[0] += a.atom_e[i];
+      }
     }
-    const int o = a.perm[i];
-    a.forces[3 * (int64_t)o + 0] = F[0];
-    a.forces[3 * (int64_t)o + 1] = F[1];
-    a.forces[3 * (int64_t)o + 2] = F[2];
-    if (a.atom_energy) a.atom_energy[o] = a.atom_e[i];
-    if (a.owned_s[i]) loc[0] = a.atom_e[i];
   }
 #pragma unroll
   for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = loc[k];

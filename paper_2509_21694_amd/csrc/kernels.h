@@ -34,6 +34,7 @@ struct NbrBuffers {
   uint8_t* owned_s;      // [N]
   int32_t* cnt;          // [N]
   int32_t* row_ptr;      // [N+1]
+  int32_t* blk;          // [N][28] start of each of the 27 stencil-offset blocks within a row, and its end
   int32_t* e_src;        // [cap] sender (sorted index)
   uint32_t* e_shift;     // [cap] S packed as three int8
   float4* e_vec;         // [cap] r_e (FP32 of the FP64 difference), species of sender in .w bits
