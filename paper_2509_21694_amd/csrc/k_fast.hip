@@ -369,7 +369,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
   constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
   __shared__ typename O::T sM1[NM1], sM2[NM2], sB2[NB2], sB1[NB1];
-  __shared__ float sYB[NW][kTileE * 16 * MQ];
+  constexpr int SYB = 16 * MQ + 1;   // odd row stride: the 16 edge lanes hit distinct banks
+  __shared__ float sYB[NW][kTileE * SYB];
   if (fast_guard(a)) return;
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NM1>(sM1, a.w1a);
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
         for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(pb[mq][kc], O::from_tiles(a2, kc), acc);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) syb[el * (16 * MQ) + 16 * mq + 4 * g + r] = acc[r];
+        for (int r = 0; r < 4; ++r) syb[el * SYB + 16 * mq + 4 * g + r] = acc[r];
       }
       float eb[kNB];
       if constexpr (PREC == 1) mlp_backward_reg<PREC>(ab2, p1, p2, lane, sB2, sB1, eb);
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
         for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
 #pragma unroll
-        for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * (16 * MQ) + sp * NLM + k];
+        for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + sp * NLM + k];
         yc_first_adj<L>(a.cg, ycb, Yb);
         add_edge_grad(a.g, e, geo, eb, Yb);
       }
@@ -832,7 +833,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
   __shared__ typename O::T sM1[NM1], sM2[NM2];
   __shared__ typename O::T sW[NWT];
-  __shared__ float sY[NW][kTileE * 16];
+  __shared__ float sY[NW][kTileE * 17];   // odd row stride against bank conflicts
   if (fast_guard(a)) return;
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3f);
@@ -874,7 +875,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         for (int k = 0; k < 16; ++k) {
           float val = 0.f;
           if (k < NLM) val = (k >= 1 && k < 4) ? -yc[k] : yc[k];
-          syc[el * 16 + k] = val;
+          syc[el * 17 + k] = val;
         }
       }
       f32x4 p1[4], p2[4], a2[4];
@@ -891,7 +892,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       // YC^T rows lm = el, edges 4g + r (zero for tail edges: their harmonics are zero)
       float yt[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) yt[r] = a.inv_n * syc[(4 * g + r) * 16 + el];
+      for (int r = 0; r < 4; ++r) yt[r] = a.inv_n * syc[(4 * g + r) * 17 + el];
       wave_lds_sync();
       static_for<L + 1>([&](auto lc) {
         constexpr int l = decltype(lc)::value;
