@@ -382,16 +382,52 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* syb = sYB[wv];
   const int S = a.n_species, KQ = 64 * S, MROWS = S * NLM;
+  // BF16 form: the row's P (NLM x 64 S BF16) is staged in a wave-private LDS
+  // slice; the next row's P is loaded into registers while this row's tiles run
+  constexpr int PW = (PREC == 1) ? 16 * MQ * 64 : 8;      // BF16 elements, >= NLM * 64 S
+  constexpr int NPL = (PW / 8 + 63) / 64;                   // 16-byte pieces per lane
+  __shared__ uint4 sPr[NW][PW / 8];
+  const unsigned short* sPw = (const unsigned short*)sPr[wv];
+  const int pieces = NLM * KQ / 8;
   const RowWalk rw = row_walk<NW>(a.n);
+  uint4 praw[NPL];
+  auto p_fetch = [&](int64_t row) {
+    if constexpr (PREC == 1) {
+      const uint4* src = (const uint4*)((const __bf16*)a.P + row * NLM * KQ);
+#pragma unroll
+      for (int q = 0; q < NPL; ++q) {
+        const int pc = q * 64 + lane;
+        praw[q] = (row < rw.end && pc < pieces) ? src[pc] : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+  };
+  auto p_stage = [&]() {
+    if constexpr (PREC == 1) {
+#pragma unroll
+      for (int q = 0; q < NPL; ++q) {
+        const int pc = q * 64 + lane;
+        if (pc < PW / 8) sPr[wv][pc] = praw[q];
+      }
+      wave_lds_sync();
+    }
+  };
+  p_fetch(rw.i);
   for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+    p_stage();
+    p_fetch(i + rw.step);
     const float* Pi = a.P + (int64_t)i * NLM * KQ;
-    const __bf16* Pbi = (const __bf16*)a.P + (int64_t)i * NLM * KQ;
     auto Pval = [&](int m, int k) -> float {
-      if (m >= MROWS) return 0.f;
-      const int s = m / NLM, lm = m - s * NLM;
-      if constexpr (PREC == 1) return (float)Pbi[lm * KQ + s * 64 + k];
-      else return Pi[lm * KQ + s * 64 + k];
+      if constexpr (PREC == 1) {
+        const int mm = m < MROWS ? m : 0;
+        const int s = mm / NLM, lm = mm - s * NLM;
+        const float v = __uint_as_float(((unsigned)sPw[lm * KQ + s * 64 + k]) << 16);
+        return m < MROWS ? v : 0.f;
+      } else {
+        if (m >= MROWS) return 0.f;
+        const int s = m / NLM, lm = m - s * NLM;
+        return Pi[lm * KQ + s * 64 + k];
+      }
     };
     // A operand of dE/da2^T = P^T Ysel^T: rows hidden 16 mt + el, k over (s,lm)
     typename O::T pa[4][KCQ];
