@@ -58,7 +58,7 @@ def phase_counts(hp, prec):
     fb = 2 if prec == "bf16" else 4            # storage of Q/P and h~ in the form
     mlp12, mlp3 = nb * H + H * H, H * P * C
     ev, src, grw = 16, 4, 32                   # e_vec, e_src, g read+write
-    return {
+    d = {
         # Q_i += a2 (x) YC over the row: layers 1-2 of the MLP and the outer product
         "edge_fwd_t1": (2 * (mlp12 + H * nlm), 0.0, ev, 8 + nlm * 64 * S * fb),
         # MLP adjoint through layers 2, 1; dE/da2 = P^T Ysel; dE/dYC = P a2
@@ -70,6 +70,15 @@ def phase_counts(hp, prec):
         # h~bar_i = sum_e YC^T (R dA_j): nlm MAC per channel on MFMA; R dA_j: P mul per channel
         "edge_pull_t2": (2.0 * nlm * C, 1.0 * P * C, ev + src, 8 + C * 4 + nlm * C * 4),
     }
+    if prec == "bf16":
+        # one fused adjoint over the reverse edges: the MLP adjoint, and
+        # s_l = <h~_i,l , YC_l>, dYC and the pull (nlm MAC per channel each) on
+        # MFMA; dR and R dA_j (P mul per channel each) on the VALU; e_rev read
+        # per edge; h~_i read and h~bar_i written (BF16) once per atom
+        d["edge_bwd_t2"] = (2 * (mlp12 + mlp3) + 6.0 * nlm * C, 2.0 * P * C, ev + 2 * src + grw,
+                            8 + nlm * C * fb + C * 4 + nlm * C * fb)
+        del d["edge_pull_t2"]
+    return d
 
 
 def kernel_roofline(name, t, hp, prec, n_edges, n_atoms):

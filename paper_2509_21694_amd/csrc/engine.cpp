@@ -700,7 +700,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   const int KQ = 64 * S;
   float* qp = p.o_qp ? (float*)(w + p.o_qp) : nullptr;
   FastArgs fa;
-  fa.n = N; fa.row_ptr = b.row_ptr; fa.e_src = b.e_src; fa.e_dst = b.e_dst; fa.e_vec = b.e_vec; fa.capacity = max_edges;
+  fa.n = N; fa.row_ptr = b.row_ptr; fa.e_src = b.e_src; fa.e_dst = b.e_dst; fa.e_rev = b.e_rev; fa.e_vec = b.e_vec; fa.capacity = max_edges;
   fa.status = b.status; fa.rc = (float)hp.r_cut; fa.envelope_p = hp.envelope_p; fa.n_species = S;
   fa.inv_n = (float)hp.inv_avg_neighbors; fa.Q = qp; fa.P = qp; fa.g = g; fa.htbar = htbar;
   auto set_fast = [&](const LayerDev& d, int role) {
@@ -783,7 +783,8 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   // ---------------- adjoint ----------------
   T.begin("outputs", s);
   launch_zero(g, sizeof(float4) * (size_t)max_edges, s);
-  if (fast_layer(K) && kind_of(K) == KIND_LAST) edge_receivers(b, N, max_edges, s);
+  // the FP32 form's edge-parallel adjoint needs each edge's receiver
+  if (fast_layer(K) && kind_of(K) == KIND_LAST && !ht_bf16) edge_receivers(b, N, max_edges, s);
   T.end(s);
   for (int t = K; t >= 1; --t) {
     const LayerDev& d = LD[t - 1];
@@ -828,10 +829,14 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         launch_l1(prec, L, false, fa, s);
       } else {
         fa.ht = ht; fa.Abar = A;
-        launch_l2(prec, C, L, 1, fa, s);
-        T.end(s);
-        T.begin("edge_pull_t" + std::to_string(t), s);
-        launch_l2(prec, C, L, 2, fa, s);
+        if (ht_bf16) {
+          launch_l2(prec, C, L, 3, fa, s);
+        } else {
+          launch_l2(prec, C, L, 1, fa, s);
+          T.end(s);
+          T.begin("edge_pull_t" + std::to_string(t), s);
+          launch_l2(prec, C, L, 2, fa, s);
+        }
       }
     } else {
       ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;

@@ -235,6 +235,49 @@ __device__ __forceinline__ void mlp_backward_reg(const f32x4* ab2, const f32x4* 
   }
 }
 
+// silu'(p) of one hidden layer's pre-activations (16 per lane), kept in BF16
+// between the forward and the adjoint of the MLP
+struct DsPack {
+  bf16x8 v[2];
+};
+__device__ __forceinline__ DsPack ds_pack(const f32x4* p) {
+  DsPack d;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) d.v[mt / 2][(mt % 2) * 4 + r] = (__bf16)dsilu(p[mt][r]);
+  return d;
+}
+
+// mlp_backward_reg with the silu' factors taken from DsPack (BF16 form)
+template <typename WT>
+__device__ __forceinline__ void mlp_backward_ds(const f32x4* ab2, const DsPack& d1, const DsPack& d2, int lane,
+                                                const WT* W2B, const WT* W1B, float* eb) {
+  typedef Op<1> O;
+  f32x4 pb2[4], pb1[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pb2[mt][r] = ab2[mt][r] * (float)d2.v[mt / 2][(mt % 2) * 4 + r];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) acc = O::mma(W2B[(mt * 2 + kc) * 64 + lane], O::from_tiles(pb2, kc), acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * (float)d1.v[mt / 2][(mt % 2) * 4 + r];
+  }
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < 2; ++kc) acc = O::mma(W1B[kc * 64 + lane], O::from_tiles(pb1, kc), acc);
+  const int src = (lane & 15) + 16;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    eb[r] = acc[r];
+    eb[4 + r] = __shfl(acc[r], src);
+  }
+}
+
 // ============================================================ first layer
 
 // Workgroups of NW waves, each wave walking its own rows (row_walk); the
@@ -985,6 +1028,223 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   }
 }
 
+// Fused adjoint of the last layer (BF16 form).  Rows i are walked as in the
+// pull; every edge e = (i <- j) stands for its reverse e' = (j <- i), whose
+// sender is the row's own atom (same length, unit vector -u):
+//   X_e'[l, c]    = sum_m YC_e'[lm] ht_i[lm, c]
+//   dR_e'[l, c]   = dA_j[c] X_e'[l, c] / n_avg                 (MLP adjoint)
+//   dE/dYC_e'[lm] = sum_c ht_i[lm, c] R_e'[l, c] dA_j[c] / n_avg
+//   htbar_i[lm,c] = sum_{e in row i} YC_e'[lm] R_e'[l, c] dA_j[c] / n_avg
+// so the only per-edge gather is dA_j, the radial MLP runs once per edge for
+// both adjoints, and dE/dr_e' goes to g[rev(e)].  Layout per chunk (channels
+// 32k + 8g + q of lane group g, edge el): R and X are D tiles (channels x
+// edges); X is a 16x16x16 MFMA of the row's features (transposed through a
+// wave-private LDS slice, one row per row) with YC masked to degree l; the
+// products with dA_j feed the MLP adjoint (B operand) and dE/dYC (an MFMA
+// against the row's features); for the pull they are transposed to edges x
+// channels by an MFMA with a 0/1 selection matrix (column n of half tt is
+// channel 32k + 2n + tt) and summed with YC^T over the tile's edges.
+template <int C, int L, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_l2_adj(FastArgs a) {
+  typedef Op<1> O;
+  typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+  constexpr int NLM = (L + 1) * (L + 1);
+  constexpr int NK = C / 32, CN = C / 16, KCC = C / 32;
+  constexpr int HT = (NLM + 3) / 4 * 4;    // channel stride of the transposed row (bf16)
+  constexpr int NG = HT / 4;                // lane groups holding degrees in the X operand
+  __shared__ bf16x8 sW[(L + 1) * CN * 2 * 64];
+  __shared__ bf16x8 sWB[(L + 1) * 4 * KCC * 64];
+  __shared__ bf16x8 sM1[4 * 64], sM2[4 * 2 * 64], sB2[4 * 2 * 64], sB1[2 * 64];
+  __shared__ unsigned sHT[NW][C * HT / 2];
+  __shared__ float sY[NW][kTileE * 17];
+  if (fast_guard(a)) return;
+  stage_lds<bf16x8, (L + 1) * CN * 2 * 64>(sW, a.w3t);
+  stage_lds<bf16x8, (L + 1) * 4 * KCC * 64>(sWB, a.w3b);
+  stage_lds<bf16x8, 4 * 64>(sM1, a.w1a);
+  stage_lds<bf16x8, 4 * 2 * 64>(sM2, a.w2a);
+  stage_lds<bf16x8, 4 * 2 * 64>(sB2, a.w2b);
+  stage_lds<bf16x8, 2 * 64>(sB1, a.w1b);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
+  unsigned* sh = sHT[wv];
+  float* syc = sY[wv];
+  const unsigned short* ht = (const unsigned short*)a.ht;
+  // 0/1 selection operands of the transposition
+  bf16x8 sel[2];
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sel[tt][j] = (__bf16)((8 * g + j == 2 * el + tt) ? 1.f : 0.f);
+  const RowWalk rw = row_walk<NW>(a.n);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
+    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+    const unsigned short* hi = ht + (int64_t)i * NLM * C;
+    // the row's features, transposed: sh[c][lm] (degrees NLM .. HT-1 zero)
+#pragma unroll
+    for (int p0 = 0; p0 < C / 2; p0 += 64) {
+      const int p = p0 + lane;
+      if (p < C / 2) {
+#pragma unroll
+        for (int q = 0; q < HT / 2; ++q) {
+          const unsigned u0 = (2 * q < NLM) ? *(const unsigned*)(hi + (2 * q) * C + 2 * p) : 0u;
+          const unsigned u1 = (2 * q + 1 < NLM) ? *(const unsigned*)(hi + (2 * q + 1) * C + 2 * p) : 0u;
+          sh[(2 * p) * (HT / 2) + q] = (u0 & 0xffffu) | (u1 << 16);
+          sh[(2 * p + 1) * (HT / 2) + q] = (u0 >> 16) | (u1 & 0xffff0000u);
+        }
+      }
+    }
+    wave_lds_sync();
+    // X operand of M-tile mt: row el -> channel 32(mt/2) + 8(el/4) + 4(mt%2) + el%4,
+    // k-slot 4g + j -> degree lm
+    auto hx_op = [&](int mt) -> s16x4 {
+      const int ch = 32 * (mt / 2) + 8 * (el / 4) + 4 * (mt % 2) + (el % 4);
+      const uint2 v = *(const uint2*)(sh + ch * (HT / 2) + 2 * (g < NG ? g : 0));
+      return (g < NG) ? __builtin_bit_cast(s16x4, v) : (s16x4){0, 0, 0, 0};
+    };
+    f32x4 hb[NK][2];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) hb[k][0] = hb[k][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int t0 = e0; t0 < e1; t0 += kTileE) {
+      const int e = t0 + el;
+      const bool valid = e < e1;
+      const int j = valid ? a.e_src[e] : 0;
+      const float* Aj = a.Abar + (int64_t)j * C + 8 * g;
+      Geo geo;
+      const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
+      edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, a.rc, a.envelope_p, geo);
+      float yc[NLM];
+      yc_last<L>(a.cg, geo.Y, yc);
+      if (g == 0) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) syc[el * 17 + k] = k < NLM ? yc[k] : 0.f;
+      }
+      // X operands: B[k-slot 4g + j][edge el] = YC[4g + j] of degree l
+      s16x4 yop[L + 1];
+#pragma unroll
+      for (int l = 0; l <= L; ++l)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          float w = 0.f;
+#pragma unroll
+          for (int gg = 0; gg < 4; ++gg) {
+            const int lm = 4 * gg + jj;
+            if (lm >= l * l && lm < (l + 1) * (l + 1)) w = (g == gg) ? yc[lm] : w;
+          }
+          yop[l][jj] = bfbits(w);
+        }
+      f32x4 ab2[4];
+      bf16x8 bop[2];
+      DsPack d1, d2;
+      {
+        f32x4 p1[4], p2[4], a2[4];
+        mlp_forward_w<1>(geo, lane, sM1, sM2, p1, p2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) { a2[mt][r] = silu(p2[mt][r]); ab2[mt][r] = 0.f; }
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) bop[kc] = O::from_tiles(a2, kc);
+        d1 = ds_pack(p1);
+        d2 = ds_pack(p2);
+      }
+      wave_lds_sync();
+      // pull operands: A[lm = el][k-slot 4g + j] = YC_{e'}[lm] of edge 4g + j
+      // (1/n_avg is already in the products with dA_j)
+      float yt[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) yt[r] = syc[(4 * g + r) * 17 + el];
+      wave_lds_sync();
+      f32x4 dy = {0.f, 0.f, 0.f, 0.f};
+      float4 an0 = *(const float4*)Aj, an1 = *(const float4*)(Aj + 4);
+      bf16x8 hn = *(const bf16x8*)(hi + (int64_t)(el < NLM ? el : 0) * C + 8 * g);
+      static_for<NK>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        __builtin_amdgcn_sched_barrier(0);
+        const float ai[8] = {a.inv_n * an0.x, a.inv_n * an0.y, a.inv_n * an0.z, a.inv_n * an0.w,
+                             a.inv_n * an1.x, a.inv_n * an1.y, a.inv_n * an1.z, a.inv_n * an1.w};
+        const bf16x8 hr = hn;
+        const s16x4 hx[2] = {hx_op(2 * k), hx_op(2 * k + 1)};
+        if constexpr (k + 1 < NK) {
+          an0 = *(const float4*)(Aj + 32 * (k + 1));
+          an1 = *(const float4*)(Aj + 32 * (k + 1) + 4);
+          hn = *(const bf16x8*)(hi + (int64_t)(el < NLM ? el : 0) * C + 32 * (k + 1) + 8 * g);
+        }
+        static_for<L + 1>([&](auto lc) {
+          constexpr int l = decltype(lc)::value;
+          if constexpr (l > 0) __builtin_amdgcn_sched_barrier(0);
+          float R8[8], X8[8];
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) d = O::mma(sW[((l * CN + 2 * k + hh) * 2 + kc) * 64 + lane], bop[kc], d);
+            const f32x4 x = mfma_bf16_k16(hx[hh], yop[l], (f32x4){0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { R8[4 * hh + r] = d[r]; X8[4 * hh + r] = x[r]; }
+          }
+          bf16x8 rb, ra;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            rb[q] = (__bf16)(ai[q] * X8[q]);
+            ra[q] = (__bf16)(ai[q] * R8[q]);
+          }
+          // MLP adjoint through layer 3
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) ab2[mt] = O::mma(sWB[((l * 4 + mt) * KCC + k) * 64 + lane], rb, ab2[mt]);
+          // dE/dYC: D[lm][edge] += ht_i[lm][chunk] (R dA)[chunk][edge], rows of degree l only
+          const bool mine = el >= l * l && el < (l + 1) * (l + 1);
+          const bf16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
+          dy = O::mma(mine ? hr : z8, ra, dy);
+          // pull: transpose (R dA) to edges x channels, then sum over the tile's edges
+          s16x4 ya;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ya[r] = mine ? bfbits(yt[r]) : (short)0;
+#pragma unroll
+          for (int tt = 0; tt < 2; ++tt) {
+            const f32x4 tr = O::mma(ra, sel[tt], (f32x4){0.f, 0.f, 0.f, 0.f});
+            const s16x4 bv = {bfbits(tr[0]), bfbits(tr[1]), bfbits(tr[2]), bfbits(tr[3])};
+            hb[k][tt] = mfma_bf16_k16(ya, bv, hb[k][tt]);
+          }
+        });
+      });
+      __builtin_amdgcn_sched_barrier(0);
+      // dE/dYC of edge el: rows 4g + r live in lane el + 16 g
+      float ycb[NLM];
+#pragma unroll
+      for (int lm = 0; lm < NLM; ++lm) ycb[lm] = __shfl(dy[lm % 4], el + 16 * (lm / 4));
+      float eb[kNB];
+      mlp_backward_ds(ab2, d1, d2, lane, sB2, sB1, eb);
+      if (lane < kTileE && valid) {
+        float Yb[kMaxNlm];
+#pragma unroll
+        for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
+        yc_last_adj<L>(a.cg, ycb, Yb);
+        const int rv = a.e_rev[e];
+        if (rv >= 0) add_edge_grad(a.g, rv, geo, eb, Yb);
+      }
+    }
+    // htbar_i: D rows lm = 4g + r, column el of half tt = channel 32k + 2 el + tt
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lm = 4 * g + r;
+      if (lm < NLM) {
+        const int64_t o = ((int64_t)i * NLM + lm) * C + 2 * el;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          if (a.htbar_bf16) {
+            const unsigned w = (unsigned)(unsigned short)bfbits(hb[k][0][r]) |
+                               ((unsigned)(unsigned short)bfbits(hb[k][1][r]) << 16);
+            *(unsigned*)((unsigned short*)a.htbar + o + 32 * k) = w;
+          } else {
+            *(float2*)(a.htbar + o + 32 * k) = make_float2(hb[k][0][r], hb[k][1][r]);
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
 // ============================================================ dispatch
 
 
@@ -1034,7 +1294,8 @@ static void l2_launch(int which, const FastArgs& a, hipStream_t s) {
   const int pf = PREC == 1 ? 64 : 128, pa = PREC == 1 ? (NWA == 8 ? 32 : 64) : 128;
   if (which == 0) k_l2_fwd<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
   else if (which == 1) k_l2_bwd_a<PREC, C, L, NWA><<<l2_grid(a.n, NWA, pa), 64 * NWA, 0, s>>>(a);
-  else k_l2_bwd_b<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
+  else if (which == 2) k_l2_bwd_b<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
+  else if constexpr (PREC == 1) k_l2_adj<C, L, 8><<<l2_grid(a.n, 8, 32), 64 * 8, 0, s>>>(a);
 }
 
 template <int PREC>

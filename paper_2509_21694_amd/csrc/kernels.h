@@ -116,6 +116,7 @@ struct FastArgs {
   const int32_t* row_ptr;
   const int32_t* e_src;
   const int32_t* e_dst;  // receiver of each edge (edge-parallel adjoint a)
+  const int32_t* e_rev;  // reverse edge (fused adjoint of the last layer)
   const float4* e_vec;
   int64_t capacity;
   const int64_t* status;
@@ -143,7 +144,8 @@ struct FastArgs {
 };
 
 void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s);
-// which: 0 forward, 1 adjoint (dR, dY, MLP), 2 adjoint (sender-side pull)
+// which: 0 forward, 1 adjoint (dR, dY, MLP), 2 adjoint (sender-side pull),
+// 3 both adjoints fused over the reverse edges (BF16 form only)
 void launch_l2(int prec, int C, int L, int which, const FastArgs& a, hipStream_t s);
 
 struct EdgeArgs {

@@ -36,8 +36,7 @@ PHASES = {
     "edge_fwd_t1": r"k_l1_fwd<1,",
     "edge_bwd_t1": r"k_l1_bwd<1,",
     "edge_fwd_t2": r"k_l2_fwd<1,",
-    "edge_bwd_t2": r"k_l2_bwd_a<1,",
-    "edge_pull_t2": r"k_l2_bwd_b<1,",
+    "edge_bwd_t2": r"k_l2_adj<",
 }
 COPY = r"copyBuffer"
 
