@@ -78,6 +78,13 @@ def phase_counts(hp, prec):
         d["edge_bwd_t2"] = (2 * (mlp12 + mlp3) + 6.0 * nlm * C, 2.0 * P * C, ev + 2 * src + grw,
                             8 + nlm * C * fb + C * 4 + nlm * C * fb)
         del d["edge_pull_t2"]
+        # forward as sender-side messages: full MLP, X_l = <h~_j,l , YC_l> on
+        # MFMA (nlm MAC per channel), m = sum_l R_l X_l on the VALU (P FMA per
+        # channel); the message (C BF16) written once per edge; h~_j read once per atom
+        d["edge_fwd_t2"] = (2 * (mlp12 + mlp3) + 2.0 * nlm * C, 2.0 * P * C, ev + src + 2 * C,
+                            8 + nlm * C * fb)
+        # A_i = sum over the row of the messages: C BF16 read per edge, C FP32 written per atom
+        d["edge_sum_t2"] = (0.0, 1.0 * C, 2 * C, 8 + 4 * C)
     return d
 
 

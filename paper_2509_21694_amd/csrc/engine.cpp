@@ -312,6 +312,13 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
           const int nn = (2 * pp.l1 + 1) * (2 * pp.l2 + 1) * (2 * pp.l3 + 1);
           std::vector<double> tmp(nn);
           if (!coupling_tensor(pp.l1, pp.l2, pp.l3, tmp.data())) { st = fail(MPIP_EINVAL, "coupling"); goto done; }
+          if (pp.l3 == 0) {
+            // the last-layer kernels use only the diagonal of a (l, l, 0) coupling
+            const int n1 = 2 * pp.l1 + 1;
+            for (int a = 0; a < n1; ++a)
+              for (int b2 = 0; b2 < n1; ++b2)
+                if (a != b2 && tmp[a * n1 + b2] != 0.0) { st = fail(MPIP_EINVAL, "(l, l, 0) coupling not diagonal"); goto done; }
+          }
           for (double v : tmp) cgv.push_back((float)v);
         }
         const void* cgp;
@@ -462,6 +469,7 @@ struct Plan {
       o_info_s, o_spec, o_owned, o_cnt, o_row, o_blk, o_esrc, o_eshift, o_evec, o_erev, o_edst, o_g;
   size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
   size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
+  size_t o_msg = 0; // last-layer messages of the BF16 form, [max_edges][C] bf16
   std::vector<size_t> o_ht, o_z0, o_zl;  // per layer 1..K (index t-1)
   int max_bins;
   int nblocks_out;
@@ -516,6 +524,7 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
     }
     if ((C == 64 || C == 128) && S * nlm <= 64 && K >= 2)
       p.o_qp = take(cur, sizeof(float) * N * nlm * 64 * S);
+    if ((C == 64 || C == 128) && K >= 2) p.o_msg = take(cur, sizeof(uint16_t) * cap * C);
     p.o_atom_e = take(cur, sizeof(double) * N);
     p.nblocks_out = (int)((N + 255) / 256);
     p.o_partials = take(cur, sizeof(double) * 10 * p.nblocks_out);
@@ -703,6 +712,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   fa.n = N; fa.row_ptr = b.row_ptr; fa.e_src = b.e_src; fa.e_dst = b.e_dst; fa.e_rev = b.e_rev; fa.e_vec = b.e_vec; fa.capacity = max_edges;
   fa.status = b.status; fa.rc = (float)hp.r_cut; fa.envelope_p = hp.envelope_p; fa.n_species = S;
   fa.inv_n = (float)hp.inv_avg_neighbors; fa.Q = qp; fa.P = qp; fa.g = g; fa.htbar = htbar;
+  fa.msg = p.o_msg ? (void*)(w + p.o_msg) : nullptr;
   auto set_fast = [&](const LayerDev& d, int role) {
     fa.w1a = d.w1a; fa.w2a = d.w2a; fa.w2b = d.w2b; fa.w1b = d.w1b; fa.w2f = d.w2f;
     fa.w3f = d.w3fp[role]; fa.w3t = d.w3t[role]; fa.w3b = d.w3bp[role]; fa.cg = d.cg[role];
@@ -741,7 +751,14 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         launch_l1(prec, L, true, fa, s);
       } else {
         fa.ht = ht; fa.A = A;
-        launch_l2(prec, C, L, 0, fa, s);
+        if (ht_bf16 && fa.msg) {
+          launch_l2(prec, C, L, 4, fa, s);
+          T.end(s);
+          T.begin("edge_sum_t" + std::to_string(t), s);
+          launch_l2(prec, C, L, 5, fa, s);
+        } else {
+          launch_l2(prec, C, L, 0, fa, s);
+        }
       }
     } else {
       ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;

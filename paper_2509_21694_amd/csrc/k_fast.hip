@@ -33,6 +33,16 @@ __device__ __forceinline__ short bfbits(float x) {
 }
 __device__ __forceinline__ float bf2f(unsigned short u) { return __uint_as_float(((unsigned)u) << 16); }
 
+// four floats to a BF16 operand of the K = 16 MFMA, converted in pairs
+__device__ __forceinline__ s16x4 pk4_bf16(f32x4 v) {
+  typedef __attribute__((ext_vector_type(2))) float f32x2;
+  typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+  const bf16x2 lo = __builtin_convertvector((f32x2){v[0], v[1]}, bf16x2);
+  const bf16x2 hi = __builtin_convertvector((f32x2){v[2], v[3]}, bf16x2);
+  const uint2 u = {__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)};
+  return __builtin_bit_cast(s16x4, u);
+}
+
 __device__ __forceinline__ f32x4 mfma_bf16_k16(s16x4 a, s16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -59,7 +69,9 @@ __device__ __forceinline__ void yc_first(const float* cg, const float* Y, float*
   }
 }
 
-// YC of the last-layer paths (l, l, 0): YC[l^2 + m] = sum_m2 C[m][m2][0] Y[l^2 + m2]
+// YC of the last-layer paths (l, l, 0).  Coupling two degree-l harmonics to
+// a scalar is diagonal in m (the model is rejected otherwise when it is
+// created), so YC[l^2 + m] = C[m][m][0] Y[l^2 + m].
 template <int L>
 __device__ __forceinline__ void yc_last(const float* cg, const float* Y, float* yc) {
   int off = 0;
@@ -67,17 +79,12 @@ __device__ __forceinline__ void yc_last(const float* cg, const float* Y, float* 
   for (int l = 0; l <= L; ++l) {
     const int n = 2 * l + 1;
 #pragma unroll
-    for (int m = 0; m < n; ++m) {
-      float s = 0.f;
-#pragma unroll
-      for (int m2 = 0; m2 < n; ++m2) s += cg[off + m * n + m2] * Y[l * l + m2];
-      yc[l * l + m] = s;
-    }
+    for (int m = 0; m < n; ++m) yc[l * l + m] = cg[off + m * n + m] * Y[l * l + m];
     off += n * n;
   }
 }
 
-// adjoint of yc_last: Ybar[l^2 + m2] = sum_m C[m][m2][0] ycbar[l^2 + m]
+// adjoint of yc_last: Ybar[l^2 + m] = C[m][m][0] ycbar[l^2 + m]
 template <int L>
 __device__ __forceinline__ void yc_last_adj(const float* cg, const float* ycb, float* Yb) {
   int off = 0;
@@ -85,12 +92,7 @@ __device__ __forceinline__ void yc_last_adj(const float* cg, const float* ycb, f
   for (int l = 0; l <= L; ++l) {
     const int n = 2 * l + 1;
 #pragma unroll
-    for (int m2 = 0; m2 < n; ++m2) {
-      float s = 0.f;
-#pragma unroll
-      for (int m = 0; m < n; ++m) s += cg[off + m * n + m2] * ycb[l * l + m];
-      Yb[l * l + m2] = s;
-    }
+    for (int m = 0; m < n; ++m) Yb[l * l + m] = cg[off + m * n + m] * ycb[l * l + m];
     off += n * n;
   }
 }
@@ -241,11 +243,15 @@ struct DsPack {
   bf16x8 v[2];
 };
 __device__ __forceinline__ DsPack ds_pack(const f32x4* p) {
+  typedef __attribute__((ext_vector_type(8))) float f32x8;
   DsPack d;
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int h = 0; h < 2; ++h) {
+    f32x8 x;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) d.v[mt / 2][(mt % 2) * 4 + r] = (__bf16)dsilu(p[mt][r]);
+    for (int q = 0; q < 8; ++q) x[q] = dsilu(p[2 * h + q / 4][q % 4]);
+    d.v[h] = __builtin_convertvector(x, bf16x8);
+  }
   return d;
 }
 
@@ -1150,11 +1156,24 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       wave_lds_sync();
       // pull operands: A[lm = el][k-slot 4g + j] = YC_{e'}[lm] of edge 4g + j
       // (1/n_avg is already in the products with dA_j)
-      float yt[4];
+      s16x4 ya[L + 1];
+      {
+        float yt[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) yt[r] = syc[(4 * g + r) * 17 + el];
+        for (int r = 0; r < 4; ++r) yt[r] = syc[(4 * g + r) * 17 + el];
+#pragma unroll
+        for (int l = 0; l <= L; ++l) {
+          const bool mine = el >= l * l && el < (l + 1) * (l + 1);
+          const bf16x4 v = {(__bf16)(mine ? yt[0] : 0.f), (__bf16)(mine ? yt[1] : 0.f), (__bf16)(mine ? yt[2] : 0.f),
+                            (__bf16)(mine ? yt[3] : 0.f)};
+          ya[l] = __builtin_bit_cast(s16x4, v);
+        }
+      }
       wave_lds_sync();
-      f32x4 dy = {0.f, 0.f, 0.f, 0.f};
+      // dE/dYC accumulated per degree (rows of the other degrees are discarded)
+      f32x4 dy[L + 1];
+#pragma unroll
+      for (int l = 0; l <= L; ++l) dy[l] = (f32x4){0.f, 0.f, 0.f, 0.f};
       float4 an0 = *(const float4*)Aj, an1 = *(const float4*)(Aj + 4);
       bf16x8 hn = *(const bf16x8*)(hi + (int64_t)(el < NLM ? el : 0) * C + 8 * g);
       static_for<NK>([&](auto kk) {
@@ -1171,7 +1190,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }
         static_for<L + 1>([&](auto lc) {
           constexpr int l = decltype(lc)::value;
-          if constexpr (l > 0) __builtin_amdgcn_sched_barrier(0);
           float R8[8], X8[8];
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh) {
@@ -1191,19 +1209,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
           // MLP adjoint through layer 3
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt) ab2[mt] = O::mma(sWB[((l * 4 + mt) * KCC + k) * 64 + lane], rb, ab2[mt]);
-          // dE/dYC: D[lm][edge] += ht_i[lm][chunk] (R dA)[chunk][edge], rows of degree l only
-          const bool mine = el >= l * l && el < (l + 1) * (l + 1);
-          const bf16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
-          dy = O::mma(mine ? hr : z8, ra, dy);
+          // dE/dYC: D[lm][edge] += ht_i[lm][chunk] (R dA)[chunk][edge]
+          dy[l] = O::mma(hr, ra, dy[l]);
           // pull: transpose (R dA) to edges x channels, then sum over the tile's edges
-          s16x4 ya;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) ya[r] = mine ? bfbits(yt[r]) : (short)0;
 #pragma unroll
           for (int tt = 0; tt < 2; ++tt) {
             const f32x4 tr = O::mma(ra, sel[tt], (f32x4){0.f, 0.f, 0.f, 0.f});
-            const s16x4 bv = {bfbits(tr[0]), bfbits(tr[1]), bfbits(tr[2]), bfbits(tr[3])};
-            hb[k][tt] = mfma_bf16_k16(ya, bv, hb[k][tt]);
+            hb[k][tt] = mfma_bf16_k16(ya[l], pk4_bf16(tr), hb[k][tt]);
           }
         });
       });
@@ -1211,7 +1223,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       // dE/dYC of edge el: rows 4g + r live in lane el + 16 g
       float ycb[NLM];
 #pragma unroll
-      for (int lm = 0; lm < NLM; ++lm) ycb[lm] = __shfl(dy[lm % 4], el + 16 * (lm / 4));
+      for (int lm = 0; lm < NLM; ++lm) {
+        const int l = lm < 1 ? 0 : (lm < 4 ? 1 : (lm < 9 ? 2 : 3));
+        ycb[lm] = __shfl(dy[l][lm % 4], el + 16 * (lm / 4));
+      }
       float eb[kNB];
       mlp_backward_ds(ab2, d1, d2, lane, sB2, sB1, eb);
       if (lane < kTileE && valid) {
@@ -1242,6 +1257,169 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       }
     }
     wave_lds_sync();
+  }
+}
+
+// Forward of the last layer (BF16 form), sender side.  Rows j are walked as
+// in the fused adjoint; each edge e' = (j <- i) of row j stands for its
+// reverse e = (i <- j), whose sender is the row's own atom, and its message
+//   m_e[c] = sum_l R_e[l, c] X_e[l, c],  X_e[l, c] = sum_m YC_e[lm] ht_j[lm, c]
+// (X a 16x16x16 MFMA of the row's transposed features, as in the adjoint) is
+// written in BF16 to the receiver-side slot M[rev(e')] in row i of the CSR.
+// A_i = sum_{e in row i} m_e / n_avg is then a contiguous segmented sum.
+template <int C, int L, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void k_l2_msg(FastArgs a) {
+  typedef Op<1> O;
+  constexpr int NLM = (L + 1) * (L + 1);
+  constexpr int NK = C / 32, CN = C / 16;
+  constexpr int HT = (NLM + 3) / 4 * 4, NG = HT / 4;
+  __shared__ bf16x8 sW[(L + 1) * CN * 2 * 64];
+  __shared__ bf16x8 sM1[4 * 64], sM2[4 * 2 * 64];
+  __shared__ unsigned sHT[NW][C * HT / 2];
+  if (fast_guard(a)) return;
+  stage_lds<bf16x8, (L + 1) * CN * 2 * 64>(sW, a.w3t);
+  stage_lds<bf16x8, 4 * 64>(sM1, a.w1a);
+  stage_lds<bf16x8, 4 * 2 * 64>(sM2, a.w2a);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
+  unsigned* sh = sHT[wv];
+  const unsigned short* ht = (const unsigned short*)a.ht;
+  unsigned short* M = (unsigned short*)a.msg;
+  const RowWalk rw = row_walk<NW>(a.n);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
+    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+    const unsigned short* hi = ht + (int64_t)i * NLM * C;
+    // the row's features, transposed: sh[c][lm] (degrees NLM .. HT-1 zero)
+#pragma unroll
+    for (int p0 = 0; p0 < C / 2; p0 += 64) {
+      const int p = p0 + lane;
+      if (p < C / 2) {
+#pragma unroll
+        for (int q = 0; q < HT / 2; ++q) {
+          const unsigned u0 = (2 * q < NLM) ? *(const unsigned*)(hi + (2 * q) * C + 2 * p) : 0u;
+          const unsigned u1 = (2 * q + 1 < NLM) ? *(const unsigned*)(hi + (2 * q + 1) * C + 2 * p) : 0u;
+          sh[(2 * p) * (HT / 2) + q] = (u0 & 0xffffu) | (u1 << 16);
+          sh[(2 * p + 1) * (HT / 2) + q] = (u0 >> 16) | (u1 & 0xffff0000u);
+        }
+      }
+    }
+    wave_lds_sync();
+    auto hx_op = [&](int mt) -> s16x4 {
+      const int ch = 32 * (mt / 2) + 8 * (el / 4) + 4 * (mt % 2) + (el % 4);
+      const uint2 v = *(const uint2*)(sh + ch * (HT / 2) + 2 * (g < NG ? g : 0));
+      return (g < NG) ? __builtin_bit_cast(s16x4, v) : (s16x4){0, 0, 0, 0};
+    };
+    for (int t0 = e0; t0 < e1; t0 += kTileE) {
+      const int e = t0 + el;
+      const bool valid = e < e1;
+      const int rv = valid ? a.e_rev[e] : -1;
+      Geo geo;
+      const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
+      edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, a.rc, a.envelope_p, geo);
+      float yc[NLM];
+      yc_last<L>(a.cg, geo.Y, yc);
+      s16x4 yop[L + 1];
+#pragma unroll
+      for (int l = 0; l <= L; ++l)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          float w = 0.f;
+#pragma unroll
+          for (int gg = 0; gg < 4; ++gg) {
+            const int lm = 4 * gg + jj;
+            if (lm >= l * l && lm < (l + 1) * (l + 1)) w = (g == gg) ? yc[lm] : w;
+          }
+          yop[l][jj] = bfbits(w);
+        }
+      bf16x8 bop[2];
+      {
+        f32x4 p1[4], p2[4], a2[4];
+        mlp_forward_w<1>(geo, lane, sM1, sM2, p1, p2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) bop[kc] = O::from_tiles(a2, kc);
+      }
+      unsigned short* dst = M + (int64_t)(rv < 0 ? 0 : rv) * C + 8 * g;
+      static_for<NK>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        __builtin_amdgcn_sched_barrier(0);
+        const s16x4 hx[2] = {hx_op(2 * k), hx_op(2 * k + 1)};
+        float m8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m8[q] = 0.f;
+#pragma unroll
+        for (int l = 0; l <= L; ++l) {
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) d = O::mma(sW[((l * CN + 2 * k + hh) * 2 + kc) * 64 + lane], bop[kc], d);
+            const f32x4 x = mfma_bf16_k16(hx[hh], yop[l], (f32x4){0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int r = 0; r < 4; ++r) m8[4 * hh + r] += d[r] * x[r];
+          }
+        }
+        typedef __attribute__((ext_vector_type(8))) float f32x8;
+        f32x8 mv;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) mv[q] = m8[q];
+        if (rv >= 0) *(bf16x8*)(dst + 32 * k) = __builtin_convertvector(mv, bf16x8);
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_lds_sync();
+  }
+}
+
+// A_i[c] = sum_{e in row i} M[e][c] / n_avg: one wave per row, C/8 lanes per
+// edge (8 channels each), 64/(C/8) edges per load, partial sums combined
+// across the lane groups at the end.
+template <int C>
+__global__ __launch_bounds__(256) void k_l2_msum(FastArgs a) {
+  constexpr int LPE = C / 8, EPI = 64 / LPE;
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (fast_guard(a) || i >= a.n) return;
+  const int lane = threadIdx.x & 63, s = lane / LPE, c8 = lane % LPE;
+  const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+  const unsigned short* M = (const unsigned short*)a.msg + 8 * c8;
+  float acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.f;
+  int e = e0 + s;
+  for (; e + 3 * EPI < e1; e += 4 * EPI) {
+    uint4 u[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) u[b] = *(const uint4*)(M + (int64_t)(e + b * EPI) * C);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const unsigned w[4] = {u[b].x, u[b].y, u[b].z, u[b].w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc[2 * t] += __uint_as_float(w[t] << 16);
+        acc[2 * t + 1] += __uint_as_float(w[t] & 0xffff0000u);
+      }
+    }
+  }
+  for (; e < e1; e += EPI) {
+    const uint4 u = *(const uint4*)(M + (int64_t)e * C);
+    const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[2 * t] += __uint_as_float(w[t] << 16);
+      acc[2 * t + 1] += __uint_as_float(w[t] & 0xffff0000u);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int o = LPE; o < 64; o <<= 1) acc[q] += __shfl_xor(acc[q], o);
+  if (s == 0) {
+    float* dst = a.A + i * C + 8 * c8;
+    *(float4*)dst = make_float4(a.inv_n * acc[0], a.inv_n * acc[1], a.inv_n * acc[2], a.inv_n * acc[3]);
+    *(float4*)(dst + 4) = make_float4(a.inv_n * acc[4], a.inv_n * acc[5], a.inv_n * acc[6], a.inv_n * acc[7]);
   }
 }
 
@@ -1295,7 +1473,11 @@ static void l2_launch(int which, const FastArgs& a, hipStream_t s) {
   if (which == 0) k_l2_fwd<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
   else if (which == 1) k_l2_bwd_a<PREC, C, L, NWA><<<l2_grid(a.n, NWA, pa), 64 * NWA, 0, s>>>(a);
   else if (which == 2) k_l2_bwd_b<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
-  else if constexpr (PREC == 1) k_l2_adj<C, L, 8><<<l2_grid(a.n, 8, 32), 64 * 8, 0, s>>>(a);
+  else if constexpr (PREC == 1) {
+    if (which == 3) k_l2_adj<C, L, 8><<<l2_grid(a.n, 8, 32), 64 * 8, 0, s>>>(a);
+    else if (which == 4) k_l2_msg<C, L, 12><<<l2_grid(a.n, 12, C == 128 ? 32 : 64), 64 * 12, 0, s>>>(a);
+    else k_l2_msum<C><<<(unsigned)((a.n + 3) / 4), 256, 0, s>>>(a);
+  }
 }
 
 template <int PREC>

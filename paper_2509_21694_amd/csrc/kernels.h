@@ -141,11 +141,13 @@ struct FastArgs {
   float* htbar;          // last layer adjoint output: [N][nlm][C]
   int htbar_bf16;        // 1: htbar stored as bf16 (same element offsets)
   float4* g;
+  void* msg;             // last layer forward, BF16 form: messages [E][C] bf16 in CSR order
 };
 
 void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s);
 // which: 0 forward, 1 adjoint (dR, dY, MLP), 2 adjoint (sender-side pull),
-// 3 both adjoints fused over the reverse edges (BF16 form only)
+// 3 both adjoints fused over the reverse edges, 4 forward as sender-side
+// messages, 5 their segmented sum into A (3, 4 and 5: BF16 form only)
 void launch_l2(int prec, int C, int L, int which, const FastArgs& a, hipStream_t s);
 
 struct EdgeArgs {

@@ -35,7 +35,8 @@ def sources_sha256(root):
 PHASES = {
     "edge_fwd_t1": r"k_l1_fwd<1,",
     "edge_bwd_t1": r"k_l1_bwd<1,",
-    "edge_fwd_t2": r"k_l2_fwd<1,",
+    "edge_fwd_t2": r"k_l2_msg<",
+    "edge_sum_t2": r"k_l2_msum<",
     "edge_bwd_t2": r"k_l2_adj<",
 }
 COPY = r"copyBuffer"
