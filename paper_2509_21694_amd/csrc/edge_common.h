@@ -78,12 +78,41 @@ struct Geo {
   float dbasis[kNB];
 };
 
+// sin t and cos t for t in [0, pi]: Taylor polynomials (through x^13 and
+// x^14) of the reduced argument x = min(t, pi - t) in [0, pi/2], whose
+// truncation error is below 1e-9; sin(pi - x) = sin x, cos(pi - x) = -cos x.
+__device__ __forceinline__ void sincos_0pi(float t, float* s, float* c) {
+  const bool up = t > 1.5707963267948966f;
+  const float x = up ? 3.14159265358979f - t : t, x2 = x * x;
+  float ps = 1.f / 6227020800.f;
+  ps = fmaf(ps, x2, -1.f / 39916800.f);
+  ps = fmaf(ps, x2, 1.f / 362880.f);
+  ps = fmaf(ps, x2, -1.f / 5040.f);
+  ps = fmaf(ps, x2, 1.f / 120.f);
+  ps = fmaf(ps, x2, -1.f / 6.f);
+  ps = fmaf(ps, x2, 1.f);
+  float pc = -1.f / 87178291200.f;
+  pc = fmaf(pc, x2, 1.f / 479001600.f);
+  pc = fmaf(pc, x2, -1.f / 3628800.f);
+  pc = fmaf(pc, x2, 1.f / 40320.f);
+  pc = fmaf(pc, x2, -1.f / 720.f);
+  pc = fmaf(pc, x2, 1.f / 24.f);
+  pc = fmaf(pc, x2, -0.5f);
+  pc = fmaf(pc, x2, 1.f);
+  *s = x * ps;
+  *c = up ? -pc : pc;
+}
+
 // Tail lanes of a tile (valid == false) evaluate a unit vector along x and
-// are zeroed at the end, so the code has no divergent branch.
+// are zeroed at the end, so the code has no divergent branch.  The cutoff
+// enters through 1/r_c (one division per kernel, hoisted out of the loops);
+// the Bessel argument pi d / r_c lies in [0, pi] for every edge.
 __device__ __forceinline__ void edge_geometry(float4 v, bool valid, float rc, int p, Geo& g) {
   const float vx = valid ? v.x : 1.f, vy = valid ? v.y : 0.f, vz = valid ? v.z : 0.f;
-  const float d = sqrtf(vx * vx + vy * vy + vz * vz);
-  const float inv = __builtin_amdgcn_rcpf(d);
+  // |v| and 1/|v| from the hardware reciprocal square root (about 1 ulp)
+  const float d2 = vx * vx + vy * vy + vz * vz;
+  const float inv = __builtin_amdgcn_rsqf(d2);
+  const float d = d2 * inv;
   const float x = vx * inv, y = vy * inv, z = vz * inv;
   const float msk = valid ? 1.f : 0.f;
   g.u[0] = msk * x; g.u[1] = msk * y; g.u[2] = msk * z; g.d = d;
@@ -93,25 +122,25 @@ __device__ __forceinline__ void edge_geometry(float4 v, bool valid, float rc, in
   g.Y[4] = msk * s15 * x * y; g.Y[5] = msk * s15 * y * z; g.Y[6] = msk * 0.5f * s5 * (3.f * z * z - 1.f);
   g.Y[7] = msk * s15 * x * z; g.Y[8] = msk * 0.5f * s15 * (x * x - y * y);
   // polynomial envelope of order p (zero from r_c on)
-  const float xr = d / rc;
+  const float irc = 1.0f / rc;
+  const float xr = d * irc;
   const float a = 0.5f * (p + 1) * (p + 2), b = (float)(p * (p + 2)), c = 0.5f * p * (p + 1);
   float xp1 = 1.f;  // x^(p-1)
   for (int k = 0; k < p - 1; ++k) xp1 *= xr;
   const float xp = xp1 * xr, xq = xp * xr, xs = xq * xr;
   const float in = (valid && xr < 1.f) ? 1.f : 0.f;
   const float env = in * (1.f - a * xp + b * xq - c * xs);
-  const float denv = in * (-a * p * xp1 + b * (p + 1) * xp - c * (p + 2) * xq) / rc;
+  const float denv = in * (-a * p * xp1 + b * (p + 1) * xp - c * (p + 2) * xq) * irc;
   // Bessel basis via the Chebyshev recurrence for sin(n t), cos(n t)
-  const float pref = sqrtf(2.0f / rc);
-  const float th = 3.14159265358979f * d / rc;
+  const float pref = sqrtf(2.0f * irc);
+  const float th = fminf(3.14159265358979f * xr, 3.14159265358979f);
   float s1, c1;
-  sincosf(th, &s1, &c1);
+  sincos_0pi(th, &s1, &c1);
   float sp = 0.f, cp = 1.f, sn = s1, cn = c1;
 #pragma unroll
   for (int n = 1; n <= kNB; ++n) {
-    const float kn = n * 3.14159265358979f / rc;
     const float B = pref * sn * inv;
-    const float dB = pref * (kn * d * cn - sn) * inv * inv;
+    const float dB = pref * ((float)n * th * cn - sn) * inv * inv;
     g.basis[n - 1] = env * B;
     g.dbasis[n - 1] = denv * B + env * dB;
     const float sx = 2.f * c1 * sn - sp, cx = 2.f * c1 * cn - cp;

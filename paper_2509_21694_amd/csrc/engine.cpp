@@ -312,12 +312,13 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
           const int nn = (2 * pp.l1 + 1) * (2 * pp.l2 + 1) * (2 * pp.l3 + 1);
           std::vector<double> tmp(nn);
           if (!coupling_tensor(pp.l1, pp.l2, pp.l3, tmp.data())) { st = fail(MPIP_EINVAL, "coupling"); goto done; }
-          if (pp.l3 == 0) {
-            // the last-layer kernels use only the diagonal of a (l, l, 0) coupling
-            const int n1 = 2 * pp.l1 + 1;
+          if (pp.l3 == 0 || pp.l1 == 0) {
+            // the specialised first- and last-layer kernels use only the
+            // diagonal of a (0, l, l) or (l, l, 0) coupling
+            const int n1 = 2 * std::max(pp.l1, pp.l3) + 1;
             for (int a = 0; a < n1; ++a)
               for (int b2 = 0; b2 < n1; ++b2)
-                if (a != b2 && tmp[a * n1 + b2] != 0.0) { st = fail(MPIP_EINVAL, "(l, l, 0) coupling not diagonal"); goto done; }
+                if (a != b2 && tmp[a * n1 + b2] != 0.0) { st = fail(MPIP_EINVAL, "scalar coupling not diagonal"); goto done; }
           }
           for (double v : tmp) cgv.push_back((float)v);
         }

@@ -51,68 +51,45 @@ __device__ __forceinline__ bool fast_guard(const FastArgs& a) {
   return (int64_t)a.row_ptr[a.n] > a.capacity || a.status[ST_FLAGS] != 0;
 }
 
-// YC of the first-layer paths (0, l, l): YC[l^2 + m] = sum_m2 C[0][m2][m] Y[l^2 + m2]
+// The couplings of the specialised layers are diagonal in m: a scalar with a
+// degree-l harmonic to degree l (first layer, paths (0, l, l)) and two
+// degree-l harmonics to a scalar (last layer, paths (l, l, 0)); the model is
+// rejected otherwise when it is created.  Only the diagonal is used, read
+// once per wave into scalar registers.
 template <int L>
-__device__ __forceinline__ void yc_first(const float* cg, const float* Y, float* yc) {
+struct CgDiag {
+  float c[(L + 1) * (L + 1)];
+};
+template <int L>
+__device__ __forceinline__ CgDiag<L> cg_diag(const float* cg) {
+  CgDiag<L> d;
   int off = 0;
 #pragma unroll
   for (int l = 0; l <= L; ++l) {
     const int n = 2 * l + 1;
 #pragma unroll
-    for (int m = 0; m < n; ++m) {
-      float s = 0.f;
-#pragma unroll
-      for (int m2 = 0; m2 < n; ++m2) s += cg[off + m2 * n + m] * Y[l * l + m2];
-      yc[l * l + m] = s;
-    }
+    for (int m = 0; m < n; ++m)
+      d.c[l * l + m] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cg[off + m * n + m])));
     off += n * n;
   }
+  return d;
 }
 
-// YC of the last-layer paths (l, l, 0).  Coupling two degree-l harmonics to
-// a scalar is diagonal in m (the model is rejected otherwise when it is
-// created), so YC[l^2 + m] = C[m][m][0] Y[l^2 + m].
+// YC of the specialised layers' paths: YC[l^2 + m] = C[m][m] Y[l^2 + m] (diagonal of
+// the coupling of path l)
 template <int L>
-__device__ __forceinline__ void yc_last(const float* cg, const float* Y, float* yc) {
-  int off = 0;
+__device__ __forceinline__ void yc_last(const CgDiag<L>& cd, const float* Y, float* yc) {
 #pragma unroll
-  for (int l = 0; l <= L; ++l) {
-    const int n = 2 * l + 1;
-#pragma unroll
-    for (int m = 0; m < n; ++m) yc[l * l + m] = cg[off + m * n + m] * Y[l * l + m];
-    off += n * n;
-  }
+  for (int k = 0; k < (L + 1) * (L + 1); ++k) yc[k] = cd.c[k] * Y[k];
 }
 
-// adjoint of yc_last: Ybar[l^2 + m] = C[m][m][0] ycbar[l^2 + m]
+// adjoint of yc_last: Ybar[l^2 + m] = C[m][m] ycbar[l^2 + m]
 template <int L>
-__device__ __forceinline__ void yc_last_adj(const float* cg, const float* ycb, float* Yb) {
-  int off = 0;
+__device__ __forceinline__ void yc_last_adj(const CgDiag<L>& cd, const float* ycb, float* Yb) {
 #pragma unroll
-  for (int l = 0; l <= L; ++l) {
-    const int n = 2 * l + 1;
-#pragma unroll
-    for (int m = 0; m < n; ++m) Yb[l * l + m] = cg[off + m * n + m] * ycb[l * l + m];
-    off += n * n;
-  }
+  for (int k = 0; k < (L + 1) * (L + 1); ++k) Yb[k] = cd.c[k] * ycb[k];
 }
 
-template <int L>
-__device__ __forceinline__ void yc_first_adj(const float* cg, const float* ycb, float* Yb) {
-  int off = 0;
-#pragma unroll
-  for (int l = 0; l <= L; ++l) {
-    const int n = 2 * l + 1;
-#pragma unroll
-    for (int m2 = 0; m2 < n; ++m2) {
-      float s = 0.f;
-#pragma unroll
-      for (int m = 0; m < n; ++m) s += cg[off + m2 * n + m] * ycb[l * l + m];
-      Yb[l * l + m2] = s;
-    }
-    off += n * n;
-  }
-}
 
 // geometry backward: g_e += dbar u + (I - u u^T)/d (dP/du)^T Ybar
 __device__ __forceinline__ void add_edge_grad(float4* g, int e, const Geo& geo, const float* ebar, const float* Yb) {
@@ -298,6 +275,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   __shared__ float sY[NW][kTileE * NLM];
   __shared__ int sS[NW][kTileE];
   if (fast_guard(a)) return;
+  const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NM1>(sM1, a.w1a);
     stage_lds<typename O::T, NM2>(sM2, a.w2f);
@@ -323,7 +301,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
       if (g == 0) {
         float yc[NLM];
-        yc_first<L>(a.cg, geo.Y, yc);
+        yc_last<L>(cgd, geo.Y, yc);
 #pragma unroll
         for (int k = 0; k < NLM; ++k) syc[el * NLM + k] = yc[k];
         ssp[el] = valid ? __float_as_int(v.w) : -1;
@@ -421,6 +399,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int SYB = 16 * MQ + 1;   // odd row stride: the 16 edge lanes hit distinct banks
   __shared__ float sYB[NW][kTileE * SYB];
   if (fast_guard(a)) return;
+  const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NM1>(sM1, a.w1a);
     stage_lds<typename O::T, NM2>(sM2, a.w2a);
@@ -513,7 +492,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
       const int sp = valid ? __float_as_int(v.w) : -1;
       float yc[NLM];
-      yc_first<L>(a.cg, geo.Y, yc);
+      yc_last<L>(cgd, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4], ab2[4];
       if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
       else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
@@ -565,7 +544,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
 #pragma unroll
         for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + sp * NLM + k];
-        yc_first_adj<L>(a.cg, ycb, Yb);
+        yc_last_adj<L>(cgd, ycb, Yb);
         add_edge_grad(a.g, e, geo, eb, Yb);
       }
       wave_lds_sync();
@@ -664,6 +643,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   __shared__ typename O::T sM1[NM1], sM2[NM2];
   __shared__ typename O::T sW[NWT];
   if (fast_guard(a)) return;
+  const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3t);
     stage_lds<typename O::T, NM1>(sM1, a.w1a);
@@ -700,7 +680,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
       float yc[NLM];
-      yc_last<L>(a.cg, geo.Y, yc);
+      yc_last<L>(cgd, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4];
       if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
       else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
@@ -774,6 +754,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
   __shared__ typename O::T sB2[NB2], sB1[NB1];
   if (fast_guard(a)) return;
+  const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3t);
     stage_lds<typename O::T, NWB>(sWB, a.w3b);
@@ -818,7 +799,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
       float yc[NLM];
-      yc_last<L>(a.cg, geo.Y, yc);
+      yc_last<L>(cgd, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4], ab2[4];
       if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
       else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
@@ -897,7 +878,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         float Yb[kMaxNlm];
 #pragma unroll
         for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
-        yc_last_adj<L>(a.cg, ycb, Yb);
+        yc_last_adj<L>(cgd, ycb, Yb);
         add_edge_grad(a.g, e, geo, eb, Yb);
       }
     }
@@ -920,6 +901,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   __shared__ typename O::T sW[NWT];
   __shared__ float sY[NW][kTileE * 17];   // odd row stride against bank conflicts
   if (fast_guard(a)) return;
+  const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3f);
     stage_lds<typename O::T, NM1>(sM1, a.w1a);
@@ -955,7 +937,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       edge_geometry(v, valid, a.rc, a.envelope_p, geo);
       if (g == 0) {
         float yc[NLM];
-        yc_last<L>(a.cg, geo.Y, yc);
+        yc_last<L>(cgd, geo.Y, yc);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           float val = 0.f;
@@ -1064,6 +1046,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
   __shared__ unsigned sHT[NW][C * HT / 2];
   __shared__ float sY[NW][kTileE * 17];
   if (fast_guard(a)) return;
+  const CgDiag<L> cgd = cg_diag<L>(a.cg);
   stage_lds<bf16x8, (L + 1) * CN * 2 * 64>(sW, a.w3t);
   stage_lds<bf16x8, (L + 1) * 4 * KCC * 64>(sWB, a.w3b);
   stage_lds<bf16x8, 4 * 64>(sM1, a.w1a);
@@ -1119,7 +1102,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
       edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, a.rc, a.envelope_p, geo);
       float yc[NLM];
-      yc_last<L>(a.cg, geo.Y, yc);
+      yc_last<L>(cgd, geo.Y, yc);
       if (g == 0) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) syc[el * 17 + k] = k < NLM ? yc[k] : 0.f;
@@ -1233,7 +1216,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         float Yb[kMaxNlm];
 #pragma unroll
         for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
-        yc_last_adj<L>(a.cg, ycb, Yb);
+        yc_last_adj<L>(cgd, ycb, Yb);
         const int rv = a.e_rev[e];
         if (rv >= 0) add_edge_grad(a.g, rv, geo, eb, Yb);
       }
@@ -1277,6 +1260,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
   __shared__ bf16x8 sM1[4 * 64], sM2[4 * 2 * 64];
   __shared__ unsigned sHT[NW][C * HT / 2];
   if (fast_guard(a)) return;
+  const CgDiag<L> cgd = cg_diag<L>(a.cg);
   stage_lds<bf16x8, (L + 1) * CN * 2 * 64>(sW, a.w3t);
   stage_lds<bf16x8, 4 * 64>(sM1, a.w1a);
   stage_lds<bf16x8, 4 * 2 * 64>(sM2, a.w2a);
@@ -1317,7 +1301,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
       const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
       edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, a.rc, a.envelope_p, geo);
       float yc[NLM];
-      yc_last<L>(a.cg, geo.Y, yc);
+      yc_last<L>(cgd, geo.Y, yc);
       s16x4 yop[L + 1];
 #pragma unroll
       for (int l = 0; l <= L; ++l)
