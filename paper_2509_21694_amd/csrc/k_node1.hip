@@ -93,14 +93,54 @@ struct PairStore {
   }
 };
 
+// whole-block copy of NT operand tiles (64 lanes x 16 B each) into LDS
+template <int NT>
+__device__ __forceinline__ void stage_tiles(bf16x8* dst, const bf16x8* src) {
+  for (int t = threadIdx.x; t < NT * 64; t += blockDim.x) dst[t] = src[t];
+}
+
+// D tiles mt = 0..MT-1 of W x B with W's A-operand tiles in LDS at
+// W[(mt * KS + k0 + kc) * 64 + lane] (kc < KC) and B as KC operands; the
+// operand reads run PF tiles ahead of the MFMAs, and each finished tile is
+// handed to consume(mt, d)
+template <int MT, int KC, typename F>
+__device__ __forceinline__ void lds_rows(const bf16x8* W, int KS, int k0, const bf16x8* B, int lane, F&& consume) {
+  constexpr int T = MT * KC, PF = 4;
+  auto ld = [&](int i) { return W[((i / KC) * KS + k0 + i % KC) * 64 + lane]; };
+  bf16x8 buf[PF];
+#pragma unroll
+  for (int i = 0; i < PF && i < T; ++i) buf[i] = ld(i);
+  f32x4 d = {0.f, 0.f, 0.f, 0.f};
+  unroll_impl([&](auto ic) {
+    constexpr int i = decltype(ic)::value, kc = i % KC;
+    if constexpr (kc == 0) __builtin_amdgcn_sched_barrier(0);
+    const bf16x8 w = buf[i % PF];
+    if constexpr (i + PF < T) buf[i % PF] = ld(i + PF);
+    d = mfma_bf16(w, B[kc], d);
+    if constexpr (kc == KC - 1) {
+      consume(i / KC, d);
+      d = (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
+  }, std::make_integer_sequence<int, T>{});
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Workgroups of 8 waves (128 atoms, 16 per wave).  Each stage's weights are
+// staged in LDS once per workgroup and read by all its waves, so a weight
+// tile crosses L2 once per 128 atoms; waves past the last atom still take
+// part in the staging and the barriers.
+constexpr int kN1Waves = 8;
+
 template <int C, int L, int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_node1_fwd(Node1Args a) {
+__global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(4))) void k_node1_fwd(Node1Args a) {
   constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, KCQ = KQ / 32, MTC = C / 16, KCC = C / 32;
+  constexpr int NVT = MTC * KCQ, NU = MTC * KCC;   // tiles of one z block of VW^T and of W_up^T
+  __shared__ bf16x8 sV[NVT * 64], sU[NU * 64];
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
-  const int64_t a0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  if (a0 >= a.n) return;
-  const bool av = a0 + n < a.n;
-  const int64_t at = av ? a0 + n : a.n - 1;
+  const int64_t a0 = ((int64_t)blockIdx.x * kN1Waves + (threadIdx.x >> 6)) * 16;
+  const bool act = a0 < a.n;
+  const bool av = act && a0 + n < a.n;
+  const int64_t at = av ? a0 + n : (act ? a.n - 1 : 0);
   const bf16x8* Q = (const bf16x8*)a.Q;   // [N][NLM][KQ / 8]
   const bf16x8* VT0 = (const bf16x8*)a.vwt[0];
   const int sp = a.spec_s[at];
@@ -108,84 +148,106 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int kc = 0; kc < KCQ; ++kc) qv[kc] = Q[((int64_t)at * NLM + lm) * (KQ / 8) + 4 * kc + g];
   };
-  // h~ rows of one (l, m): D tile mt, lane (g, n) holds output channel (C/4) g + 4 mt + r
-  auto up_store = [&](int l, int lm, const f32x4* h) {
-    const bf16x8* U = (const bf16x8*)a.upt[l];
+  // h~ rows of one (l, m) from the W_up^T tiles in sU: D tile mt, lane (g, n)
+  // holds output channel (C/4) g + 4 mt + r
+  auto up_store = [&](int lm, const f32x4* h) {
     bf16x8 hb[KCC];
 #pragma unroll
     for (int kc = 0; kc < KCC; ++kc) hb[kc] = tiles_to_op(h, kc);
     __bf16* dst = (__bf16*)a.ht + ((int64_t)at * NLM + lm) * C + (C / 4) * g;
     PairStore ps;
-    stream_rows<MTC, KCC>(U, 0, KCC, 0, hb, lane, [&](int mt, f32x4 d) {
+    lds_rows<MTC, KCC>(sU, KCC, 0, hb, lane, [&](int mt, f32x4 d) {
       if (av) ps.put(mt, d, dst);
     });
   };
   // scalars: h_0 = emb + SiLU(z_0[0:C])
-  {
+  stage_tiles<NVT>(sV, VT0);
+  stage_tiles<NU>(sU, (const bf16x8*)a.upt[0]);
+  __syncthreads();
+  if (act) {
     bf16x8 q0[KCQ];
     qload(0, q0);
     f32x4 z[MTC];
-    stream_rows<MTC, KCQ>(VT0, 0, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
+    lds_rows<MTC, KCQ>(sV, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
       const float4 e = *(const float4*)(a.emb + (int64_t)sp * C + 16 * mt + 4 * g);
       const float ev[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
       for (int r = 0; r < 4; ++r) z[mt][r] = ev[r] + silu(d[r]);
       if (av) *(float4*)(a.h + (int64_t)at * NLM * C + 16 * mt + 4 * g) = make_float4(z[mt][0], z[mt][1], z[mt][2], z[mt][3]);
     });
-    up_store(0, 0, z);
+    up_store(0, z);
   }
   // degrees l >= 1: h_lm = sigmoid(z_0[gate block l]) * z_lm
 #pragma unroll
   for (int l = 1; l <= L; ++l) {
+    __syncthreads();
+    stage_tiles<NVT>(sV, VT0 + (size_t)l * NVT * 64);
+    __syncthreads();
     f32x4 gt[MTC];
-    {
+    if (act) {
       bf16x8 q0[KCQ];
       qload(0, q0);
-      stream_rows<MTC, KCQ>(VT0, l * MTC, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
+      lds_rows<MTC, KCQ>(sV, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) gt[mt][r] = sigm(d[r]);
       });
     }
-    const bf16x8* VT = (const bf16x8*)a.vwt[l];
-    for (int m = 0; m < 2 * l + 1; ++m) {
-      const int lm = l * l + m;
-      bf16x8 ql[KCQ];
-      qload(lm, ql);
-      f32x4 z[MTC];
-      stream_rows<MTC, KCQ>(VT, 0, KCQ, 0, ql, lane, [&](int mt, f32x4 d) {
+    __syncthreads();
+    stage_tiles<NVT>(sV, (const bf16x8*)a.vwt[l]);
+    stage_tiles<NU>(sU, (const bf16x8*)a.upt[l]);
+    __syncthreads();
+    if (act) {
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        const int lm = l * l + m;
+        bf16x8 ql[KCQ];
+        qload(lm, ql);
+        f32x4 z[MTC];
+        lds_rows<MTC, KCQ>(sV, KCQ, 0, ql, lane, [&](int mt, f32x4 d) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) z[mt][r] = gt[mt][r] * d[r];
-      });
-      up_store(l, lm, z);
+          for (int r = 0; r < 4; ++r) z[mt][r] = gt[mt][r] * d[r];
+        });
+        up_store(lm, z);
+      }
     }
   }
 }
 
 template <int C, int L, int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_node1_bwd(Node1Args a) {
-  constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, KCQ = KQ / 32, MTC = C / 16, KCC = C / 32;
-  constexpr int MTP = KQ / 16, NZC = (1 + L) * KCC;   // P row tiles; k-chunks of z_0
+struct N1Bwd {
+  static constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, KCQ = KQ / 32, MTC = C / 16, KCC = C / 32;
+  static constexpr int MTP = KQ / 16, NZC = (1 + L) * KCC;   // P row tiles; k-chunks of z_0
+  static constexpr int NVT = MTC * KCQ, NU = MTC * KCC, NVW = MTP * KCC, NP0 = (MTP / 2) * NZC;
+  static constexpr int NT = (NVT + NU + NVW) > NP0 ? (NVT + NU + NVW) : NP0;   // LDS tiles
+};
+
+template <int C, int L, int S>
+__global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(2))) void k_node1_bwd(Node1Args a) {
+  typedef N1Bwd<C, L, S> D;
+  constexpr int NLM = D::NLM, KQ = D::KQ, KCQ = D::KCQ, MTC = D::MTC, KCC = D::KCC, MTP = D::MTP, NZC = D::NZC;
+  constexpr int NVT = D::NVT, NU = D::NU;
+  __shared__ bf16x8 sW[D::NT * 64];
+  bf16x8* sU = sW;                  // W_up_l (hbar rows)
+  bf16x8* sV = sW + NU * 64;        // a z block of VW^T
+  bf16x8* sP = sV + NVT * 64;       // VW_l (P rows)
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
-  const int64_t a0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  if (a0 >= a.n) return;
-  const bool av = a0 + n < a.n;
-  const int64_t at = av ? a0 + n : a.n - 1;
+  const int64_t a0 = ((int64_t)blockIdx.x * kN1Waves + (threadIdx.x >> 6)) * 16;
+  const bool act = a0 < a.n;
+  const bool av = act && a0 + n < a.n;
+  const int64_t at = av ? a0 + n : (act ? a.n - 1 : 0);
   const bf16x8* Q = (const bf16x8*)a.Q;
   const bf16x8* HB = (const bf16x8*)a.htbar;   // [N][NLM][C / 8]
   const bf16x8* VT0 = (const bf16x8*)a.vwt[0];
-  const bf16x8* VW0 = (const bf16x8*)a.vw[0];
   const bool own = a.owned_s[at] != 0;
   auto qload = [&](int lm, bf16x8* qv) {
 #pragma unroll
     for (int kc = 0; kc < KCQ; ++kc) qv[kc] = Q[((int64_t)at * NLM + lm) * (KQ / 8) + 4 * kc + g];
   };
   // hbar rows of one (l, m): W_up_l h~bar_lm^T, channel 16 mt + 4 g + r (the positions of z)
-  auto hbar_row = [&](int l, int lm, f32x4* hb) {
-    const bf16x8* U = (const bf16x8*)a.up[l];
+  auto hbar_row = [&](int lm, f32x4* hb) {
     bf16x8 hv[KCC];
 #pragma unroll
     for (int kc = 0; kc < KCC; ++kc) hv[kc] = HB[((int64_t)at * NLM + lm) * (C / 8) + 4 * kc + g];
-    stream_rows<MTC, KCC>(U, 0, KCC, 0, hv, lane, [&](int mt, f32x4 d) { hb[mt] = d; });
+    lds_rows<MTC, KCC>(sU, KCC, 0, hv, lane, [&](int mt, f32x4 d) { hb[mt] = d; });
   };
   // P rows: D tile mt, lane (g, n) holds P index (KQ/4) g + 4 mt + r
   auto pdst = [&](int lm) { return (__bf16*)a.P + ((int64_t)at * NLM + lm) * KQ + (KQ / 4) * g; };
@@ -193,12 +255,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // formed from them at the end, after the last read of Q_0 (P overwrites Q)
   bf16x8 z0b[(1 + L) * KCC];
   // scalars: zbar_0[0:C] = hbar_0 * SiLU'(z_0[0:C]), hbar_0 = w_read (root atoms) + W_up_0 h~bar_0
-  {
+  stage_tiles<NU>(sU, (const bf16x8*)a.up[0]);
+  stage_tiles<NVT>(sV, VT0);
+  __syncthreads();
+  if (act) {
     f32x4 hb[MTC];
-    hbar_row(0, 0, hb);
+    hbar_row(0, hb);
     bf16x8 q0[KCQ];
     qload(0, q0);
-    stream_rows<MTC, KCQ>(VT0, 0, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
+    lds_rows<MTC, KCQ>(sV, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
       const float4 w = *(const float4*)(a.w_read + 16 * mt + 4 * g);
       const float wv[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -209,63 +274,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 #pragma unroll
   for (int l = 1; l <= L; ++l) {
+    __syncthreads();
+    stage_tiles<NVT>(sV, VT0 + (size_t)l * NVT * 64);
+    __syncthreads();
     f32x4 s[MTC], dg[MTC];
-    {
+    if (act) {
       bf16x8 q0[KCQ];
       qload(0, q0);
-      stream_rows<MTC, KCQ>(VT0, l * MTC, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
+      lds_rows<MTC, KCQ>(sV, KCQ, 0, q0, lane, [&](int mt, f32x4 d) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) { s[mt][r] = sigm(d[r]); dg[mt][r] = 0.f; }
       });
     }
-    const bf16x8* VT = (const bf16x8*)a.vwt[l];
-    const bf16x8* VW = (const bf16x8*)a.vw[l];
-    for (int m = 0; m < 2 * l + 1; ++m) {
-      const int lm = l * l + m;
-      f32x4 hb[MTC];
-      hbar_row(l, lm, hb);
-      bf16x8 ql[KCQ];
-      qload(lm, ql);
-      // z_lm consumed tile by tile: dgate += hbar z, zbar_lm = hbar sigmoid(gate) (in hb)
-      stream_rows<MTC, KCQ>(VT, 0, KCQ, 0, ql, lane, [&](int mt, f32x4 d) {
+    __syncthreads();
+    stage_tiles<NU>(sU, (const bf16x8*)a.up[l]);
+    stage_tiles<NVT>(sV, (const bf16x8*)a.vwt[l]);
+    stage_tiles<D::NVW>(sP, (const bf16x8*)a.vw[l]);
+    __syncthreads();
+    if (act) {
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        const int lm = l * l + m;
+        f32x4 hb[MTC];
+        hbar_row(lm, hb);
+        bf16x8 ql[KCQ];
+        qload(lm, ql);
+        // z_lm consumed tile by tile: dgate += hbar z, zbar_lm = hbar sigmoid(gate) (in hb)
+        lds_rows<MTC, KCQ>(sV, KCQ, 0, ql, lane, [&](int mt, f32x4 d) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          dg[mt][r] += hb[mt][r] * d[r];
-          hb[mt][r] *= s[mt][r];
-        }
-      });
-      bf16x8 zb[KCC];
+          for (int r = 0; r < 4; ++r) {
+            dg[mt][r] += hb[mt][r] * d[r];
+            hb[mt][r] *= s[mt][r];
+          }
+        });
+        bf16x8 zb[KCC];
 #pragma unroll
-      for (int kc = 0; kc < KCC; ++kc) zb[kc] = tiles_to_op(hb, kc);
-      __bf16* dst = pdst(lm);
-      PairStore ps;
-      stream_rows<MTP, KCC>(VW, 0, KCC, 0, zb, lane, [&](int mt, f32x4 d) {
-        if (av) ps.put(mt, d, dst);
-      });
+        for (int kc = 0; kc < KCC; ++kc) zb[kc] = tiles_to_op(hb, kc);
+        __bf16* dst = pdst(lm);
+        PairStore ps;
+        lds_rows<MTP, KCC>(sP, KCC, 0, zb, lane, [&](int mt, f32x4 d) {
+          if (av) ps.put(mt, d, dst);
+        });
+      }
+      // zbar of the gate block l: sum_m hbar_lm z_lm * sigmoid'
+#pragma unroll
+      for (int mt = 0; mt < MTC; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dg[mt][r] *= s[mt][r] * (1.f - s[mt][r]);
+#pragma unroll
+      for (int kc = 0; kc < KCC; ++kc) z0b[l * KCC + kc] = tiles_to_op(dg, kc);
     }
-    // zbar of the gate block l: sum_m hbar_lm z_lm * sigmoid'
-#pragma unroll
-    for (int mt = 0; mt < MTC; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) dg[mt][r] *= s[mt][r] * (1.f - s[mt][r]);
-#pragma unroll
-    for (int kc = 0; kc < KCC; ++kc) z0b[l * KCC + kc] = tiles_to_op(dg, kc);
   }
-  {
-    __bf16* dst = pdst(0);
-    PairStore ps;
-    stream_rows<MTP, NZC>(VW0, 0, NZC, 0, z0b, lane, [&](int mt, f32x4 d) {
-      if (av) ps.put(mt, d, dst);
-    });
+  // P_0 = zbar_0 (VW_0)^T in two halves of its row tiles
+  __bf16* dst = pdst(0);
+  PairStore ps;
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+    __syncthreads();
+    stage_tiles<D::NP0>(sW, (const bf16x8*)a.vw[0] + (size_t)hf * D::NP0 * 64);
+    __syncthreads();
+    if (act)
+      lds_rows<MTP / 2, NZC>(sW, NZC, 0, z0b, lane, [&](int mt, f32x4 d) {
+        if (av) ps.put(hf * (MTP / 2) + mt, d, dst);
+      });
   }
 }
 
 template <int C, int L>
 static void node1_c(bool fwd, int S, const Node1Args& a, hipStream_t s) {
-  const unsigned grid = (unsigned)((a.n + 63) / 64);
-#define MPIP_N1(SS)                                                       \
-  if (fwd) k_node1_fwd<C, L, SS><<<grid, 256, 0, s>>>(a);                 \
-  else k_node1_bwd<C, L, SS><<<grid, 256, 0, s>>>(a);
+  const unsigned grid = (unsigned)((a.n + 16 * kN1Waves - 1) / (16 * kN1Waves));
+#define MPIP_N1(SS)                                                                 \
+  if (fwd) k_node1_fwd<C, L, SS><<<grid, 64 * kN1Waves, 0, s>>>(a);                 \
+  else k_node1_bwd<C, L, SS><<<grid, 64 * kN1Waves, 0, s>>>(a);
   switch (S) {
     case 1: MPIP_N1(1) break;
     case 2: MPIP_N1(2) break;
