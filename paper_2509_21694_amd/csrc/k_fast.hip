@@ -151,12 +151,6 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
-// LDS written by some lanes of a wave and read by others of the same wave
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Rows of the calling wave.  Workgroups are dispatched to the 8 XCDs in
 // round-robin order, so workgroup b runs on XCD b % 8: each XCD takes a
@@ -500,23 +494,29 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
-      // Ysel^T operand for this lane's edge (column el): slot -> row m of (s, lm)
-      auto ysel = [&](int m) -> float {
+      // Ysel^T operand for this lane's edge (column el): slot -> row m of (s, lm);
+      // the slot's row is a compile-time value per lane group, chosen by g
+      auto ysel_fixed = [&](int m) -> float {   // m known at compile time after unrolling
         if (m >= MROWS) return 0.f;
         const int s = m / NLM, lm = m - s * NLM;
-        float val = 0.f;
-#pragma unroll
-        for (int k = 0; k < NLM; ++k) val = (k == lm) ? yc[k] : val;
-        return (s == sp) ? val : 0.f;
+        return (s == sp) ? yc[lm] : 0.f;
       };
       typename O::T yb[KCQ];
 #pragma unroll
       for (int kc = 0; kc < KCQ; ++kc) {
         if constexpr (PREC == 1) {
 #pragma unroll
-          for (int j = 0; j < 8; ++j) yb[kc][j] = (__bf16)ysel(32 * kc + 8 * g + j);
+          for (int j = 0; j < 8; ++j) {
+            float v = ysel_fixed(32 * kc + j);
+#pragma unroll
+            for (int gg = 1; gg < 4; ++gg) v = (g == gg) ? ysel_fixed(32 * kc + 8 * gg + j) : v;
+            yb[kc][j] = (__bf16)v;
+          }
         } else {
-          yb[kc] = ysel(4 * kc + g);
+          float v = ysel_fixed(4 * kc);
+#pragma unroll
+          for (int gg = 1; gg < 4; ++gg) v = (g == gg) ? ysel_fixed(4 * kc + gg) : v;
+          yb[kc] = v;
         }
       }
 #pragma unroll

@@ -323,6 +323,7 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
   if (i >= n) return;
   if (FILL && row_ptr[n] > capacity) return;
   const GridParams g = *gp;
+  if (g.stencil[0] && g.stencil[1] && g.stencil[2]) return;   // k_nbr_w
   const int4 me = info_s[i];
   int bi[3];
   {
@@ -394,6 +395,127 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
   if (!FILL) cnt[i] = count;
   if (FILL && stencil3) blk[28 * i + 27] = count;
   if (coincident) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_COINCIDENT);
+}
+
+// The same search with one wave per atom when all three dimensions use the
+// 27-bin stencil (the bulk case): the candidates of the 27 bins are laid end
+// to end and spread over the lanes (a lane finds its bin by a binary search
+// in the wave's LDS prefix of bin sizes), tested with the same FP64
+// predicate, and the passing ones are compacted with a ballot so each row
+// is written contiguously.  Edge order (stencil block, then bin order) and
+// the per-block offsets blk are those of k_nbr.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restrict__ pos_s,
+                                               const int4* __restrict__ info_s, const int32_t* __restrict__ spec_s,
+                                               CellInfo ci, const GridParams* __restrict__ gp,
+                                               const int32_t* __restrict__ bin_start,
+                                               const int32_t* __restrict__ bin_count, int32_t* __restrict__ blk,
+                                               int32_t* __restrict__ cnt, const int32_t* __restrict__ row_ptr,
+                                               int64_t capacity, int32_t* __restrict__ e_src,
+                                               uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec,
+                                               int64_t* __restrict__ status) {
+  __shared__ int sPre[4][28], sStart[4][27], sShift[4][27], sCnt[4][27];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * 4 + wv;
+  const GridParams g = *gp;
+  if (!(g.stencil[0] && g.stencil[1] && g.stencil[2])) return;
+  if (i >= n) return;
+  if (FILL && row_ptr[n] > capacity) return;
+  const int4 me = info_s[i];
+  const int bi[3] = {me.w % g.nb[0], (me.w / g.nb[0]) % g.nb[1], me.w / (g.nb[0] * g.nb[1])};
+  // lane k < 27: stencil block k = ((oz+1)*3 + (oy+1))*3 + (ox+1)
+  int bc = 0;
+  if (lane < 27) {
+    const int o[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+    int c[3], Sp[3];
+    bool skip = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int cc = bi[d] + o[d];
+      Sp[d] = 0;
+      if (ci.pbc[d]) {
+        if (g.nb[d] < 3) skip = true;
+        if (cc < 0) { cc += g.nb[d]; Sp[d] = -1; }
+        else if (cc >= g.nb[d]) { cc -= g.nb[d]; Sp[d] = 1; }
+      } else if (cc < 0 || cc >= g.nb[d]) {
+        skip = true;
+      }
+      c[d] = cc;
+    }
+    int bs = 0;
+    if (!skip) {
+      const int bin = (c[2] * g.nb[1] + c[1]) * g.nb[0] + c[0];
+      bs = bin_start[bin];
+      bc = bin_count[bin];
+    }
+    sStart[wv][lane] = bs;
+    sShift[wv][lane] = (Sp[0] + 1) | ((Sp[1] + 1) << 2) | ((Sp[2] + 1) << 4);
+    sCnt[wv][lane] = 0;
+  }
+  // exclusive prefix of the bin sizes over lanes 0..26
+  int v = bc;
+#pragma unroll
+  for (int o = 1; o < 32; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  if (lane < 27) sPre[wv][lane] = v - bc;
+  if (lane == 26) sPre[wv][27] = v;
+  const int total = __shfl(v, 26);
+  wave_lds_sync();
+  const double xi[3] = {pos_s[3 * i], pos_s[3 * i + 1], pos_s[3 * i + 2]};
+  const double rc2 = ci.rc * ci.rc;
+  const int64_t out = FILL ? row_ptr[i] : 0;
+  int count = 0, coincident = 0;
+  for (int base = 0; base < total; base += 64) {
+    const int f = base + lane;
+    bool pass = false;
+    int j = 0, k = 0, S[3] = {0, 0, 0};
+    double dx[3] = {0.0, 0.0, 0.0};
+    if (f < total) {
+      // largest k with pre[k] <= f (empty bins share the prefix of the next one)
+#pragma unroll
+      for (int step = 16; step > 0; step >>= 1)
+        if (k + step < 27 && sPre[wv][k + step] <= f) k += step;
+      j = sStart[wv][k] + (f - sPre[wv][k]);
+      const int sc = sShift[wv][k];
+      const int Sp[3] = {(sc & 3) - 1, ((sc >> 2) & 3) - 1, ((sc >> 4) & 3) - 1};
+      const int4 oj = info_s[j];
+      S[0] = ci.pbc[0] ? Sp[0] - oj.x + me.x : 0;
+      S[1] = ci.pbc[1] ? Sp[1] - oj.y + me.y : 0;
+      S[2] = ci.pbc[2] ? Sp[2] - oj.z + me.z : 0;
+      if (!(j == i && S[0] == 0 && S[1] == 0 && S[2] == 0)) {
+        const double xj[3] = {pos_s[3 * (int64_t)j], pos_s[3 * (int64_t)j + 1], pos_s[3 * (int64_t)j + 2]};
+        pass = pair_test(xi, xj, ci, S[0], S[1], S[2], rc2, dx);
+        if (pass && dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+      }
+    }
+    const unsigned long long m = __ballot(pass);
+    if (FILL && pass) {
+      const int64_t eidx = out + count + __popcll(m & ((1ull << lane) - 1ull));
+      e_src[eidx] = j;
+      e_shift[eidx] = (uint32_t)(S[0] & 0xff) | ((uint32_t)(S[1] & 0xff) << 8) | ((uint32_t)(S[2] & 0xff) << 16);
+      e_vec[eidx] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], __int_as_float(spec_s[j]));
+      atomicAdd(&sCnt[wv][k], 1);
+    }
+    count += __popcll(m);
+  }
+  if (FILL) {
+    wave_lds_sync();
+    // blk: edges of the row before each stencil block, then the row total
+    int c = lane < 27 ? sCnt[wv][lane] : 0;
+    int w = c;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const int t = __shfl_up(w, o);
+      if (lane >= o) w += t;
+    }
+    if (lane < 27) blk[28 * i + lane] = w - c;
+    if (lane == 0) blk[28 * i + 27] = count;
+  } else if (lane == 0) {
+    cnt[i] = count;
+  }
+  if (__any(coincident) && lane == 0) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_COINCIDENT);
 }
 
 __global__ void k_check_capacity(const int32_t* __restrict__ row_ptr, int64_t n, int64_t capacity,
@@ -493,10 +615,16 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   k_bin_sort<<<gb, 256, 0, s>>>(b.grid, b.bin_start, b.bin_count, b.perm);
   k_gather_sorted<<<ga, nblk, 0, s>>>(b.perm, n, sys.positions, sys.species, b.info, sys.n_owned, ci.n_species, b.pos_s,
                                       b.info_s, b.spec_s, b.inv_perm, b.owned_s);
+  // one of each pair does the work: k_nbr_w when all dimensions use the 27-bin stencil, else k_nbr
+  const unsigned gw = (unsigned)((n + 3) / 4);
+  k_nbr_w<false><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt,
+                                    nullptr, capacity, nullptr, nullptr, nullptr, b.status);
   k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt, nullptr,
                                    capacity, nullptr, nullptr, nullptr, b.status);
   exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
   k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
+  k_nbr_w<true><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr,
+                                   b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.status);
   k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
   k_nbr_rev<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.info_s, b.grid, b.blk,
