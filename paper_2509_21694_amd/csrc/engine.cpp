@@ -353,6 +353,18 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
         if ((st = node(x.down[l], C, C, true, &d.down_t[l])) != MPIP_OK) goto done;
         if ((st = node(x.down[l], C, C, false, &d.down[l])) != MPIP_OK) goto done;
       }
+      // the fused last-layer node kernel (BF16 form; any layer t >= 2 can be the last)
+      d.nk_dt = d.nk_d = nullptr;
+      if (bf && t >= 2 && (C == 64 || C == 128)) {
+        const float* Wd = x.down[0];   // [C][C (1 + L)]; the scalar block is columns 0..C-1
+        const int nzd = C * (1 + L);
+        if ((st = pack(C / 16, C / 32, [&](int mt, int kc, int lane, int j) {
+               return Wd[(size_t)(32 * kc + 8 * (lane >> 4) + j) * nzd + 16 * mt + (lane & 15)];
+             }, &d.nk_dt)) != MPIP_OK) goto done;
+        if ((st = pack(C / 16, C / 32, [&](int mt, int kc, int lane, int j) {
+               return Wd[(size_t)(16 * mt + (lane & 15)) * nzd + phi_bf(kc, lane >> 4, j)];
+             }, &d.nk_d)) != MPIP_OK) goto done;
+      }
       // ---- operand layouts of the specialised first / last layer kernels
       // layer-2 B operand, edges x features: col h2 = 16 nt + lane%16, k-slot -> h1
       if ((st = pack(4, KC64, [&](int nt, int k, int lane, int j) {
@@ -723,6 +735,12 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   // the node work between them runs in the fused kernels of k_node1.hip
   const bool node1 = ht_bf16 && K == 2 && fast_layer(1) && fast_layer(2) && LD[0].n1_vwt[0] != nullptr;
   fa.htbar_bf16 = node1 ? 1 : 0;
+  // the last layer's node update fused with its adjoint (needs the messages of the BF16 form in A)
+  const bool nodeK = node1 && fa.msg && LD[K - 1].nk_dt != nullptr;
+  NodeKArgs nk;
+  nk.n = N; nk.nlm = nlm; nk.A = A; nk.h = h; nk.w_read = m->w_read; nk.e0 = m->e0;
+  nk.spec_s = b.spec_s; nk.owned_s = b.owned_s; nk.atom_e = atom_e;
+  nk.dt = LD[K - 1].nk_dt; nk.d = LD[K - 1].nk_d;
   Node1Args n1;
   n1.n = N; n1.Q = qp; n1.P = qp; n1.h = h; n1.ht = node1 ? (void*)(w + p.o_ht[1]) : nullptr; n1.htbar = htbar;
   n1.spec_s = b.spec_s; n1.owned_s = b.owned_s; n1.emb = m->emb; n1.w_read = m->w_read;
@@ -776,6 +794,13 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
       T.end(s);
       continue;
     }
+    if (nodeK && t == K) {
+      // node update, readout and their adjoint: atom energies, and dE/dA over A
+      T.begin("node_last", s);
+      launch_nodeK(C, nk, s);
+      T.end(s);
+      continue;
+    }
     if (fast && kind == KIND_FIRST) {
       // z_l = Q_l (V_l W_down_l) (Q in BF16 in the BF16 form); the messages are never stored
       gemm(at(qp, 0, ht_bf16), (int64_t)nlm * KQ, 0, z0, nz, 0, N, 1, KQ, nz, KQ, d.vwt[0], 0, 0, ht_bf16);
@@ -794,9 +819,11 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
     launch_gate_fwd(na, t == 1, t == K, s);
     T.end(s);
   }
-  T.begin("gates", s);
-  launch_readout(na, s);
-  T.end(s);
+  if (!nodeK) {
+    T.begin("gates", s);
+    launch_readout(na, s);
+    T.end(s);
+  }
 
   // ---------------- adjoint ----------------
   T.begin("outputs", s);
@@ -823,6 +850,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
       T.end(s);
       continue;
     }
+    if (nodeK && t == K) goto edge_adjoint;   // dE/dA is already in A
     T.begin("gates", s);
     launch_gate_bwd(na, t == K, (t == K && K >= 2 && !node1) ? 1 : 0, s);
     T.end(s);
@@ -840,6 +868,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
           gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
                2 * l + 1, C, C, C, d.down[l], 0);
     }
+  edge_adjoint:
     T.begin("edge_bwd_t" + std::to_string(t), s);
     if (fast) {
       set_fast(d, role);

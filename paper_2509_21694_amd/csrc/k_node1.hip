@@ -339,6 +339,67 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(2
   }
 }
 
+// The last layer's node update and its adjoint (BF16 form, only the scalar
+// output live): per tile of 16 atoms, z_0 = W_down^T A (the scalar block),
+// E_i = e0 + w_read . (h_0 + SiLU(z_0)), zbar_0 = w_read SiLU'(z_0) on root
+// atoms, dE/dA = W_down zbar_0 written over A.  Both packings of W_down sit in
+// LDS once per workgroup of 8 waves (128 atoms).
+template <int C>
+__global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(4))) void k_nodeK(NodeKArgs a) {
+  constexpr int MT = C / 16, KC = C / 32;
+  __shared__ bf16x8 sDt[MT * KC * 64], sD[MT * KC * 64];
+  stage_tiles<MT * KC>(sDt, (const bf16x8*)a.dt);
+  stage_tiles<MT * KC>(sD, (const bf16x8*)a.d);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  const int64_t a0 = ((int64_t)blockIdx.x * kN1Waves + (threadIdx.x >> 6)) * 16;
+  if (a0 >= a.n) return;
+  const bool av = a0 + n < a.n;
+  const int64_t at = av ? a0 + n : a.n - 1;
+  float* Ai = a.A + at * C;
+  // B operand: this atom's messages, k-slot (kc, g, j) = channel 32 kc + 8 g + j
+  bf16x8 ab[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    const float4 u = *(const float4*)(Ai + 32 * kc + 8 * g), v = *(const float4*)(Ai + 32 * kc + 8 * g + 4);
+    const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ab[kc][j] = (__bf16)x[j];
+  }
+  const bool own = a.owned_s[at] != 0;
+  const float* h0 = a.h + at * (int64_t)a.nlm * C;
+  double es = 0.0;
+  f32x4 zb[MT];
+  // D tile mt: z feature 16 mt + 4 g + r of atom n
+  lds_rows<MT, KC>(sDt, KC, 0, ab, lane, [&](int mt, f32x4 d) {
+    const float4 hv = *(const float4*)(h0 + 16 * mt + 4 * g);
+    const float4 wv = *(const float4*)(a.w_read + 16 * mt + 4 * g);
+    const float hh[4] = {hv.x, hv.y, hv.z, hv.w}, ww[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      es += (double)(hh[r] + silu(d[r])) * (double)ww[r];
+      zb[mt][r] = own ? ww[r] * dsilu(d[r]) : 0.f;
+    }
+  });
+  es += __shfl_xor(es, 16);
+  es += __shfl_xor(es, 32);
+  if (g == 0 && av) a.atom_e[at] = (double)a.e0[a.spec_s[at]] + es;
+  bf16x8 zo[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) zo[kc] = tiles_to_op(zb, kc);
+  // every lane has read its A row above; the wave writes dE/dA over it
+  lds_rows<MT, KC>(sD, KC, 0, zo, lane, [&](int mt, f32x4 d) {
+    if (av) *(float4*)(Ai + 16 * mt + 4 * g) = make_float4(d[0], d[1], d[2], d[3]);
+  });
+}
+
+void launch_nodeK(int C, const NodeKArgs& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  const unsigned grid = (unsigned)((a.n + 16 * kN1Waves - 1) / (16 * kN1Waves));
+  if (C == 64) k_nodeK<64><<<grid, 64 * kN1Waves, 0, s>>>(a);
+  else k_nodeK<128><<<grid, 64 * kN1Waves, 0, s>>>(a);
+}
+
 template <int C, int L>
 static void node1_c(bool fwd, int S, const Node1Args& a, hipStream_t s) {
   const unsigned grid = (unsigned)((a.n + 16 * kN1Waves - 1) / (16 * kN1Waves));

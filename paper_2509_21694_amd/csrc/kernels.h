@@ -91,6 +91,8 @@ struct LayerDev {
   const void* n1_upt[3];   // next layer's W_up_l^T: rows output channel (C/4)(r/4) + 4 mt + r%4, k permuted
   const void* n1_up[3];    // next layer's W_up_l: rows channel, k = channel in order
   const void* n1_vw[3];    // V_l W_down_l: rows (s, k) as (S*16)(r/4) + 4 mt + r%4, k = z feature permuted per C block
+  const void* nk_dt;       // last layer, W_down's scalar block transposed: rows z feature, k = channel in order
+  const void* nk_d;        // last layer, W_down's scalar block: rows channel, k = z feature permuted
 };
 
 struct Node1Args {
@@ -110,6 +112,22 @@ struct Node1Args {
   const void* vw[3];
 };
 void launch_node1(bool fwd, int C, int L, int S, const Node1Args& a, hipStream_t s);
+
+// the last layer's node update, readout and their adjoint in one pass (BF16 form)
+struct NodeKArgs {
+  int64_t n;
+  int nlm;
+  float* A;               // [N][C]: messages in, dE/dA out (same rows)
+  const float* h;         // [N][nlm][C]: the previous layer's h_0 rows
+  const float* w_read;    // [C]
+  const float* e0;        // [S]
+  const int32_t* spec_s;
+  const uint8_t* owned_s;
+  double* atom_e;         // [N]
+  const void* dt;         // LayerDev::nk_dt
+  const void* d;          // LayerDev::nk_d
+};
+void launch_nodeK(int C, const NodeKArgs& a, hipStream_t s);
 
 struct FastArgs {
   int64_t n;
