@@ -663,8 +663,10 @@ mpip_status mpip_neighbor_list(const mpip_system* sys, double r_cut, void* strea
 
 // Layers forward, readout and the adjoint of all layers on a built CSR:
 // leaves dE/dr_e in the workspace (g) and per-atom energies (atom_e).
-static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b, int64_t N, mpip_precision prec,
-                      int32_t K, int64_t max_edges, hipStream_t s) {
+// Returns the buffer holding the last layer's part of the edge gradients
+// when it is kept apart from g (see FastArgs::g2p), else null.
+static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b, int64_t N,
+                               mpip_precision prec, int32_t K, int64_t max_edges, hipStream_t s) {
   const mpip_hparams& hp = m->hp;
   const int C = hp.channels, L = hp.l_max, nlm = (L + 1) * (L + 1), S = hp.n_species;
   const int pi = prec == MPIP_BF16_MIXED ? 1 : 0;
@@ -726,6 +728,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   fa.status = b.status; fa.rc = (float)hp.r_cut; fa.envelope_p = hp.envelope_p; fa.n_species = S;
   fa.inv_n = (float)hp.inv_avg_neighbors; fa.Q = qp; fa.P = qp; fa.g = g; fa.htbar = htbar;
   fa.msg = p.o_msg ? (void*)(w + p.o_msg) : nullptr;
+  fa.g2p = nullptr;
   auto set_fast = [&](const LayerDev& d, int role) {
     fa.w1a = d.w1a; fa.w2a = d.w2a; fa.w2b = d.w2b; fa.w1b = d.w1b; fa.w2f = d.w2f;
     fa.w3f = d.w3fp[role]; fa.w3t = d.w3t[role]; fa.w3b = d.w3bp[role]; fa.cg = d.cg[role];
@@ -737,6 +740,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   fa.htbar_bf16 = node1 ? 1 : 0;
   // the last layer's node update fused with its adjoint (needs the messages of the BF16 form in A)
   const bool nodeK = node1 && fa.msg && LD[K - 1].nk_dt != nullptr;
+  // two specialised layers in the BF16 form: the last layer's edge gradients go
+  // to the (then dead) message buffer and the first layer's adjoint combines them
+  if (node1 && fa.msg) fa.g2p = (float4*)fa.msg;
   NodeKArgs nk;
   nk.n = N; nk.nlm = nlm; nk.A = A; nk.h = h; nk.w_read = m->w_read; nk.e0 = m->e0;
   nk.spec_s = b.spec_s; nk.owned_s = b.owned_s; nk.atom_e = atom_e;
@@ -827,7 +833,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
 
   // ---------------- adjoint ----------------
   T.begin("outputs", s);
-  launch_zero(g, sizeof(float4) * (size_t)max_edges, s);
+  if (!fa.g2p) launch_zero(g, sizeof(float4) * (size_t)max_edges, s);
   // the FP32 form's edge-parallel adjoint needs each edge's receiver
   if (fast_layer(K) && kind_of(K) == KIND_LAST && !ht_bf16) edge_receivers(b, N, max_edges, s);
   T.end(s);
@@ -897,7 +903,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         gemm(htbar + l * l * C, (int64_t)nlm * C, C, hbar + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
              2 * l + 1, C, C, C, d.up[l], 1);
   }
+  return fa.g2p;
 }
+
 
 extern "C" {
 
@@ -931,9 +939,9 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
   build_neighbors(b, *sys, ci, max_edges, s);
   T.end(s);
 
-  run_model(m, p, w, b, N, prec, K, max_edges, s);
+  const float4* g2p = run_model(m, p, w, b, N, prec, K, max_edges, s);
   OutArgs oa;
-  oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = g; oa.e_rev = b.e_rev; oa.perm = b.perm;
+  oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = g; oa.g2p = g2p; oa.e_rev = b.e_rev; oa.perm = b.perm;
   oa.owned_s = b.owned_s; oa.atom_e = atom_e; oa.capacity = max_edges; oa.status = b.status;
   oa.partials = (double*)(w + p.o_partials); oa.nblocks = p.nblocks_out;
   oa.forces = out->forces; oa.atom_energy = out->atom_energy; oa.energy = out->energy; oa.virial = out->virial;
@@ -1130,10 +1138,10 @@ mpip_status mpip_evaluate_batch(mpip_model* m, int32_t B, const int64_t* atom_pt
   T.begin("neighbors", s);
   build_neighbors_batch(b, bb, B, positions, species, N, hp.n_species, hp.r_cut, max_edges, s);
   T.end(s);
-  run_model(m, p, w, b, N, prec, K, max_edges, s);
+  const float4* g2p = run_model(m, p, w, b, N, prec, K, max_edges, s);
   T.begin("outputs", s);
-  launch_batch_outputs(N, B, b, (const float4*)(w + p.o_g), (const double*)(w + p.o_atom_e), bb, max_edges, forces,
-                       energy, virial, s);
+  launch_batch_outputs(N, B, b, (const float4*)(w + p.o_g), g2p, (const double*)(w + p.o_atom_e), bb, max_edges,
+                       forces, energy, virial, s);
   T.end(s);
   hipError_t e = hipGetLastError();
   if (cur != m->device) hipSetDevice(cur);

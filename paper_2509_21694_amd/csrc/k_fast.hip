@@ -91,8 +91,8 @@ __device__ __forceinline__ void yc_last_adj(const CgDiag<L>& cd, const float* yc
 }
 
 
-// geometry backward: g_e += dbar u + (I - u u^T)/d (dP/du)^T Ybar
-__device__ __forceinline__ void add_edge_grad(float4* g, int e, const Geo& geo, const float* ebar, const float* Yb) {
+// geometry backward: dE/dr_e = dbar u + (I - u u^T)/d (dP/du)^T Ybar
+__device__ __forceinline__ float4 edge_grad(const Geo& geo, const float* ebar, const float* Yb) {
   float dbar = 0.f;
 #pragma unroll
   for (int n = 0; n < kNB; ++n) dbar += ebar[n] * geo.dbasis[n];
@@ -100,10 +100,17 @@ __device__ __forceinline__ void add_edge_grad(float4* g, int e, const Geo& geo, 
   sh_grad_contract(Yb, geo.u, gu);
   const float ud = gu[0] * geo.u[0] + gu[1] * geo.u[1] + gu[2] * geo.u[2];
   const float invd = __builtin_amdgcn_rcpf(geo.d);
+  return make_float4(dbar * geo.u[0] + (gu[0] - ud * geo.u[0]) * invd, dbar * geo.u[1] + (gu[1] - ud * geo.u[1]) * invd,
+                     dbar * geo.u[2] + (gu[2] - ud * geo.u[2]) * invd, 0.f);
+}
+
+// g_e += dE/dr_e
+__device__ __forceinline__ void add_edge_grad(float4* g, int e, const Geo& geo, const float* ebar, const float* Yb) {
+  const float4 d = edge_grad(geo, ebar, Yb);
   float4 acc = g[e];
-  acc.x += dbar * geo.u[0] + (gu[0] - ud * geo.u[0]) * invd;
-  acc.y += dbar * geo.u[1] + (gu[1] - ud * geo.u[1]) * invd;
-  acc.z += dbar * geo.u[2] + (gu[2] - ud * geo.u[2]) * invd;
+  acc.x += d.x;
+  acc.y += d.y;
+  acc.z += d.z;
   g[e] = acc;
 }
 
@@ -545,7 +552,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
         for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + sp * NLM + k];
         yc_last_adj<L>(cgd, ycb, Yb);
-        add_edge_grad(a.g, e, geo, eb, Yb);
+        if (a.g2p) {
+          // this layer's part only; the outputs add the last layer's from g2p
+          a.g[e] = edge_grad(geo, eb, Yb);
+        } else {
+          add_edge_grad(a.g, e, geo, eb, Yb);
+        }
       }
       wave_lds_sync();
     }
@@ -1217,8 +1229,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
         for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
         yc_last_adj<L>(cgd, ycb, Yb);
-        const int rv = a.e_rev[e];
-        if (rv >= 0) add_edge_grad(a.g, rv, geo, eb, Yb);
+        if (a.g2p) {
+          // dE/dr of the reverse edge, kept in this edge's slot (written once, coalesced)
+          a.g2p[e] = edge_grad(geo, eb, Yb);
+        } else {
+          const int rv = a.e_rev[e];
+          if (rv >= 0) add_edge_grad(a.g, rv, geo, eb, Yb);
+        }
       }
     }
     // htbar_i: D rows lm = 4g + r, column el of half tt = channel 32k + 2 el + tt

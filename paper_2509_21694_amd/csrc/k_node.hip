@@ -280,40 +280,50 @@ void launch_gate_bwd(const NodeArgs& a, int last, int init_hbar, hipStream_t s) 
 
 // ------------------------------------------------------------ outputs
 
-// Per atom: F_i = sum_{e in row i} g_e - g_rev(e) (FP64), written in input
-// order; per block: sum of root energies and of r_e (x) g_e, fixed order.
-// One wave per row (lanes over the row's edges, a butterfly sum per row);
-// each lane keeps its virial partial sums over all rows of its wave.
+// Per atom: F_i = sum_{e in row i} G_e - G_rev(e) (FP64), written in input
+// order, with G_e = g[e] (+ g2p[rev(e)] when the last layer's part is kept
+// apart); per block: sum of root energies and of r_e (x) G_e, fixed order.
+// A wave takes 64 rows, 4 at a time with 16 lanes over each row's edges and
+// a 16-lane butterfly per row; each lane keeps its virial partial sums.
 __global__ __launch_bounds__(256) void k_forces(OutArgs a) {
   __shared__ double sh[10][256];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, el = lane & 15;
   double loc[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) loc[k] = 0.0;
   const bool run = (a.status[ST_FLAGS] == 0) && ((int64_t)a.row_ptr[a.n] <= a.capacity);
   if (run) {
     const int64_t r0 = (int64_t)blockIdx.x * 256 + w * 64;
-    for (int64_t i = r0; i < r0 + 64 && i < a.n; ++i) {
+    for (int64_t ib = r0; ib < r0 + 64; ib += 4) {
+      const int64_t i = ib + q;
       double F[3] = {0.0, 0.0, 0.0};
-      for (int e = a.row_ptr[i] + lane; e < a.row_ptr[i + 1]; e += 64) {
-        const float4 ge = a.g[e];
-        const int rv = a.e_rev[e];
-        const float4 gr = rv >= 0 ? a.g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 r = a.e_vec[e];
-        F[0] += (double)ge.x - (double)gr.x;
-        F[1] += (double)ge.y - (double)gr.y;
-        F[2] += (double)ge.z - (double)gr.z;
-        const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
+      if (i < a.n) {
+        for (int e = a.row_ptr[i] + el; e < a.row_ptr[i + 1]; e += 16) {
+          const int rv = a.e_rev[e];
+          float4 ge = a.g[e];
+          float4 gr = rv >= 0 ? a.g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
+          if (a.g2p) {
+            const float4 he = a.g2p[e];
+            const float4 hr = rv >= 0 ? a.g2p[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
+            ge.x += hr.x; ge.y += hr.y; ge.z += hr.z;
+            gr.x += he.x; gr.y += he.y; gr.z += he.z;
+          }
+          const float4 r = a.e_vec[e];
+          F[0] += (double)ge.x - (double)gr.x;
+          F[1] += (double)ge.y - (double)gr.y;
+          F[2] += (double)ge.z - (double)gr.z;
+          const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+          for (int p = 0; p < 3; ++p)
 #pragma unroll
-          for (int q = 0; q < 3; ++q) loc[1 + 3 * p + q] += rr[p] * gg[q];
+            for (int c = 0; c < 3; ++c) loc[1 + 3 * p + c] += rr[p] * gg[c];
+        }
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1)
+      for (int off = 8; off > 0; off >>= 1)
 #pragma unroll
         for (int d = 0; d < 3; ++d) F[d] += __shfl_xor(F[d], off);
-      if (lane == 0) {
+      if (el == 0 && i < a.n) {
         const int o = a.perm[i];
         a.forces[3 * (int64_t)o + 0] = F[0];
         a.forces[3 * (int64_t)o + 1] = F[1];

@@ -160,6 +160,12 @@ struct FastArgs {
   int htbar_bf16;        // 1: htbar stored as bf16 (same element offsets)
   float4* g;
   void* msg;             // last layer forward, BF16 form: messages [E][C] bf16 in CSR order
+  // When set (two specialised layers, BF16 form): the fused last-layer adjoint
+  // writes dE/dr of each edge's reverse into the edge's own slot of g2p and
+  // the first-layer adjoint writes its own part to g (so g needs no
+  // clearing); the outputs combine dE/dr_e = g[e] + g2p[rev(e)].  Otherwise
+  // both accumulate into g.
+  float4* g2p;
 };
 
 void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s);
@@ -234,6 +240,7 @@ struct OutArgs {
   const int32_t* row_ptr;
   const float4* e_vec;
   const float4* g;
+  const float4* g2p;      // null, or the last layer's part of dE/dr of each edge's reverse (see FastArgs)
   const int32_t* e_rev;
   const int32_t* perm;
   const uint8_t* owned_s;
@@ -263,9 +270,9 @@ struct BatchBuffers {
 };
 void build_neighbors_batch(const NbrBuffers& b, const BatchBuffers& bb, int B, const double* pos,
                            const int32_t* spec, int64_t n, int n_species, double rc, int64_t capacity, hipStream_t s);
-void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g, const double* atom_e,
-                          const BatchBuffers& bb, int64_t capacity, double* forces, double* energy, double* virial,
-                          hipStream_t s);
+void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g, const float4* g2p,
+                          const double* atom_e, const BatchBuffers& bb, int64_t capacity, double* forces,
+                          double* energy, double* virial, hipStream_t s);
 
 // ------------------------------------------------------------------ partitions
 struct SlabArgs {
