@@ -197,12 +197,53 @@ mpip_status mpip_accumulate_rows(const double* src, const int32_t* index, int64_
  * (m1, m2, m3).  EINVAL for l > 2 or a triple without natural parity. */
 mpip_status mpip_coupling_tensor(int32_t l1, int32_t l2, int32_t l3, double* out);
 
+/* Molecular dynamics on the device around mpip_evaluate (the MD runs of
+ * the results section use Langevin dynamics).  Each of n_steps steps is the
+ * BAOAB splitting (Leimkuhler and Matthews): v += a dt/2; x += v dt/2;
+ * v = c1 v + sqrt(1 - c1^2) sqrt(kB T / m) xi with c1 = exp(-friction dt);
+ * x += v dt/2; forces at the new x (a full evaluation, neighbour list
+ * rebuilt); v += a dt/2, with a = F/m.  friction = 0 gives velocity Verlet
+ * (NVE).  xi: three standard normal numbers per atom and step from
+ * Philox4x32-10 (Salmon et al., SC'11) with key = seed and counter
+ * (atom index, step index), through the Box-Muller transform of
+ * u = (word + 1) / 2^32 (radius) and (word + 0.5) / 2^32 (angle).
+ * Units: Angstrom, fs, eV, amu, K. */
+typedef struct {
+  double dt;               /* time step, fs, > 0                                      */
+  int64_t n_steps;         /* >= 0                                                    */
+  double friction;         /* Langevin friction, 1/fs, >= 0 (0: NVE)                  */
+  double temperature;      /* Langevin bath temperature, K, >= 0                      */
+  uint64_t seed;           /* key of the noise generator                              */
+} mpip_md_params;
+
+/* Workspace bytes needed by mpip_md_run (the evaluation's plus the
+ * integrator's scratch).  Host only. */
+mpip_status mpip_md_workspace_size(const mpip_model* model, const mpip_system* sys, mpip_precision prec,
+                                   int32_t K, int64_t max_edges, size_t* bytes);
+
+/* n_steps MD steps of the system `sys` (its positions field is ignored;
+ * species, cell, pbc and n_owned are used as in mpip_evaluate) on `stream`.
+ * positions, velocities (Angstrom / fs) and forces: device FP64 [N,3] in
+ * input order, updated in place; on entry `forces` must hold the forces at
+ * `positions` (e.g. from mpip_evaluate), on return they are those at the
+ * final positions.  masses: device FP64 [n_species], amu.  epot, ekin:
+ * device FP64 [n_steps] or NULL, the root-atom potential energy and the
+ * kinetic energy (eV) after each step.  Asynchronous; never allocates; the
+ * workspace (>= mpip_md_workspace_size bytes) must not be used concurrently.
+ * Data-dependent errors of any step are reported by mpip_workspace_status
+ * after the run (the trajectory is then undefined from that step on). */
+mpip_status mpip_md_run(mpip_model* model, const mpip_system* sys, double* positions, double* velocities,
+                        double* forces, const double* masses, const mpip_md_params* params,
+                        mpip_precision prec, int32_t K, void* stream, void* workspace, size_t workspace_bytes,
+                        int64_t max_edges, double* epot, double* ekin);
+
 /* Per-phase GPU timing of mpip_evaluate (tracing aid).  When enabled, each
  * evaluation records HIP events around its kernel phases on the evaluation
  * stream (no synchronisation); mpip_timing_read synchronises those events,
  * adds their durations to per-phase totals and returns the totals since the
  * last enable.  Phase names: "neighbors", "node_gemm", "gates", "outputs",
- * "edge_fwd_t<k>", "edge_bwd_t<k>" (k = layer).  Host-side only; the model
+ * "node_fused", "node_last", "edge_fwd_t<k>", "edge_sum_t<k>",
+ * "edge_bwd_t<k>", "edge_pull_t<k>" (k = layer).  Host-side only; the model
  * must not be evaluated concurrently on two streams while enabled. */
 #define MPIP_MAX_PHASES 48
 typedef struct {

@@ -61,6 +61,11 @@ class TimingC(ctypes.Structure):
                 ("ms", ctypes.c_double * MAX_PHASES), ("calls", ctypes.c_int64 * MAX_PHASES)]
 
 
+class MdParamsC(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("n_steps", ctypes.c_int64), ("friction", ctypes.c_double),
+                ("temperature", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python paper_2509_21694_amd/build.py`")
@@ -100,6 +105,10 @@ def _load():
     lib.mpip_evaluate_batch.argtypes = [V, I32, P(I64), V, V, P(ctypes.c_double), P(ctypes.c_uint8), I32, I32, V, V,
                                         SZ, I64, V, V, V]
     lib.mpip_evaluate_batch.restype = I32
+    lib.mpip_md_workspace_size.argtypes = [V, P(SystemC), I32, I32, I64, P(SZ)]
+    lib.mpip_md_workspace_size.restype = I32
+    lib.mpip_md_run.argtypes = [V, P(SystemC), V, V, V, V, P(MdParamsC), I32, I32, V, V, SZ, I64, V, V]
+    lib.mpip_md_run.restype = I32
     lib.mpip_last_error.argtypes = []
     lib.mpip_last_error.restype = ctypes.c_char_p
     return lib
@@ -111,7 +120,8 @@ EXPORTED = ["mpip_weights_count", "mpip_model_create", "mpip_model_destroy", "mp
             "mpip_evaluate", "mpip_workspace_status", "mpip_neighbor_workspace_size",
             "mpip_neighbor_list", "mpip_coupling_tensor", "mpip_timing_enable", "mpip_timing_read",
             "mpip_slab_workspace_size", "mpip_slab_share", "mpip_accumulate_rows",
-            "mpip_batch_workspace_size", "mpip_evaluate_batch", "mpip_last_error"]
+            "mpip_batch_workspace_size", "mpip_evaluate_batch", "mpip_md_workspace_size", "mpip_md_run",
+            "mpip_last_error"]
 
 
 def _check(st: int):
@@ -242,6 +252,49 @@ class Model:
             o["n_edges"] = int(ne.value)
             return o
         raise MpipError(ECAPACITY, "edge capacity")
+
+
+    def md_run(self, positions, velocities, species, masses, cell, pbc=(True, True, True), *, dt: float,
+               n_steps: int, forces=None, friction: float = 0.0, temperature: float = 0.0, seed: int = 0,
+               K: Optional[int] = None, precision="fp32", max_edges: Optional[int] = None, stream=None):
+        """``n_steps`` MD steps on the device (mpip_md_run): BAOAB Langevin,
+        velocity Verlet when ``friction`` is 0.  ``positions``, ``velocities``
+        (cuda float64 [N,3]) are updated in place; ``forces`` (cuda float64
+        [N,3]) must hold the forces at ``positions`` or be None (then they are
+        evaluated first).  ``masses``: cuda float64 [n_species] (amu).
+        Returns cuda tensors epot [n_steps], ekin [n_steps] (eV) and the
+        final forces; synchronises the stream and raises on a data error."""
+        torch = self.torch
+        K = self.hp.n_layers if K is None else int(K)
+        N = int(positions.shape[0])
+        for t in (positions, velocities):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and tuple(t.shape) == (N, 3)
+        assert masses.dtype == torch.float64 and masses.is_cuda and masses.numel() >= self.hp.n_species
+        if max_edges is None:
+            max_edges = int(estimate_edges(N, cell, self.hp.r_cut) * 1.1)
+        if forces is None:
+            forces = self.evaluate(positions, species, cell, pbc, K=K, precision=precision, max_edges=max_edges,
+                                   stream=stream)["forces"]
+        prec = PRECISIONS[precision]
+        sysc = _system(positions, species, cell, pbc, None)
+        need = ctypes.c_size_t()
+        _check(lib.mpip_md_workspace_size(self._h, ctypes.byref(sysc), prec, K, max_edges, ctypes.byref(need)))
+        if self._ws is None or self._ws.numel() < need.value:
+            self._ws = None
+            self._ws = torch.empty(int(need.value), dtype=torch.uint8, device=self.device)
+        ws = self._ws
+        epot = torch.empty(max(n_steps, 1), dtype=torch.float64, device=self.device)
+        ekin = torch.empty(max(n_steps, 1), dtype=torch.float64, device=self.device)
+        prm = MdParamsC(float(dt), int(n_steps), float(friction), float(temperature), int(seed))
+        sp = _stream_ptr(torch, self.device, stream)
+        _check(lib.mpip_md_run(self._h, ctypes.byref(sysc), ctypes.c_void_p(positions.data_ptr()),
+                               ctypes.c_void_p(velocities.data_ptr()), ctypes.c_void_p(forces.data_ptr()),
+                               ctypes.c_void_p(masses.data_ptr()), ctypes.byref(prm), prec, K, ctypes.c_void_p(sp),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), max_edges,
+                               ctypes.c_void_p(epot.data_ptr()), ctypes.c_void_p(ekin.data_ptr())))
+        ne = ctypes.c_int64()
+        _check(lib.mpip_workspace_status(ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(sp), ctypes.byref(ne)))
+        return epot[:n_steps], ekin[:n_steps], forces
 
 
 class Batch:

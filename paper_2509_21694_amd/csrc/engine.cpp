@@ -1150,3 +1150,88 @@ mpip_status mpip_evaluate_batch(mpip_model* m, int32_t B, const int64_t* atom_pt
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- molecular dynamics
+
+namespace {
+struct MdScratch {
+  size_t base, total;   // evaluation workspace bytes; plus the integrator's scratch
+  size_t o_sticky, o_energy, o_virial, o_partials;
+  int nblocks;
+};
+MdScratch md_scratch(int64_t N, int64_t max_edges, const mpip_hparams* hp, int K) {
+  MdScratch s;
+  s.base = make_plan(N, max_edges, hp, K).total;
+  size_t cur = s.base;
+  s.nblocks = (int)((N + 255) / 256);
+  s.o_sticky = take(cur, sizeof(int64_t));
+  s.o_energy = take(cur, sizeof(double));
+  s.o_virial = take(cur, 9 * sizeof(double));
+  s.o_partials = take(cur, sizeof(double) * (size_t)s.nblocks);
+  s.total = cur + 256;
+  return s;
+}
+}  // namespace
+
+extern "C" {
+
+mpip_status mpip_md_workspace_size(const mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K,
+                                   int64_t max_edges, size_t* bytes) {
+  size_t b = 0;
+  const mpip_status st = mpip_workspace_size(m, sys, prec, K, max_edges, &b);
+  if (st != MPIP_OK) return st;
+  *bytes = md_scratch(sys->n_atoms, max_edges, &m->hp, K).total;
+  return MPIP_OK;
+}
+
+mpip_status mpip_md_run(mpip_model* m, const mpip_system* sys, double* positions, double* velocities, double* forces,
+                        const double* masses, const mpip_md_params* prm, mpip_precision prec, int32_t K,
+                        void* stream, void* ws, size_t ws_bytes, int64_t max_edges, double* epot, double* ekin) {
+  if (!m || !sys || !prm) return fail(MPIP_EINVAL, "null argument");
+  if (!positions || !velocities || !forces || !masses) return fail(MPIP_EINVAL, "null positions, velocities, forces or masses");
+  if (!(prm->dt > 0.0) || !std::isfinite(prm->dt)) return fail(MPIP_EINVAL, "dt must be positive");
+  if (prm->n_steps < 0) return fail(MPIP_EINVAL, "n_steps must be >= 0");
+  if (!(prm->friction >= 0.0) || !(prm->temperature >= 0.0)) return fail(MPIP_EINVAL, "friction and temperature must be >= 0");
+  if (K < 1 || K > m->hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
+  if (!ws) return fail(MPIP_EINVAL, "null workspace");
+  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  const int64_t N = sys->n_atoms;
+  if (N < 1) return fail(MPIP_EINVAL, "n_atoms must be >= 1");
+  const MdScratch sc = md_scratch(N, max_edges, &m->hp, K);
+  if (ws_bytes < sc.total) return fail(MPIP_ECAPACITY, "workspace too small");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != m->device) HIPCHK(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  int64_t* sticky = (int64_t*)(w + sc.o_sticky);
+  double* energy = (double*)(w + sc.o_energy);
+  double* partials = (double*)(w + sc.o_partials);
+  mpip_system s2 = *sys;
+  s2.positions = positions;
+  mpip_outputs out;
+  out.energy = energy;
+  out.forces = forces;
+  out.virial = (double*)(w + sc.o_virial);
+  out.atom_energy = nullptr;
+  launch_zero(sticky, sizeof(int64_t), s);
+  for (int64_t step = 0; step < prm->n_steps; ++step) {
+    md_first(N, positions, velocities, forces, sys->species, masses, prm->dt, prm->friction, prm->temperature,
+             prm->seed, step, s);
+    const mpip_status st = mpip_evaluate(m, &s2, prec, K, stream, ws, ws_bytes, max_edges, &out);
+    if (st != MPIP_OK) {
+      if (cur != m->device) hipSetDevice(cur);
+      return st;
+    }
+    md_second(N, velocities, forces, sys->species, masses, prm->dt, partials, s);
+    md_record(partials, sc.nblocks, energy, (const int64_t*)w, epot ? epot + step : nullptr,
+              ekin ? ekin + step : nullptr, sticky, s);
+  }
+  md_flags(sticky, (int64_t*)w, s);
+  hipError_t e = hipGetLastError();
+  if (cur != m->device) hipSetDevice(cur);
+  if (e != hipSuccess) return fail(MPIP_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return MPIP_OK;
+}
+
+}  // extern "C"

@@ -129,6 +129,16 @@ struct NodeKArgs {
 };
 void launch_nodeK(int C, const NodeKArgs& a, hipStream_t s);
 
+// molecular dynamics (k_md.hip): the two halves of a BAOAB / velocity-Verlet
+// step around the force evaluation, and the per-step energy record
+void md_first(int64_t n, double* x, double* v, const double* f, const int32_t* spec, const double* masses, double dt,
+              double friction, double temperature, uint64_t seed, int64_t step, hipStream_t s);
+void md_second(int64_t n, double* v, const double* f, const int32_t* spec, const double* masses, double dt,
+               double* partials, hipStream_t s);
+void md_record(const double* partials, int nblocks, const double* energy, const int64_t* status, double* epot,
+               double* ekin, int64_t* sticky, hipStream_t s);
+void md_flags(const int64_t* sticky, int64_t* status, hipStream_t s);
+
 struct FastArgs {
   int64_t n;
   const int32_t* row_ptr;

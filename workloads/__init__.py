@@ -267,6 +267,15 @@ def batch_structures(n_struct: int = 512, seed: int = 501, seed_species: int = 5
     return out
 
 
+# masses (amu) of a three-species Li3PO4 stand-in (Li, P, O), for MD runs
+MASSES_LPO = (6.94, 30.973762, 15.999)
+
+
+def velocities(n: int, sigma: float, seed: int) -> np.ndarray:
+    """Initial velocities for MD tests: N(0, sigma) per component (A/fs)."""
+    return np.random.default_rng(seed).standard_normal((n, 3)) * sigma
+
+
 def rejitter(pos: np.ndarray, seed: int, amp: float = 0.01) -> np.ndarray:
     """Small seeded displacement (+-amp, uniform) applied between timed calls
     so that no neighbour-list cache can help."""
