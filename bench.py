@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device to device once before the steps (a kernel of known "
                          "traffic for scaling hardware byte counters)")
+    ap.add_argument("--md-steps", type=int, default=10,
+                    help="also time this many on-device MD steps (first precision; 0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -258,6 +260,31 @@ def main():
         results[prec] = r
 
     head = precs[0]
+    md = None
+    if args.md_steps > 0:
+        # velocity Verlet around the evaluation (mpip_md_run), neighbour list of
+        # radius r_c + 0.5 A reused until an atom has moved 0.25 A
+        x = pos_sets[0].clone()
+        v = torch.tensor(W.velocities(N, 0.005, 12), dtype=torch.float64, device=dev)
+        ms_t = torch.tensor(W.MASSES_LPO, dtype=torch.float64, device=dev)
+        cap = int(results[head]["n_edges"] * 1.02) + 4096
+        F = model.evaluate(x, species, s.cell, s.pbc, K=K, precision=head, max_edges=cap)["forces"]
+        _, _, F = model.md_run(x, v, species, ms_t, s.cell, s.pbc, dt=1.0, n_steps=2, forces=F, skin=0.5, K=K,
+                               precision=head, max_edges=cap)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ep, ek, F = model.md_run(x, v, species, ms_t, s.cell, s.pbc, dt=1.0, n_steps=args.md_steps, forces=F,
+                                 skin=0.5, K=K, precision=head, max_edges=cap)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        et = (ep + ek).cpu().numpy()
+        md_ms = (t1 - t0) / args.md_steps * 1e3
+        log(f"md ({head}): {md_ms:.3f} ms/step")
+        md = {"metric": "MD atom-steps/s (velocity Verlet on the device, dt 1 fs, neighbour list reused "
+                        "within a 0.5 A skin)", "value": round(N / (md_ms * 1e-3), 1),
+              "us_per_atom_step": round(md_ms * 1e3 / N, 6), "ms_per_step": round(md_ms, 4),
+              "steps": args.md_steps, "dtype": head,
+              "energy_drift_per_atom": float(np.abs(et - et[0]).max() / N)}
     line = {"metric": METRIC, "value": results[head]["value"], "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": results[head]["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,
@@ -269,7 +296,8 @@ def main():
                        "channels": hp.channels, "precision": head},
             "roofline": results[head]["roofline"],
             "cpu_baseline": base or None,
-            "forms": results}
+            "forms": results,
+            "md": md}
     if "bf16" in results and "fp32" in results:
         line["bf16_speedup_over_fp32"] = round(results["fp32"]["ms_per_step"] / results["bf16"]["ms_per_step"], 3)
     print(json.dumps(line))

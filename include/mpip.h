@@ -201,9 +201,13 @@ mpip_status mpip_coupling_tensor(int32_t l1, int32_t l2, int32_t l3, double* out
  * the results section use Langevin dynamics).  Each of n_steps steps is the
  * BAOAB splitting (Leimkuhler and Matthews): v += a dt/2; x += v dt/2;
  * v = c1 v + sqrt(1 - c1^2) sqrt(kB T / m) xi with c1 = exp(-friction dt);
- * x += v dt/2; forces at the new x (a full evaluation, neighbour list
- * rebuilt); v += a dt/2, with a = F/m.  friction = 0 gives velocity Verlet
- * (NVE).  xi: three standard normal numbers per atom and step from
+ * x += v dt/2; forces at the new x; v += a dt/2, with a = F/m.  friction
+ * = 0 gives velocity Verlet (NVE).  Neighbour list: with skin = 0 it is
+ * rebuilt at every step; with skin > 0 a list of radius r_cut + skin is
+ * built and kept while no atom has moved more than skin/2 since (checked on
+ * the device each step, one 8-byte read by the host), and every step
+ * selects from it, in FP64 with the same predicate as a fresh build, the
+ * pairs closer than r_cut -- the same edge set as a rebuild.  xi: three standard normal numbers per atom and step from
  * Philox4x32-10 (Salmon et al., SC'11) with key = seed and counter
  * (atom index, step index), through the Box-Muller transform of
  * u = (word + 1) / 2^32 (radius) and (word + 0.5) / 2^32 (angle).
@@ -214,12 +218,14 @@ typedef struct {
   double friction;         /* Langevin friction, 1/fs, >= 0 (0: NVE)                  */
   double temperature;      /* Langevin bath temperature, K, >= 0                      */
   uint64_t seed;           /* key of the noise generator                              */
+  double skin;             /* Angstrom, >= 0: neighbour-list reuse (see above)         */
 } mpip_md_params;
 
 /* Workspace bytes needed by mpip_md_run (the evaluation's plus the
  * integrator's scratch).  Host only. */
-mpip_status mpip_md_workspace_size(const mpip_model* model, const mpip_system* sys, mpip_precision prec,
-                                   int32_t K, int64_t max_edges, size_t* bytes);
+mpip_status mpip_md_workspace_size(const mpip_model* model, const mpip_system* sys,
+                                   const mpip_md_params* params, mpip_precision prec, int32_t K,
+                                   int64_t max_edges, size_t* bytes);
 
 /* n_steps MD steps of the system `sys` (its positions field is ignored;
  * species, cell, pbc and n_owned are used as in mpip_evaluate) on `stream`.
@@ -229,7 +235,10 @@ mpip_status mpip_md_workspace_size(const mpip_model* model, const mpip_system* s
  * final positions.  masses: device FP64 [n_species], amu.  epot, ekin:
  * device FP64 [n_steps] or NULL, the root-atom potential energy and the
  * kinetic energy (eV) after each step.  Asynchronous; never allocates; the
- * workspace (>= mpip_md_workspace_size bytes) must not be used concurrently.
+ * workspace (>= mpip_md_workspace_size bytes for the same params) must not
+ * be used concurrently; with skin > 0 the host waits for each step's
+ * displacement check.  max_edges bounds the edges closer than r_cut; the
+ * list of radius r_cut + skin gets max_edges ((r_cut + skin) / r_cut)^3 * 1.5.
  * Data-dependent errors of any step are reported by mpip_workspace_status
  * after the run (the trajectory is then undefined from that step on). */
 mpip_status mpip_md_run(mpip_model* model, const mpip_system* sys, double* positions, double* velocities,

@@ -63,7 +63,7 @@ class TimingC(ctypes.Structure):
 
 class MdParamsC(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("n_steps", ctypes.c_int64), ("friction", ctypes.c_double),
-                ("temperature", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("temperature", ctypes.c_double), ("seed", ctypes.c_uint64), ("skin", ctypes.c_double)]
 
 
 def _load():
@@ -105,7 +105,7 @@ def _load():
     lib.mpip_evaluate_batch.argtypes = [V, I32, P(I64), V, V, P(ctypes.c_double), P(ctypes.c_uint8), I32, I32, V, V,
                                         SZ, I64, V, V, V]
     lib.mpip_evaluate_batch.restype = I32
-    lib.mpip_md_workspace_size.argtypes = [V, P(SystemC), I32, I32, I64, P(SZ)]
+    lib.mpip_md_workspace_size.argtypes = [V, P(SystemC), P(MdParamsC), I32, I32, I64, P(SZ)]
     lib.mpip_md_workspace_size.restype = I32
     lib.mpip_md_run.argtypes = [V, P(SystemC), V, V, V, V, P(MdParamsC), I32, I32, V, V, SZ, I64, V, V]
     lib.mpip_md_run.restype = I32
@@ -256,10 +256,13 @@ class Model:
 
     def md_run(self, positions, velocities, species, masses, cell, pbc=(True, True, True), *, dt: float,
                n_steps: int, forces=None, friction: float = 0.0, temperature: float = 0.0, seed: int = 0,
-               K: Optional[int] = None, precision="fp32", max_edges: Optional[int] = None, stream=None):
+               skin: float = 0.0, K: Optional[int] = None, precision="fp32", max_edges: Optional[int] = None,
+               stream=None):
         """``n_steps`` MD steps on the device (mpip_md_run): BAOAB Langevin,
         velocity Verlet when ``friction`` is 0.  ``positions``, ``velocities``
-        (cuda float64 [N,3]) are updated in place; ``forces`` (cuda float64
+        (cuda float64 [N,3]) are updated in place; ``skin`` > 0 reuses a
+        neighbour list of radius r_cut + skin while no atom has moved more
+        than skin/2 (same edges as a rebuild); ``forces`` (cuda float64
         [N,3]) must hold the forces at ``positions`` or be None (then they are
         evaluated first).  ``masses``: cuda float64 [n_species] (amu).
         Returns cuda tensors epot [n_steps], ekin [n_steps] (eV) and the
@@ -277,15 +280,16 @@ class Model:
                                    stream=stream)["forces"]
         prec = PRECISIONS[precision]
         sysc = _system(positions, species, cell, pbc, None)
+        prm = MdParamsC(float(dt), int(n_steps), float(friction), float(temperature), int(seed), float(skin))
         need = ctypes.c_size_t()
-        _check(lib.mpip_md_workspace_size(self._h, ctypes.byref(sysc), prec, K, max_edges, ctypes.byref(need)))
+        _check(lib.mpip_md_workspace_size(self._h, ctypes.byref(sysc), ctypes.byref(prm), prec, K, max_edges,
+                                          ctypes.byref(need)))
         if self._ws is None or self._ws.numel() < need.value:
             self._ws = None
             self._ws = torch.empty(int(need.value), dtype=torch.uint8, device=self.device)
         ws = self._ws
         epot = torch.empty(max(n_steps, 1), dtype=torch.float64, device=self.device)
         ekin = torch.empty(max(n_steps, 1), dtype=torch.float64, device=self.device)
-        prm = MdParamsC(float(dt), int(n_steps), float(friction), float(temperature), int(seed))
         sp = _stream_ptr(torch, self.device, stream)
         _check(lib.mpip_md_run(self._h, ctypes.byref(sysc), ctypes.c_void_p(positions.data_ptr()),
                                ctypes.c_void_p(velocities.data_ptr()), ctypes.c_void_p(forces.data_ptr()),

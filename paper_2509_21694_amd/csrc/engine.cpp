@@ -907,6 +907,21 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
 }
 
 
+// the model, its adjoint and the outputs on the neighbour list already in b
+static void eval_on_list(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b, int64_t N, mpip_precision prec,
+                         int32_t K, int64_t max_edges, hipStream_t s, const mpip_outputs* out) {
+  PhaseTimer& T = m->timer;
+  const float4* g2p = run_model(m, p, w, b, N, prec, K, max_edges, s);
+  OutArgs oa;
+  oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = (float4*)(w + p.o_g); oa.g2p = g2p; oa.e_rev = b.e_rev;
+  oa.perm = b.perm; oa.owned_s = b.owned_s; oa.atom_e = (double*)(w + p.o_atom_e); oa.capacity = max_edges;
+  oa.status = b.status; oa.partials = (double*)(w + p.o_partials); oa.nblocks = p.nblocks_out;
+  oa.forces = out->forces; oa.atom_energy = out->atom_energy; oa.energy = out->energy; oa.virial = out->virial;
+  T.begin("outputs", s);
+  launch_outputs(oa, s);
+  T.end(s);
+}
+
 extern "C" {
 
 mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K, void* stream,
@@ -938,16 +953,9 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
   T.begin("neighbors", s);
   build_neighbors(b, *sys, ci, max_edges, s);
   T.end(s);
-
-  const float4* g2p = run_model(m, p, w, b, N, prec, K, max_edges, s);
-  OutArgs oa;
-  oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = g; oa.g2p = g2p; oa.e_rev = b.e_rev; oa.perm = b.perm;
-  oa.owned_s = b.owned_s; oa.atom_e = atom_e; oa.capacity = max_edges; oa.status = b.status;
-  oa.partials = (double*)(w + p.o_partials); oa.nblocks = p.nblocks_out;
-  oa.forces = out->forces; oa.atom_energy = out->atom_energy; oa.energy = out->energy; oa.virial = out->virial;
-  T.begin("outputs", s);
-  launch_outputs(oa, s);
-  T.end(s);
+  (void)g;
+  (void)atom_e;
+  eval_on_list(m, p, w, b, N, prec, K, max_edges, s, out);
   hipError_t e = hipGetLastError();
   if (cur != m->device) hipSetDevice(cur);
   if (e != hipSuccess) return fail(MPIP_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -1156,18 +1164,38 @@ mpip_status mpip_evaluate_batch(mpip_model* m, int32_t B, const int64_t* atom_pt
 namespace {
 struct MdScratch {
   size_t base, total;   // evaluation workspace bytes; plus the integrator's scratch
-  size_t o_sticky, o_energy, o_virial, o_partials;
+  size_t o_sticky, o_energy, o_virial, o_partials, o_flag;
+  // neighbour list of radius r_c + skin and what its reuse needs (skin > 0)
+  size_t o_srow = 0, o_ssrc = 0, o_sshift = 0, o_svec = 0, o_srev = 0, o_map = 0, o_xref = 0;
+  int64_t sup_cap = 0;
   int nblocks;
 };
-MdScratch md_scratch(int64_t N, int64_t max_edges, const mpip_hparams* hp, int K) {
+int64_t skin_capacity(int64_t max_edges, double r_cut, double skin) {
+  const double q = (r_cut + skin) / r_cut;
+  // 1.5: a lattice shell just outside r_cut can make the ratio well above the volume ratio
+  const double c = (double)max_edges * q * q * q * 1.5 + 1024.0;
+  return c > 2147483000.0 ? 2147483000 : (int64_t)c;
+}
+MdScratch md_scratch(int64_t N, int64_t max_edges, const mpip_hparams* hp, int K, double skin) {
   MdScratch s;
   s.base = make_plan(N, max_edges, hp, K).total;
   size_t cur = s.base;
   s.nblocks = (int)((N + 255) / 256);
   s.o_sticky = take(cur, sizeof(int64_t));
+  s.o_flag = take(cur, sizeof(int64_t));
   s.o_energy = take(cur, sizeof(double));
   s.o_virial = take(cur, 9 * sizeof(double));
   s.o_partials = take(cur, sizeof(double) * (size_t)s.nblocks);
+  if (skin > 0.0) {
+    s.sup_cap = skin_capacity(max_edges, hp->r_cut, skin);
+    s.o_srow = take(cur, sizeof(int32_t) * (size_t)(N + 1));
+    s.o_ssrc = take(cur, sizeof(int32_t) * (size_t)s.sup_cap);
+    s.o_sshift = take(cur, sizeof(uint32_t) * (size_t)s.sup_cap);
+    s.o_svec = take(cur, sizeof(float4) * (size_t)s.sup_cap);
+    s.o_srev = take(cur, sizeof(int32_t) * (size_t)s.sup_cap);
+    s.o_map = take(cur, sizeof(int32_t) * (size_t)s.sup_cap);
+    s.o_xref = take(cur, sizeof(double) * 3 * (size_t)N);
+  }
   s.total = cur + 256;
   return s;
 }
@@ -1175,12 +1203,13 @@ MdScratch md_scratch(int64_t N, int64_t max_edges, const mpip_hparams* hp, int K
 
 extern "C" {
 
-mpip_status mpip_md_workspace_size(const mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K,
-                                   int64_t max_edges, size_t* bytes) {
+mpip_status mpip_md_workspace_size(const mpip_model* m, const mpip_system* sys, const mpip_md_params* prm,
+                                   mpip_precision prec, int32_t K, int64_t max_edges, size_t* bytes) {
+  if (!prm) return fail(MPIP_EINVAL, "null params");
   size_t b = 0;
   const mpip_status st = mpip_workspace_size(m, sys, prec, K, max_edges, &b);
   if (st != MPIP_OK) return st;
-  *bytes = md_scratch(sys->n_atoms, max_edges, &m->hp, K).total;
+  *bytes = md_scratch(sys->n_atoms, max_edges, &m->hp, K, prm->skin > 0.0 ? prm->skin : 0.0).total;
   return MPIP_OK;
 }
 
@@ -1192,37 +1221,77 @@ mpip_status mpip_md_run(mpip_model* m, const mpip_system* sys, double* positions
   if (!(prm->dt > 0.0) || !std::isfinite(prm->dt)) return fail(MPIP_EINVAL, "dt must be positive");
   if (prm->n_steps < 0) return fail(MPIP_EINVAL, "n_steps must be >= 0");
   if (!(prm->friction >= 0.0) || !(prm->temperature >= 0.0)) return fail(MPIP_EINVAL, "friction and temperature must be >= 0");
+  if (!(prm->skin >= 0.0) || !std::isfinite(prm->skin)) return fail(MPIP_EINVAL, "skin must be >= 0");
+  if (prec != MPIP_FP32 && prec != MPIP_BF16_MIXED) return fail(MPIP_EINVAL, "bad precision");
   if (K < 1 || K > m->hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
   if (!ws) return fail(MPIP_EINVAL, "null workspace");
   if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  mpip_system s2 = *sys;
+  s2.positions = positions;
+  CellInfo ci;
+  mpip_status st0 = check_system(&s2, &ci, m->hp.r_cut, m->hp.n_species);
+  if (st0 != MPIP_OK) return st0;
   const int64_t N = sys->n_atoms;
-  if (N < 1) return fail(MPIP_EINVAL, "n_atoms must be >= 1");
-  const MdScratch sc = md_scratch(N, max_edges, &m->hp, K);
+  const bool skin = prm->skin > 0.0;
+  const MdScratch sc = md_scratch(N, max_edges, &m->hp, K, skin ? prm->skin : 0.0);
   if (ws_bytes < sc.total) return fail(MPIP_ECAPACITY, "workspace too small");
   int cur = 0;
   HIPCHK(hipGetDevice(&cur));
   if (cur != m->device) HIPCHK(hipSetDevice(m->device));
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
+  const Plan p = make_plan(N, max_edges, &m->hp, K);
+  const NbrBuffers b = nbr_buffers(w, p);
+  // the list of radius r_c + skin shares the atom order and scratch of b
+  NbrBuffers sup = b;
+  CellInfo ci_list = ci;
+  if (skin) {
+    sup.row_ptr = (int32_t*)(w + sc.o_srow);
+    sup.e_src = (int32_t*)(w + sc.o_ssrc);
+    sup.e_shift = (uint32_t*)(w + sc.o_sshift);
+    sup.e_vec = (float4*)(w + sc.o_svec);
+    sup.e_rev = (int32_t*)(w + sc.o_srev);
+    ci_list.rc = m->hp.r_cut + prm->skin;
+  }
+  int32_t* map = skin ? (int32_t*)(w + sc.o_map) : nullptr;
+  double* xref = skin ? (double*)(w + sc.o_xref) : nullptr;
+  int64_t* moved = (int64_t*)(w + sc.o_flag);
   int64_t* sticky = (int64_t*)(w + sc.o_sticky);
   double* energy = (double*)(w + sc.o_energy);
   double* partials = (double*)(w + sc.o_partials);
-  mpip_system s2 = *sys;
-  s2.positions = positions;
   mpip_outputs out;
   out.energy = energy;
   out.forces = forces;
   out.virial = (double*)(w + sc.o_virial);
   out.atom_energy = nullptr;
+  PhaseTimer& T = m->timer;
   launch_zero(sticky, sizeof(int64_t), s);
+  bool rebuild = true;
   for (int64_t step = 0; step < prm->n_steps; ++step) {
     md_first(N, positions, velocities, forces, sys->species, masses, prm->dt, prm->friction, prm->temperature,
-             prm->seed, step, s);
-    const mpip_status st = mpip_evaluate(m, &s2, prec, K, stream, ws, ws_bytes, max_edges, &out);
-    if (st != MPIP_OK) {
-      if (cur != m->device) hipSetDevice(cur);
-      return st;
+             prm->seed, step, xref, 0.25 * prm->skin * prm->skin, moved, s);
+    if (skin && step > 0) {
+      // the rebuild decision needs the displacement flag on the host
+      int64_t f = 0;
+      HIPCHK(hipMemcpyAsync(&f, moved, sizeof(f), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      rebuild = f != 0;
     }
+    launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
+    T.begin("neighbors", s);
+    if (!skin) {
+      build_neighbors(b, s2, ci, max_edges, s);
+    } else {
+      if (rebuild) {
+        build_neighbors(sup, s2, ci_list, sc.sup_cap, s);
+        md_reference(N, positions, xref, moved, s);
+      } else {
+        refresh_sorted(b, positions, N, s);
+      }
+      compact_list(b, sup, sc.sup_cap, map, ci, N, max_edges, s);
+    }
+    T.end(s);
+    eval_on_list(m, p, w, b, N, prec, K, max_edges, s, &out);
     md_second(N, velocities, forces, sys->species, masses, prm->dt, partials, s);
     md_record(partials, sc.nblocks, energy, (const int64_t*)w, epot ? epot + step : nullptr,
               ekin ? ekin + step : nullptr, sticky, s);

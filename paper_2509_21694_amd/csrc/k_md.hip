@@ -53,9 +53,11 @@ __device__ __forceinline__ void normals3(uint64_t seed, int64_t atom, int64_t st
 }
 
 // B, A, O, A of one step (everything before the new forces)
+// (with a reference: flags an atom that has moved more than sqrt(thr2) since the list was built)
 __global__ void k_md_first(int64_t n, double* __restrict__ x, double* __restrict__ v, const double* __restrict__ f,
                            const int32_t* __restrict__ spec, const double* __restrict__ masses, double dt, double c1,
-                           double c2, double kT, uint64_t seed, int64_t step) {
+                           double c2, double kT, uint64_t seed, int64_t step, const double* __restrict__ xref,
+                           double thr2, int64_t* __restrict__ moved) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double m = masses[spec[i]];
@@ -73,11 +75,24 @@ __global__ void k_md_first(int64_t n, double* __restrict__ x, double* __restrict
 #pragma unroll
     for (int d = 0; d < 3; ++d) vi[d] = c1 * vi[d] + c2 * sig * z[d];
   }
+  double d2 = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    x[3 * i + d] = xi[d] + 0.5 * dt * vi[d];
+    const double xn = xi[d] + 0.5 * dt * vi[d];
+    x[3 * i + d] = xn;
     v[3 * i + d] = vi[d];
+    if (xref) d2 += (xn - xref[3 * i + d]) * (xn - xref[3 * i + d]);
   }
+  if (xref && d2 > thr2) atomicOr((unsigned long long*)moved, 1ull);
+}
+
+// the positions the neighbour list was built for
+__global__ void k_md_reference(int64_t n, const double* __restrict__ x, double* __restrict__ xref,
+                               int64_t* __restrict__ moved) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i == 0) *moved = 0;
+  if (i >= 3 * n) return;
+  xref[i] = x[i];
 }
 
 // B with the new forces; per-block sums of the kinetic energy (eV), fixed order
@@ -136,10 +151,15 @@ __global__ void k_md_flags(const int64_t* __restrict__ sticky, int64_t* __restri
 }  // namespace
 
 void md_first(int64_t n, double* x, double* v, const double* f, const int32_t* spec, const double* masses, double dt,
-              double friction, double temperature, uint64_t seed, int64_t step, hipStream_t s) {
+              double friction, double temperature, uint64_t seed, int64_t step, const double* xref, double thr2,
+              int64_t* moved, hipStream_t s) {
   const double c1 = exp(-friction * dt), c2 = sqrt(1.0 - c1 * c1);
   k_md_first<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, x, v, f, spec, masses, dt, c1, c2,
-                                                          kBoltzmann * temperature, seed, step);
+                                                          kBoltzmann * temperature, seed, step, xref, thr2, moved);
+}
+
+void md_reference(int64_t n, const double* x, double* xref, int64_t* moved, hipStream_t s) {
+  k_md_reference<<<(unsigned)((3 * n + 255) / 256), 256, 0, s>>>(n, x, xref, moved);
 }
 
 void md_second(int64_t n, double* v, const double* f, const int32_t* spec, const double* masses, double dt,

@@ -590,6 +590,123 @@ __global__ void k_nbr_export(int64_t n, const int32_t* __restrict__ row_ptr, con
   }
 }
 
+// ---------------------------------------------------------------- list reuse
+// A list built with a larger radius r_c + skin (the "superset": rows sup_row,
+// senders sup_src, shifts sup_shift, reverse edges sup_rev) stays valid while
+// no atom has moved more than skin/2: every pair now closer than r_c is in it
+// with the same image shift.  Each evaluation then re-applies the FP64
+// predicate d < r_c to the superset's (i, j, S) at the current positions and
+// compacts the kept edges, in superset order, into the working list.
+
+// sorted positions from the input positions (the permutation of the build)
+__global__ void k_refresh_sorted(const double* __restrict__ pos, const int32_t* __restrict__ perm, int64_t n,
+                                 double* __restrict__ pos_s) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t o = perm[k];
+  pos_s[3 * k] = pos[3 * o];
+  pos_s[3 * k + 1] = pos[3 * o + 1];
+  pos_s[3 * k + 2] = pos[3 * o + 2];
+}
+
+// one wave per row: keep flag of every superset edge (in map) and the row's count
+__global__ __launch_bounds__(256) void k_skin_count(int64_t n, const double* __restrict__ pos_s, CellInfo ci,
+                                                    const int32_t* __restrict__ sup_row,
+                                                    const int32_t* __restrict__ sup_src,
+                                                    const uint32_t* __restrict__ sup_shift, int64_t sup_cap,
+                                                    int32_t* __restrict__ map, int32_t* __restrict__ cnt,
+                                                    int64_t* __restrict__ status) {
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n || sup_row[n] > sup_cap) return;
+  const double xi[3] = {pos_s[3 * i], pos_s[3 * i + 1], pos_s[3 * i + 2]};
+  const double rc2 = ci.rc * ci.rc;
+  int count = 0, coincident = 0;
+  for (int e0 = sup_row[i]; e0 < sup_row[i + 1]; e0 += 64) {
+    const int e = e0 + lane;
+    bool keep = false;
+    if (e < sup_row[i + 1]) {
+      const int64_t j = sup_src[e];
+      const uint32_t sh = sup_shift[e];
+      const double xj[3] = {pos_s[3 * j], pos_s[3 * j + 1], pos_s[3 * j + 2]};
+      double dx[3];
+      keep = pair_test(xi, xj, ci, (int8_t)(sh & 0xff), (int8_t)((sh >> 8) & 0xff), (int8_t)((sh >> 16) & 0xff), rc2, dx);
+      if (keep && dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+      map[e] = keep ? 1 : 0;
+    }
+    count += __popcll(__ballot(keep));
+  }
+  if (lane == 0) cnt[i] = count;
+  if (__any(coincident) && lane == 0) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_COINCIDENT);
+}
+
+// one wave per row: kept edges written in superset order; map[e] becomes the
+// working index of superset edge e (or -1)
+__global__ __launch_bounds__(256) void k_skin_fill(int64_t n, const double* __restrict__ pos_s,
+                                                   const int32_t* __restrict__ spec_s, CellInfo ci,
+                                                   const int32_t* __restrict__ sup_row,
+                                                   const int32_t* __restrict__ sup_src,
+                                                   const uint32_t* __restrict__ sup_shift, int64_t sup_cap,
+                                                   const int32_t* __restrict__ row_ptr, int64_t capacity,
+                                                   int32_t* __restrict__ map, int32_t* __restrict__ e_src,
+                                                   uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec) {
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n || sup_row[n] > sup_cap || row_ptr[n] > capacity) return;
+  const double xi[3] = {pos_s[3 * i], pos_s[3 * i + 1], pos_s[3 * i + 2]};
+  int64_t out = row_ptr[i];
+  for (int e0 = sup_row[i]; e0 < sup_row[i + 1]; e0 += 64) {
+    const int e = e0 + lane;
+    const bool in = e < sup_row[i + 1];
+    const bool keep = in && map[e] != 0;
+    const unsigned long long m = __ballot(keep);
+    if (keep) {
+      const int64_t k = out + __popcll(m & ((1ull << lane) - 1ull));
+      const int32_t j = sup_src[e];
+      const uint32_t sh = sup_shift[e];
+      const int S0 = (int8_t)(sh & 0xff), S1 = (int8_t)((sh >> 8) & 0xff), S2 = (int8_t)((sh >> 16) & 0xff);
+      const double xj[3] = {pos_s[3 * (int64_t)j], pos_s[3 * (int64_t)j + 1], pos_s[3 * (int64_t)j + 2]};
+      double dx[3];
+      pair_test(xi, xj, ci, S0, S1, S2, 0.0, dx);
+      e_src[k] = j;
+      e_shift[k] = sh;
+      e_vec[k] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], __int_as_float(spec_s[j]));
+      map[e] = (int32_t)k;
+    } else if (in) {
+      map[e] = -1;
+    }
+    out += __popcll(m);
+  }
+}
+
+// reverse edges of the working list through the superset's
+__global__ void k_skin_rev(int64_t n, const int32_t* __restrict__ sup_row, const int32_t* __restrict__ sup_rev,
+                           int64_t sup_cap, const int32_t* __restrict__ map, const int32_t* __restrict__ row_ptr,
+                           int64_t capacity, int32_t* __restrict__ e_rev) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (sup_row[n] > sup_cap || row_ptr[n] > capacity || e >= sup_row[n]) return;
+  const int k = map[e];
+  if (k < 0) return;
+  const int r = sup_rev[e];
+  e_rev[k] = r >= 0 ? map[r] : -1;
+}
+
+void refresh_sorted(const NbrBuffers& b, const double* pos, int64_t n, hipStream_t s) {
+  k_refresh_sorted<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pos, b.perm, n, b.pos_s);
+}
+
+void compact_list(const NbrBuffers& b, const NbrBuffers& sup, int64_t sup_cap, int32_t* map, const CellInfo& ci,
+                  int64_t n, int64_t capacity, hipStream_t s) {
+  const unsigned gw = (unsigned)((n + 3) / 4);
+  k_skin_count<<<gw, 256, 0, s>>>(n, b.pos_s, ci, sup.row_ptr, sup.e_src, sup.e_shift, sup_cap, map, b.cnt, b.status);
+  exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
+  k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
+  k_skin_fill<<<gw, 256, 0, s>>>(n, b.pos_s, b.spec_s, ci, sup.row_ptr, sup.e_src, sup.e_shift, sup_cap, b.row_ptr,
+                                 capacity, map, b.e_src, b.e_shift, b.e_vec);
+  k_skin_rev<<<(unsigned)((sup_cap + 255) / 256), 256, 0, s>>>(n, sup.row_ptr, sup.e_rev, sup_cap, map, b.row_ptr,
+                                                               capacity, b.e_rev);
+}
+
 // ---------------------------------------------------------------- driver
 
 void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo& ci, int64_t capacity,

@@ -42,6 +42,14 @@ struct NbrBuffers {
   int32_t* e_dst;        // [cap] receiver (sorted index) of each edge, for edge-parallel passes
 };
 
+// neighbour-list reuse within a skin: sorted positions refreshed from the
+// input positions, and the working list (in b) compacted from a list built
+// with a larger radius (row_ptr, e_src, e_shift, e_rev of `sup`) by the FP64
+// predicate at ci.rc; map: [sup_cap] scratch
+void refresh_sorted(const NbrBuffers& b, const double* pos, int64_t n, hipStream_t s);
+void compact_list(const NbrBuffers& b, const NbrBuffers& sup, int64_t sup_cap, int32_t* map, const CellInfo& ci,
+                  int64_t n, int64_t capacity, hipStream_t s);
+
 int64_t scan_tmp_elems(int64_t n);
 void exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s);
 void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo& ci, int64_t capacity,
@@ -132,7 +140,9 @@ void launch_nodeK(int C, const NodeKArgs& a, hipStream_t s);
 // molecular dynamics (k_md.hip): the two halves of a BAOAB / velocity-Verlet
 // step around the force evaluation, and the per-step energy record
 void md_first(int64_t n, double* x, double* v, const double* f, const int32_t* spec, const double* masses, double dt,
-              double friction, double temperature, uint64_t seed, int64_t step, hipStream_t s);
+              double friction, double temperature, uint64_t seed, int64_t step, const double* xref, double thr2,
+              int64_t* moved, hipStream_t s);
+void md_reference(int64_t n, const double* x, double* xref, int64_t* moved, hipStream_t s);
 void md_second(int64_t n, double* v, const double* f, const int32_t* spec, const double* masses, double dt,
                double* partials, hipStream_t s);
 void md_record(const double* partials, int nblocks, const double* energy, const int64_t* status, double* epot,
