@@ -84,7 +84,9 @@ typedef struct {
   double* energy;          /* device [1]: sum of root-atom energies, eV              */
   double* forces;          /* device [N,3]: -dE/dx_i, eV/Angstrom, input atom order  */
   double* virial;          /* device [9]: W = -sum_e r_e (x) dE/dr_e, eV, row-major  */
-  double* atom_energy;     /* device [N] per-atom energies E_i (input order), or NULL */
+  double* atom_energy;     /* device [N] per-atom energies E_i (input order), or NULL;
+                              zero on the non-root atoms of a trimmed share
+                              (see mpip_evaluate)                                      */
 } mpip_outputs;
 
 typedef struct mpip_model mpip_model;
@@ -122,7 +124,17 @@ mpip_status mpip_workspace_size(const mpip_model* model, const mpip_system* sys,
  * once.  Data-dependent errors (edge capacity exceeded, species out of range,
  * non-finite positions, coincident atoms) are recorded in the workspace and
  * reported by mpip_workspace_status after the stream is synchronised; the
- * outputs are then undefined.  Orthorhombic cells only (else EUNSUPPORTED). */
+ * outputs are then undefined.  Orthorhombic cells only (else EUNSUPPORTED).
+ *
+ * Partition shares (0 < n_owned < n_atoms, n_atoms >= 64): the energy of the
+ * root atoms after K layers depends only on their K-hop neighbourhood
+ * (Methods "Graph Partitioning"), so layer t is evaluated only on atoms
+ * within K - t hops of a root (receptive-field trimming).  The hop classes
+ * are found on the device by a breadth-first expansion over the built list
+ * and read back once: such a call synchronises `stream` once, after the
+ * neighbour list is built.  Energy, forces (including the partial forces on
+ * halo atoms) and virial are those of the root energy, as without trimming;
+ * atom_energy holds E_i on the roots and zero on every other atom. */
 mpip_status mpip_evaluate(mpip_model* model, const mpip_system* sys, mpip_precision prec,
                           int32_t K, void* stream, void* workspace, size_t workspace_bytes,
                           int64_t max_edges, const mpip_outputs* out);
@@ -250,7 +262,7 @@ mpip_status mpip_md_run(mpip_model* model, const mpip_system* sys, double* posit
  * evaluation records HIP events around its kernel phases on the evaluation
  * stream (no synchronisation); mpip_timing_read synchronises those events,
  * adds their durations to per-phase totals and returns the totals since the
- * last enable.  Phase names: "neighbors", "node_gemm", "gates", "outputs",
+ * last enable.  Phase names: "neighbors", "trim", "node_gemm", "gates", "outputs",
  * "node_fused", "node_last", "edge_fwd_t<k>", "edge_sum_t<k>",
  * "edge_bwd_t<k>", "edge_pull_t<k>" (k = layer).  Host-side only; the model
  * must not be evaluated concurrently on two streams while enabled. */

@@ -665,8 +665,13 @@ mpip_status mpip_neighbor_list(const mpip_system* sys, double r_cut, void* strea
 // leaves dE/dr_e in the workspace (g) and per-atom energies (atom_e).
 // Returns the buffer holding the last layer's part of the edge gradients
 // when it is kept apart from g (see FastArgs::g2p), else null.
+// rows: null, or rows[t] (t = 0..K) = the row prefix that layer t updates on
+// a share whose rows are sorted by hop class (receptive-field trimming):
+// layer t's receivers are rows < rows[t], and the passes that act on senders
+// (features into layer t, the adjoint's pull) cover rows < rows[t - 1].
 static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b, int64_t N,
-                               mpip_precision prec, int32_t K, int64_t max_edges, hipStream_t s) {
+                               mpip_precision prec, int32_t K, int64_t max_edges, hipStream_t s,
+                               const int64_t* rows = nullptr) {
   const mpip_hparams& hp = m->hp;
   const int C = hp.channels, L = hp.l_max, nlm = (L + 1) * (L + 1), S = hp.n_species;
   const int pi = prec == MPIP_BF16_MIXED ? 1 : 0;
@@ -679,6 +684,12 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
   float4* g = (float4*)(w + p.o_g);
   double* atom_e = (double*)(w + p.o_atom_e);
   PhaseTimer& T = m->timer;
+  // rows layer t updates (R(0) = N: layer-1 senders are all atoms)
+  auto R = [&](int t) -> int64_t { return rows ? rows[t] : N; };
+  // zero rows [r0, N) of an array with `width` floats per row
+  auto zero_rows = [&](float* base, int64_t r0, int64_t width) {
+    if (r0 < N) launch_zero(base + r0 * width, sizeof(float) * (size_t)((N - r0) * width), s);
+  };
   EdgeArgs ea;
   ea.n = N;
   ea.row_ptr = b.row_ptr;
@@ -768,20 +779,24 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
     if (t >= 2 && !node1)
       for (int l = 0; l <= L; ++l)
         gemm(h + l * l * C, (int64_t)nlm * C, C, at(ht, l * l * C, fast ? ht_bf16 : 0), (int64_t)nlm * C, C,
-             N * (2 * l + 1), 2 * l + 1, C, C, C, d.up_t[l], 0, fast ? ht_bf16 : 0);
+             R(t - 1) * (2 * l + 1), 2 * l + 1, C, C, C, d.up_t[l], 0, fast ? ht_bf16 : 0);
     T.begin("edge_fwd_t" + std::to_string(t), s);
     if (fast) {
       set_fast(d, role);
       if (kind == KIND_FIRST) {
+        fa.n = R(1);
         launch_l1(prec, L, true, fa, s);
       } else {
         fa.ht = ht; fa.A = A;
         if (ht_bf16 && fa.msg) {
+          fa.n = R(K - 1);   // sender-side: rows whose features feed the roots
           launch_l2(prec, C, L, 4, fa, s);
           T.end(s);
           T.begin("edge_sum_t" + std::to_string(t), s);
+          fa.n = R(K);
           launch_l2(prec, C, L, 5, fa, s);
         } else {
+          fa.n = R(K);
           launch_l2(prec, C, L, 0, fa, s);
         }
       }
@@ -789,6 +804,7 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
       ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;
       ea.w3f = d.w3f[role]; ea.w3b = d.w3b[role]; ea.cg = d.cg[role];
       ea.ht = ht; ea.A = A;
+      ea.n = R(t);
       launch_edge_fwd(prec, C, L, kind, ea, s);
     }
     T.end(s);
@@ -796,6 +812,7 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
     float* zl = t < K ? (float*)(w + p.o_zl[t - 1]) : nullptr;
     if (node1 && t == 1) {
       T.begin("node_fused", s);
+      n1.n = R(1);
       launch_node1(true, C, L, S, n1, s);
       T.end(s);
       continue;
@@ -803,39 +820,48 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
     if (nodeK && t == K) {
       // node update, readout and their adjoint: atom energies, and dE/dA over A
       T.begin("node_last", s);
+      nk.n = R(K);
       launch_nodeK(C, nk, s);
       T.end(s);
       continue;
     }
+    const int64_t Mt = R(t);
     if (fast && kind == KIND_FIRST) {
       // z_l = Q_l (V_l W_down_l) (Q in BF16 in the BF16 form); the messages are never stored
-      gemm(at(qp, 0, ht_bf16), (int64_t)nlm * KQ, 0, z0, nz, 0, N, 1, KQ, nz, KQ, d.vwt[0], 0, 0, ht_bf16);
+      gemm(at(qp, 0, ht_bf16), (int64_t)nlm * KQ, 0, z0, nz, 0, Mt, 1, KQ, nz, KQ, d.vwt[0], 0, 0, ht_bf16);
       for (int l = 1; l <= L; ++l)
         gemm(at(qp, l * l * KQ, ht_bf16), (int64_t)nlm * KQ, KQ, zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C,
-             N * (2 * l + 1), 2 * l + 1, KQ, C, KQ, d.vwt[l], 0, 0, ht_bf16);
+             Mt * (2 * l + 1), 2 * l + 1, KQ, C, KQ, d.vwt[l], 0, 0, ht_bf16);
     } else {
-      gemm(A, (int64_t)nout * C, 0, z0, nz, 0, N, 1, C, (t == K) ? C : nz, C, d.down_t[0], 0);
+      gemm(A, (int64_t)nout * C, 0, z0, nz, 0, Mt, 1, C, (t == K) ? C : nz, C, d.down_t[0], 0);
       if (t < K)
         for (int l = 1; l <= L; ++l)
-          gemm(A + l * l * C, (int64_t)nlm * C, C, zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, N * (2 * l + 1),
+          gemm(A + l * l * C, (int64_t)nlm * C, C, zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, Mt * (2 * l + 1),
                2 * l + 1, C, C, C, d.down_t[l], 0);
     }
     na.z0 = z0; na.zl = zl;
+    na.n = Mt;
     T.begin("gates", s);
     launch_gate_fwd(na, t == 1, t == K, s);
     T.end(s);
   }
   if (!nodeK) {
     T.begin("gates", s);
+    na.n = R(K);
     launch_readout(na, s);
     T.end(s);
   }
+  // atoms beyond the roots' receptive field get no energy
+  if (rows && R(K) < N) launch_zero(atom_e + R(K), sizeof(double) * (size_t)(N - R(K)), s);
 
   // ---------------- adjoint ----------------
   T.begin("outputs", s);
   if (!fa.g2p) launch_zero(g, sizeof(float4) * (size_t)max_edges, s);
   // the FP32 form's edge-parallel adjoint needs each edge's receiver
   if (fast_layer(K) && kind_of(K) == KIND_LAST && !ht_bf16) edge_receivers(b, N, max_edges, s);
+  // trimmed: the adjoint's pull adds into hbar rows up to R(K - 1), the
+  // layer-K seed (gate adjoint) writes rows < R(K) only
+  if (rows && !node1 && K >= 2) zero_rows(hbar, R(K), (int64_t)nlm * C);
   T.end(s);
   for (int t = K; t >= 1; --t) {
     const LayerDev& d = LD[t - 1];
@@ -848,46 +874,58 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
     na.z0 = z0; na.zl = zl;
     if (node1 && t == 1) {
       T.begin("node_fused", s);
+      n1.n = R(1);
       launch_node1(false, C, L, S, n1, s);
       T.end(s);
       T.begin("edge_bwd_t1", s);
       set_fast(d, role);
+      fa.n = R(1);
       launch_l1(prec, L, false, fa, s);
       T.end(s);
       continue;
     }
-    if (nodeK && t == K) goto edge_adjoint;   // dE/dA is already in A
+    if (nodeK && t == K) {
+      // dE/dA is already in A on the roots; the pull reads it on every receiver
+      if (rows) zero_rows(A, R(K), (int64_t)nout * C);
+      goto edge_adjoint;
+    }
+    na.n = R(t);
     T.begin("gates", s);
     launch_gate_bwd(na, t == K, (t == K && K >= 2 && !node1) ? 1 : 0, s);
     T.end(s);
     if (fast && kind == KIND_FIRST) {
       // P_l = zbar_l (V_l W_down_l)^T (P in BF16 in the BF16 form)
-      gemm(z0, nz, 0, at(qp, 0, ht_bf16), (int64_t)nlm * KQ, 0, N, 1, nz, KQ, nz, d.vw[0], 0, ht_bf16);
+      gemm(z0, nz, 0, at(qp, 0, ht_bf16), (int64_t)nlm * KQ, 0, R(1), 1, nz, KQ, nz, d.vw[0], 0, ht_bf16);
       for (int l = 1; l <= L; ++l)
         gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, at(qp, l * l * KQ, ht_bf16), (int64_t)nlm * KQ, KQ,
-             N * (2 * l + 1), 2 * l + 1, C, KQ, C, d.vw[l], 0, ht_bf16);
+             R(1) * (2 * l + 1), 2 * l + 1, C, KQ, C, d.vw[l], 0, ht_bf16);
     } else {
-      // Abar (in A) = zbar @ W_down^T
-      gemm(z0, nz, 0, A, (int64_t)nout * C, 0, N, 1, (t == K) ? C : nz, C, nz, d.down[0], 0);
+      // Abar (in A) = zbar @ W_down^T; zero beyond layer t's receivers
+      gemm(z0, nz, 0, A, (int64_t)nout * C, 0, R(t), 1, (t == K) ? C : nz, C, nz, d.down[0], 0);
       if (t < K)
         for (int l = 1; l <= L; ++l)
-          gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, A + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
+          gemm(zl + (l * l - 1) * C, (int64_t)(nlm - 1) * C, C, A + l * l * C, (int64_t)nlm * C, C, R(t) * (2 * l + 1),
                2 * l + 1, C, C, C, d.down[l], 0);
+      if (rows) zero_rows(A, R(t), (int64_t)nout * C);
     }
   edge_adjoint:
     T.begin("edge_bwd_t" + std::to_string(t), s);
     if (fast) {
       set_fast(d, role);
       if (kind == KIND_FIRST) {
+        fa.n = R(1);
         launch_l1(prec, L, false, fa, s);
       } else {
         fa.ht = ht; fa.Abar = A;
         if (ht_bf16) {
+          fa.n = R(K - 1);   // sender-side
           launch_l2(prec, C, L, 3, fa, s);
         } else {
+          fa.n = R(K);       // edge-parallel over the roots' edges
           launch_l2(prec, C, L, 1, fa, s);
           T.end(s);
           T.begin("edge_pull_t" + std::to_string(t), s);
+          fa.n = R(K - 1);   // pull onto the senders
           launch_l2(prec, C, L, 2, fa, s);
         }
       }
@@ -895,13 +933,21 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
       ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;
       ea.w3f = d.w3f[role]; ea.w3b = d.w3b[role]; ea.cg = d.cg[role];
       ea.ht = ht; ea.Abar = A;
+      // every row with a receiver of layer t among its neighbours
+      ea.n = R(t - 1);
       launch_edge_bwd(prec, C, L, kind, ea, s);
     }
     T.end(s);
     if (t >= 2 && !node1)
       for (int l = 0; l <= L; ++l)
-        gemm(htbar + l * l * C, (int64_t)nlm * C, C, hbar + l * l * C, (int64_t)nlm * C, C, N * (2 * l + 1),
+        gemm(htbar + l * l * C, (int64_t)nlm * C, C, hbar + l * l * C, (int64_t)nlm * C, C, R(t - 1) * (2 * l + 1),
              2 * l + 1, C, C, C, d.up[l], 1);
+  }
+  if (rows && fa.g2p) {
+    // g (layer 1) and g2p (last layer) are written, not accumulated, on the
+    // rows the passes walked; the rest must read as zero
+    zero_edges_from(g, b.row_ptr, R(1), N, max_edges, s);
+    zero_edges_from(fa.g2p, b.row_ptr, R(K - 1), N, max_edges, s);
   }
   return fa.g2p;
 }
@@ -909,9 +955,10 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
 
 // the model, its adjoint and the outputs on the neighbour list already in b
 static void eval_on_list(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b, int64_t N, mpip_precision prec,
-                         int32_t K, int64_t max_edges, hipStream_t s, const mpip_outputs* out) {
+                         int32_t K, int64_t max_edges, hipStream_t s, const mpip_outputs* out,
+                         const int64_t* rows = nullptr) {
   PhaseTimer& T = m->timer;
-  const float4* g2p = run_model(m, p, w, b, N, prec, K, max_edges, s);
+  const float4* g2p = run_model(m, p, w, b, N, prec, K, max_edges, s, rows);
   OutArgs oa;
   oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = (float4*)(w + p.o_g); oa.g2p = g2p; oa.e_rev = b.e_rev;
   oa.perm = b.perm; oa.owned_s = b.owned_s; oa.atom_e = (double*)(w + p.o_atom_e); oa.capacity = max_edges;
@@ -953,9 +1000,26 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
   T.begin("neighbors", s);
   build_neighbors(b, *sys, ci, max_edges, s);
   T.end(s);
-  (void)g;
   (void)atom_e;
-  eval_on_list(m, p, w, b, N, prec, K, max_edges, s, out);
+  std::vector<int64_t> rows;
+  if (sys->n_owned > 0 && sys->n_owned < N && N >= trim_min_atoms() && K <= trim_max_layers()) {
+    // receptive-field trimming of a partition share: hop classes from the
+    // roots, read back once, then the rows are re-ordered by class
+    T.begin("trim", s);
+    const int64_t* d = trim_classes(b, N, K, max_edges, s);
+    T.end(s);
+    std::vector<int64_t> hb(K + 3);
+    HIPCHK(hipMemcpyAsync(hb.data(), d, sizeof(int64_t) * (K + 3), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hb[K + 2] == 0) {   // else the list is unusable and every pass skips on the status word
+      T.begin("trim", s);
+      trim_permute(b, N, max_edges, g, s);
+      T.end(s);
+      rows.resize(K + 1);
+      for (int t = 0; t <= K; ++t) rows[t] = hb[K - t + 1];
+    }
+  }
+  eval_on_list(m, p, w, b, N, prec, K, max_edges, s, out, rows.empty() ? nullptr : rows.data());
   hipError_t e = hipGetLastError();
   if (cur != m->device) hipSetDevice(cur);
   if (e != hipSuccess) return fail(MPIP_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));

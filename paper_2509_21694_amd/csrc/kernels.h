@@ -50,6 +50,20 @@ void refresh_sorted(const NbrBuffers& b, const double* pos, int64_t n, hipStream
 void compact_list(const NbrBuffers& b, const NbrBuffers& sup, int64_t sup_cap, int32_t* map, const CellInfo& ci,
                   int64_t n, int64_t capacity, hipStream_t s);
 
+// receptive-field trimming of a partition share (k_trim.hip): hop classes
+// from the root atoms (owned_s) over the built list, K - 1 breadth-first
+// levels (class K = K or more hops); returns a device array bounds[0..K+2]:
+// first row of each class in the class-sorted order, n, and 1 if the list is
+// unusable (then nothing may be permuted).  Needs n >= trim_min_atoms().
+const int64_t* trim_classes(const NbrBuffers& b, int64_t n, int K, int64_t capacity, hipStream_t s);
+// re-orders the rows (node arrays, CSR, senders, reverse edges) by class;
+// tmp: [capacity] float4 scratch
+void trim_permute(const NbrBuffers& b, int64_t n, int64_t capacity, float4* tmp, hipStream_t s);
+// g[e] = 0 for the edges of rows row0 .. n-1
+void zero_edges_from(float4* g, const int32_t* row_ptr, int64_t row0, int64_t n, int64_t capacity, hipStream_t s);
+int trim_max_layers();
+constexpr int64_t trim_min_atoms() { return 64; }
+
 int64_t scan_tmp_elems(int64_t n);
 void exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s);
 void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo& ci, int64_t capacity,

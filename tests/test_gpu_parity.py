@@ -48,7 +48,7 @@ def edge_set(i, j, S):
     return set(zip(np.asarray(i).tolist(), np.asarray(j).tolist(), map(tuple, np.asarray(S).tolist())))
 
 
-def compare(o, ref, n, prec, label, volume):
+def compare(o, ref, n, prec, label, volume, n_owned=None):
     E = float(o["energy"].cpu()[0])
     F = o["forces"].cpu().numpy()
     Wv = o["virial"].cpu().numpy()
@@ -71,9 +71,13 @@ def compare(o, ref, n, prec, label, volume):
         assert rms <= 2e-2 * frms
         assert dW / volume <= 1e-5
     if o.get("atom_energy") is not None:
+        # a partition share (n_owned < N) is trimmed to the roots' receptive
+        # field: atom energies on the roots, zero elsewhere
         ae = o["atom_energy"].cpu().numpy()
+        k = ae.shape[0] if n_owned is None else n_owned
         tol = 1e-6 if prec == "fp32" else 1e-3
-        assert np.abs(ae - ref.atom_energy).max() <= tol
+        assert np.abs(ae[:k] - ref.atom_energy[:k]).max() <= tol
+        assert np.all(ae[k:] == 0.0)
 
 
 # ----------------------------------------------------------- neighbour list
@@ -150,7 +154,7 @@ def test_small_e0_and_ghost_rows(torch, M):
     model = M.Model(W.HP_SMALL, blob)
     pos, sp = dev_inputs(torch, s)
     o = model.evaluate(pos, sp, s.cell, s.pbc, precision="fp32", n_owned=n_own, atom_energy=True)
-    compare(o, ref, s.n_atoms, "fp32", "small n_owned=50", abs(np.linalg.det(s.cell)))
+    compare(o, ref, s.n_atoms, "fp32", "small n_owned=50", abs(np.linalg.det(s.cell)), n_owned=n_own)
 
 
 def test_determinism_and_autograd(torch, M, small_case):
