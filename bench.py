@@ -185,6 +185,8 @@ def main():
                          "traffic for scaling hardware byte counters)")
     ap.add_argument("--md-steps", type=int, default=10,
                     help="also time this many on-device MD steps (first precision; 0: skip)")
+    ap.add_argument("--partitioned-steps", type=int, default=2,
+                    help="also time this many evaluations of the 8M-atom box as 8 slab partitions (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -285,6 +287,36 @@ def main():
               "us_per_atom_step": round(md_ms * 1e3 / N, 6), "ms_per_step": round(md_ms, 4),
               "steps": args.md_steps, "dtype": head,
               "energy_drift_per_atom": float(np.abs(et - et[0]).max() / N)}
+    part = None
+    if args.partitioned_steps > 0:
+        # one-GPU partitioned mode: the whole 200^3 box in 8 slabs along x,
+        # halo K r_cut, each share built, evaluated (trimmed) and integrated
+        # on the device one after the other (mpip_evaluate_partitioned)
+        Kp, n_parts = 2, 8
+        s8 = W.slab_full_system(200, 200, 200, 401, 402)
+        hp8 = W.HP_MPDP
+        model8 = M.Model(hp8, W.make_weights(hp8, W.WEIGHT_SEEDS["slab8m"]))
+        p8 = torch.tensor(s8.positions, dtype=torch.float64, device=dev)
+        sp8 = torch.tensor(s8.species, dtype=torch.int32, device=dev)
+        o8 = model8.evaluate_partitioned(p8, sp8, s8.cell, s8.pbc, n_parts=n_parts, K=Kp, precision=head)
+        parts = o8["parts"]
+        ml, me = int(parts[:, 0].max() * 1.02) + 1024, int(parts[:, 2].max() * 1.02) + 4096
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.partitioned_steps):
+            model8.evaluate_partitioned(p8, sp8, s8.cell, s8.pbc, n_parts=n_parts, K=Kp, precision=head,
+                                        max_local=ml, max_edges=me)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p_ms = (t1 - t0) / args.partitioned_steps * 1e3
+        log(f"partitioned ({head}): {p_ms:.3f} ms per 8M-atom evaluation")
+        part = {"metric": "atom-steps/s of a whole 8,000,000-atom box evaluated as 8 slab partitions one after "
+                          "the other on one GPU (K=2, l_max=2, C=64, halo 2 r_cut, trimmed shares)",
+                "value": round(s8.n_atoms / (p_ms * 1e-3), 1), "ms_per_step": round(p_ms, 3),
+                "steps": args.partitioned_steps, "dtype": head, "n_parts": n_parts,
+                "halo_growth_H": round(float(parts[:, 0].sum()) / s8.n_atoms - 1.0, 4),
+                "share_rows_max": int(parts[:, 0].max()), "share_edges_max": int(parts[:, 2].max())}
+        del model8, p8, sp8, o8
     line = {"metric": METRIC, "value": results[head]["value"], "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": results[head]["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,
@@ -297,7 +329,8 @@ def main():
             "roofline": results[head]["roofline"],
             "cpu_baseline": base or None,
             "forms": results,
-            "md": md}
+            "md": md,
+            "partitioned": part}
     if "bf16" in results and "fp32" in results:
         line["bf16_speedup_over_fp32"] = round(results["fp32"]["ms_per_step"] / results["bf16"]["ms_per_step"], 3)
     print(json.dumps(line))

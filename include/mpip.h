@@ -195,6 +195,37 @@ mpip_status mpip_slab_share(const double* positions, const int32_t* species, int
                             int64_t capacity, double* out_positions, int32_t* out_species,
                             int32_t* out_index, int64_t* n_local, int64_t* n_owned);
 
+/* Sequential evaluation of a whole structure in n_parts partitions on one GPU
+ * (the one-GPU mode of the paper's pipeline: Methods "Graph Partitioning"
+ * and "Global Output Integration").  For part = 0 .. n_parts-1: the slab and
+ * its halo of depth `halo` along `axis` are built on the device as by
+ * mpip_slab_share, evaluated as a share (its root atoms owned, pbc[axis] = 0,
+ * receptive-field trimming as in mpip_evaluate), and integrated into `out`:
+ * energy and virial summed over parts, every share row's partial force added
+ * to the atom it copies, root-atom energies stored (atom_energy optional).
+ * With halo >= K r_cut and a cutoff shorter than every slab, the outputs are
+ * those of one evaluation of the whole structure (up to summation order).
+ * sys: the whole structure, n_owned == n_atoms, orthorhombic, periodic along
+ * `axis`.  max_local bounds the rows of one share, max_edges its directed
+ * edges; the workspace (device) holds mpip_partitioned_workspace_size bytes
+ * for the same arguments, and is reused for every part, so the structure
+ * itself may be far larger than one evaluation's workspace allows.
+ * part_sizes: NULL or host int64 [3 n_parts] receiving per part (rows,
+ * roots, directed edges): halo growth H = rows / roots - 1.
+ * Synchronous (each share's size and status are read back).  Errors: those of
+ * mpip_slab_share (ECAPACITY: a share has more than max_local rows, its size
+ * in part_sizes) and of mpip_evaluate / mpip_workspace_status (ECAPACITY: more
+ * than max_edges edges, the count in part_sizes); the outputs are then
+ * incomplete. */
+mpip_status mpip_partitioned_workspace_size(const mpip_model* model, const mpip_system* sys,
+                                            mpip_precision prec, int32_t K, int32_t n_parts, int32_t axis,
+                                            double halo, int64_t max_local, int64_t max_edges,
+                                            size_t* bytes);
+mpip_status mpip_evaluate_partitioned(mpip_model* model, const mpip_system* sys, mpip_precision prec,
+                                      int32_t K, int32_t n_parts, int32_t axis, double halo, void* stream,
+                                      void* workspace, size_t workspace_bytes, int64_t max_local,
+                                      int64_t max_edges, const mpip_outputs* out, int64_t* part_sizes);
+
 /* Output integration (Methods "Global Output Integration"): dst[index[k]]
  * += src[k] for rows of 3 doubles (device pointers), e.g. a partition's
  * force rows (root and halo) into the full structure's forces.

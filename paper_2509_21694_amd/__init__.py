@@ -109,6 +109,12 @@ def _load():
     lib.mpip_md_workspace_size.restype = I32
     lib.mpip_md_run.argtypes = [V, P(SystemC), V, V, V, V, P(MdParamsC), I32, I32, V, V, SZ, I64, V, V]
     lib.mpip_md_run.restype = I32
+    lib.mpip_partitioned_workspace_size.argtypes = [V, P(SystemC), I32, I32, I32, I32, ctypes.c_double, I64, I64,
+                                                    P(SZ)]
+    lib.mpip_partitioned_workspace_size.restype = I32
+    lib.mpip_evaluate_partitioned.argtypes = [V, P(SystemC), I32, I32, I32, I32, ctypes.c_double, V, V, SZ, I64,
+                                              I64, P(OutputsC), P(I64)]
+    lib.mpip_evaluate_partitioned.restype = I32
     lib.mpip_last_error.argtypes = []
     lib.mpip_last_error.restype = ctypes.c_char_p
     return lib
@@ -121,7 +127,7 @@ EXPORTED = ["mpip_weights_count", "mpip_model_create", "mpip_model_destroy", "mp
             "mpip_neighbor_list", "mpip_coupling_tensor", "mpip_timing_enable", "mpip_timing_read",
             "mpip_slab_workspace_size", "mpip_slab_share", "mpip_accumulate_rows",
             "mpip_batch_workspace_size", "mpip_evaluate_batch", "mpip_md_workspace_size", "mpip_md_run",
-            "mpip_last_error"]
+            "mpip_partitioned_workspace_size", "mpip_evaluate_partitioned", "mpip_last_error"]
 
 
 def _check(st: int):
@@ -299,6 +305,61 @@ class Model:
         ne = ctypes.c_int64()
         _check(lib.mpip_workspace_status(ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(sp), ctypes.byref(ne)))
         return epot[:n_steps], ekin[:n_steps], forces
+
+    def evaluate_partitioned(self, positions, species, cell, pbc=(True, True, True), *, n_parts: int,
+                             axis: int = 0, halo: Optional[float] = None, K: Optional[int] = None,
+                             precision="fp32", atom_energy: bool = False, max_local: Optional[int] = None,
+                             max_edges: Optional[int] = None, stream=None):
+        """Whole structure in ``n_parts`` slab partitions along ``axis``,
+        evaluated one after the other on this GPU with one reused workspace
+        (mpip_evaluate_partitioned); ``halo`` defaults to K r_cut.  Returns a
+        dict of cuda tensors (energy [1], forces [N,3], virial [3,3],
+        atom_energy [N]) and ``parts``: numpy int64 [n_parts, 3] of (rows,
+        roots, directed edges) per share.  Retries once with larger share
+        capacities when a share outgrows the estimates."""
+        torch = self.torch
+        K = self.hp.n_layers if K is None else int(K)
+        N = int(positions.shape[0])
+        assert positions.dtype == torch.float64 and positions.is_cuda and positions.is_contiguous()
+        assert species.dtype == torch.int32 and species.is_cuda and species.is_contiguous()
+        if halo is None:
+            halo = K * self.hp.r_cut
+        c = np.asarray(cell, dtype=np.float64).reshape(3, 3)
+        Lax = float(c[axis, axis])
+        if max_local is None:
+            max_local = min(int(N * (1.0 / n_parts + 2.0 * halo / Lax) * 1.05) + 1024,
+                            N * (2 * (int(math.ceil(halo / Lax)) + 1) + 1))
+        if max_edges is None:
+            max_edges = estimate_edges(N, cell, self.hp.r_cut) * max_local // N + 1024
+        prec = PRECISIONS[precision]
+        o = {"energy": torch.empty(1, dtype=torch.float64, device=self.device),
+             "forces": torch.empty((N, 3), dtype=torch.float64, device=self.device),
+             "virial": torch.empty((3, 3), dtype=torch.float64, device=self.device),
+             "atom_energy": torch.empty(N, dtype=torch.float64, device=self.device) if atom_energy else None}
+        oc = OutputsC(o["energy"].data_ptr(), o["forces"].data_ptr(), o["virial"].data_ptr(),
+                      o["atom_energy"].data_ptr() if atom_energy else None)
+        sysc = _system(positions, species, cell, pbc, None)
+        sp = _stream_ptr(torch, self.device, stream)
+        parts = np.zeros((n_parts, 3), dtype=np.int64)
+        for attempt in range(2):
+            need = ctypes.c_size_t()
+            _check(lib.mpip_partitioned_workspace_size(self._h, ctypes.byref(sysc), prec, K, n_parts, axis,
+                                                       float(halo), max_local, max_edges, ctypes.byref(need)))
+            if self._ws is None or self._ws.numel() < need.value:
+                self._ws = None
+                self._ws = torch.empty(int(need.value), dtype=torch.uint8, device=self.device)
+            st = lib.mpip_evaluate_partitioned(self._h, ctypes.byref(sysc), prec, K, n_parts, axis, float(halo),
+                                               ctypes.c_void_p(sp), ctypes.c_void_p(self._ws.data_ptr()),
+                                               self._ws.numel(), max_local, max_edges, ctypes.byref(oc),
+                                               parts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+            if st == ECAPACITY and attempt == 0:
+                max_local = max(max_local, int(parts[:, 0].max() * 1.05) + 1024)
+                max_edges = max(max_edges, int(parts[:, 2].max() * 1.05) + 1024)
+                continue
+            _check(st)
+            o["parts"] = parts
+            return o
+        raise MpipError(ECAPACITY, "share capacity")
 
 
 class Batch:

@@ -1134,6 +1134,124 @@ mpip_status mpip_accumulate_rows(const double* src, const int32_t* index, int64_
   return MPIP_OK;
 }
 
+// ------------------------------------------------------- partitioned driver
+
+namespace {
+struct PartLayout {
+  size_t o_slab, o_pos, o_spec, o_idx, o_e, o_w, o_f, o_ae, o_eval, total;
+  size_t slab_bytes, eval_bytes;
+};
+
+PartLayout part_layout(const mpip_model* m, int64_t N, double L, double halo, int64_t max_local, int64_t max_edges,
+                       int K) {
+  PartLayout q;
+  size_t cur = 0;
+  q.slab_bytes = mpip_slab_workspace_size(N, L, halo);
+  q.o_slab = take(cur, q.slab_bytes);
+  q.o_pos = take(cur, sizeof(double) * 3 * max_local);
+  q.o_spec = take(cur, sizeof(int32_t) * max_local);
+  q.o_idx = take(cur, sizeof(int32_t) * max_local);
+  q.o_e = take(cur, sizeof(double));
+  q.o_w = take(cur, sizeof(double) * 9);
+  q.o_f = take(cur, sizeof(double) * 3 * max_local);
+  q.o_ae = take(cur, sizeof(double) * max_local);
+  q.eval_bytes = make_plan(max_local, max_edges, &m->hp, K).total;
+  q.o_eval = take(cur, q.eval_bytes);
+  q.total = cur + 256;
+  return q;
+}
+
+mpip_status check_partitioned(const mpip_model* m, const mpip_system* sys, int32_t K, int32_t n_parts, int32_t axis,
+                              double halo, int64_t max_local, int64_t max_edges) {
+  if (!m || !sys) return fail(MPIP_EINVAL, "null argument");
+  if (K < 1 || K > m->hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
+  if (n_parts < 1 || axis < 0 || axis > 2 || !(halo >= 0.0) || !std::isfinite(halo))
+    return fail(MPIP_EINVAL, "bad partition arguments");
+  if (sys->n_atoms < 1 || sys->n_owned != sys->n_atoms) return fail(MPIP_EINVAL, "every atom must be owned");
+  if (!sys->pbc[axis]) return fail(MPIP_EUNSUPPORTED, "the split axis must be periodic");
+  if (!(sys->cell[4 * axis] > 0.0)) return fail(MPIP_ECELL, "cell length along the axis must be positive");
+  if (max_local < 1 || max_local > (int64_t)1 << 30) return fail(MPIP_EINVAL, "max_local out of range");
+  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  return MPIP_OK;
+}
+}  // namespace
+
+mpip_status mpip_partitioned_workspace_size(const mpip_model* m, const mpip_system* sys, mpip_precision prec,
+                                            int32_t K, int32_t n_parts, int32_t axis, double halo,
+                                            int64_t max_local, int64_t max_edges, size_t* bytes) {
+  (void)prec;
+  mpip_status st = check_partitioned(m, sys, K, n_parts, axis, halo, max_local, max_edges);
+  if (st != MPIP_OK) return st;
+  if (!bytes) return fail(MPIP_EINVAL, "null argument");
+  *bytes = part_layout(m, sys->n_atoms, sys->cell[4 * axis], halo, max_local, max_edges, K).total;
+  return MPIP_OK;
+}
+
+mpip_status mpip_evaluate_partitioned(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K,
+                                      int32_t n_parts, int32_t axis, double halo, void* stream, void* ws,
+                                      size_t ws_bytes, int64_t max_local, int64_t max_edges,
+                                      const mpip_outputs* out, int64_t* part_sizes) {
+  mpip_status st = check_partitioned(m, sys, K, n_parts, axis, halo, max_local, max_edges);
+  if (st != MPIP_OK) return st;
+  if (!out || !out->energy || !out->forces || !out->virial) return fail(MPIP_EINVAL, "null output buffer");
+  if (!ws) return fail(MPIP_EINVAL, "null workspace");
+  const int64_t N = sys->n_atoms;
+  const PartLayout q = part_layout(m, N, sys->cell[4 * axis], halo, max_local, max_edges, K);
+  if (ws_bytes < q.total) return fail(MPIP_ECAPACITY, "workspace too small");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != m->device) HIPCHK(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  double* lpos = (double*)(w + q.o_pos);
+  int32_t* lspec = (int32_t*)(w + q.o_spec);
+  int32_t* lidx = (int32_t*)(w + q.o_idx);
+  double* le = (double*)(w + q.o_e);
+  double* lw = (double*)(w + q.o_w);
+  double* lf = (double*)(w + q.o_f);
+  double* lae = (double*)(w + q.o_ae);
+  launch_zero(out->energy, sizeof(double), s);
+  launch_zero(out->virial, sizeof(double) * 9, s);
+  launch_zero(out->forces, sizeof(double) * 3 * (size_t)N, s);
+  if (out->atom_energy) launch_zero(out->atom_energy, sizeof(double) * (size_t)N, s);
+  auto done = [&](mpip_status r) {
+    if (cur != m->device) hipSetDevice(cur);
+    return r;
+  };
+  for (int part = 0; part < n_parts; ++part) {
+    int64_t nl = 0, no = 0;
+    st = mpip_slab_share(sys->positions, sys->species, N, sys->cell, axis, n_parts, part, halo, s, w + q.o_slab,
+                         q.slab_bytes, max_local, lpos, lspec, lidx, &nl, &no);
+    if (part_sizes) { part_sizes[3 * part] = nl; part_sizes[3 * part + 1] = no; part_sizes[3 * part + 2] = 0; }
+    if (st != MPIP_OK) return done(st);
+    if (nl == 0) continue;
+    mpip_system ss;
+    ss.n_atoms = nl;
+    ss.n_owned = no;
+    ss.positions = lpos;
+    ss.species = lspec;
+    for (int k = 0; k < 9; ++k) ss.cell[k] = sys->cell[k];
+    for (int d = 0; d < 3; ++d) ss.pbc[d] = d == axis ? 0 : sys->pbc[d];
+    mpip_outputs so;
+    so.energy = le; so.forces = lf; so.virial = lw; so.atom_energy = out->atom_energy ? lae : nullptr;
+    st = mpip_evaluate(m, &ss, prec, K, s, w + q.o_eval, q.eval_bytes, max_edges, &so);
+    if (st != MPIP_OK) return done(st);
+    int64_t ne = 0;
+    st = mpip_workspace_status(w + q.o_eval, s, &ne);
+    if (part_sizes) part_sizes[3 * part + 2] = ne;
+    if (st != MPIP_OK) return done(st);
+    // output integration: partial forces of roots and halo images onto the
+    // atoms they copy, root energy and virial summed, root atom energies
+    accumulate_rows_launch(lf, lidx, nl, N, out->forces, s);
+    add_energy_virial_launch(le, lw, out->energy, out->virial, s);
+    if (out->atom_energy) scatter_scalars_launch(lae, lidx, no, N, out->atom_energy, s);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return done(fail(MPIP_EDEVICE, std::string("partitioned evaluation: ") + hipGetErrorString(e)));
+  return done(MPIP_OK);
+}
+
 // ------------------------------------------------------------------ batches
 
 static size_t batch_extra_offset(const Plan& p) { return (p.total + 255) & ~(size_t)255; }

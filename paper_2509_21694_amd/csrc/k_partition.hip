@@ -95,4 +95,31 @@ void accumulate_rows_launch(const double* src, const int32_t* index, int64_t n, 
   k_accumulate_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, index, n, n_dst, dst);
 }
 
+// E += e, W += w: one partition's root energy and virial into the totals
+__global__ void k_add_energy_virial(const double* __restrict__ e, const double* __restrict__ w, double* __restrict__ E,
+                                    double* __restrict__ W) {
+  const int k = threadIdx.x;
+  if (k == 0) E[0] += e[0];
+  if (k < 9) W[k] += w[k];
+}
+
+void add_energy_virial_launch(const double* e, const double* w, double* E, double* W, hipStream_t s) {
+  k_add_energy_virial<<<1, 64, 0, s>>>(e, w, E, W);
+}
+
+// dst[index[k]] = src[k] for the first n rows (root-atom energies)
+__global__ void k_scatter_scalars(const double* __restrict__ src, const int32_t* __restrict__ index, int64_t n,
+                                  int64_t n_dst, double* __restrict__ dst) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t o = index[k];
+  if (o >= 0 && o < n_dst) dst[o] = src[k];
+}
+
+void scatter_scalars_launch(const double* src, const int32_t* index, int64_t n, int64_t n_dst, double* dst,
+                            hipStream_t s) {
+  if (n <= 0) return;
+  k_scatter_scalars<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, index, n, n_dst, dst);
+}
+
 }  // namespace mpip

@@ -325,6 +325,9 @@ void slab_write_launch(const double* pos, const int32_t* spec, int64_t n, const 
                        int32_t* out_idx, hipStream_t s);
 void accumulate_rows_launch(const double* src, const int32_t* index, int64_t n, int64_t n_dst, double* dst,
                             hipStream_t s);
+void add_energy_virial_launch(const double* e, const double* w, double* E, double* W, hipStream_t s);
+void scatter_scalars_launch(const double* src, const int32_t* index, int64_t n, int64_t n_dst, double* dst,
+                            hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace mpip

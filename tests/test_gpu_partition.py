@@ -125,3 +125,81 @@ def test_share_of_8m_box(torch, M, K):
         assert abs(ae[k] - r.atom_energy[c]) <= 1e-3
         if check_force:
             assert np.abs(F[k] - r.forces[c]).max() <= max(5e-3, 5e-2 * np.abs(r.forces[c]).max())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("K", [2, 6])
+def test_partitioned_driver_downscale(torch, M, K, prec):
+    """mpip_evaluate_partitioned on the 20,000-atom downscale: the 8 slabs
+    built, evaluated (trimmed) and integrated on the device one after the
+    other, against the oracle's evaluation of the whole box."""
+    path = os.path.join(GOLDEN, f"slab20k_K{K}.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing (tests/golden/make_golden.py)")
+    g = np.load(path)
+    s = W.slab_downscale_full()
+    hp = W.HP_MPDP
+    model = M.Model(hp, W.make_weights(hp, W.WEIGHT_SEEDS["slab8m"]))
+    pos = torch.tensor(s.positions, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    print(f"[driver slab20k K={K} {prec}]", flush=True)
+    o = model.evaluate_partitioned(pos, sp, s.cell, s.pbc, n_parts=8, K=K, precision=prec, atom_energy=True)
+    parts = o["parts"]
+    for p in range(8):
+        lp, _, _, n_own, _ = oracle.slab_share(s.positions, s.species, s.cell, 8, p, K * RC)
+        assert parts[p, 0] == lp.shape[0] and parts[p, 1] == n_own
+    assert parts[:, 1].sum() == s.n_atoms
+    E = float(o["energy"].cpu()[0])
+    F = o["forces"].cpu().numpy()
+    Wv = o["virial"].cpu().numpy()
+    ae = o["atom_energy"].cpu().numpy()
+    dE = abs(E - float(g["energy"])) / s.n_atoms
+    dF = np.abs(F - g["forces"])
+    rms, frms = np.sqrt(np.mean(dF ** 2)), np.sqrt(np.mean(g["forces"] ** 2))
+    dW = np.abs(Wv - g["virial"]).max() / abs(np.linalg.det(s.cell))
+    dae = np.abs(ae - g["atom_energy"]).max()
+    print(f"[driver slab20k K={K} {prec}] H={parts[:, 0].sum() / s.n_atoms - 1:.3f} dE/N={dE:.2e} "
+          f"max|dF|={dF.max():.2e} rms={rms:.2e} |dW|/V={dW:.2e} max|dE_i|={dae:.2e}")
+    if prec == "fp32":
+        assert dE <= 1e-6 and dF.max() <= 1e-4 and dF.max() <= 1e-5 * np.abs(g["forces"]).max()
+        assert dW <= 1e-8 and dae <= 1e-6
+    else:
+        assert dE <= 1e-3 and rms <= 5e-3 and rms <= 2e-2 * frms and dW <= 1e-5 and dae <= 1e-3
+
+
+def test_partitioned_driver_8m(torch, M):
+    """The whole 8,000,000-atom box as 8 slabs (K = 2, BF16, halo 2 r_c):
+    net force and energy bookkeeping on all atoms, and the exact force of an
+    atom deep in a slab and of one on a slab face (its force is the sum of
+    partial forces from two shares) against the oracle on local clusters."""
+    K = 2
+    s = W.slab_full_system(200, 200, 200, 401, 402)
+    hp = W.HP_MPDP
+    blob = W.make_weights(hp, W.WEIGHT_SEEDS["slab8m"])
+    model = M.Model(hp, blob)
+    pos = torch.tensor(s.positions, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    print("[driver slab8m] 8 parts, K=2, bf16", flush=True)
+    o = model.evaluate_partitioned(pos, sp, s.cell, s.pbc, n_parts=8, K=K, precision="bf16", atom_energy=True)
+    parts = o["parts"]
+    assert parts[:, 1].sum() == s.n_atoms
+    F = o["forces"].cpu().numpy()
+    ae = o["atom_energy"].cpu().numpy()
+    E = float(o["energy"].cpu()[0])
+    print(f"[driver slab8m] rows per part {parts[:, 0].tolist()} H={parts[:, 0].sum() / s.n_atoms - 1:.3f} "
+          f"edges max {parts[:, 2].max()}", flush=True)
+    assert np.all(np.isfinite(F)) and np.all(np.isfinite(ae))
+    net = np.abs(F.sum(axis=0)).max()
+    assert net <= 1e-9 * np.abs(F).sum()
+    assert abs(E - ae.sum()) <= 1e-9 * np.abs(ae).sum()
+    Lx = s.cell[0, 0]
+    x = np.mod(s.positions[:, 0], Lx)
+    for x0, label in ((Lx / 16 + 3 * Lx / 8, "deep"), (Lx / 8, "face")):
+        a = int(np.argmin(np.abs(x - x0)))
+        lq, lsq, n_in, gi, c = oracle.local_cluster(s.positions, s.species, s.cell, a, 2 * K * RC, K * RC)
+        r = oracle.evaluate(lq, lsq, np.eye(3), [False] * 3, blob, hp, K=K, n_owned=n_in)
+        dF = np.abs(F[a] - r.forces[c]).max()
+        print(f"[driver slab8m] {label} atom {a} (x={x[a]:.2f}): dE_i={abs(ae[a] - r.atom_energy[c]):.2e} "
+              f"|dF|={dF:.2e} |F|={np.abs(r.forces[c]).max():.2e}")
+        assert abs(ae[a] - r.atom_energy[c]) <= 1e-3
+        assert dF <= max(5e-3, 5e-2 * np.abs(r.forces[c]).max())
