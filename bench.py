@@ -316,7 +316,29 @@ def main():
                 "steps": args.partitioned_steps, "dtype": head, "n_parts": n_parts,
                 "halo_growth_H": round(float(parts[:, 0].sum()) / s8.n_atoms - 1.0, 4),
                 "share_rows_max": int(parts[:, 0].max()), "share_edges_max": int(parts[:, 2].max())}
-        del model8, p8, sp8, o8
+        # the same with the K-hop graph halo (whole-structure list once, hops per part)
+        og = model8.evaluate_partitioned(p8, sp8, s8.cell, s8.pbc, n_parts=n_parts, K=Kp, precision=head,
+                                         graph_halo=True, max_local=ml, max_edges=me)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.partitioned_steps):
+            og = model8.evaluate_partitioned(p8, sp8, s8.cell, s8.pbc, n_parts=n_parts, K=Kp, precision=head,
+                                             graph_halo=True, max_local=ml, max_edges=me)
+        torch.cuda.synchronize()
+        g_ms = (time.perf_counter() - t0) / args.partitioned_steps * 1e3
+        log(f"partitioned, graph halo ({head}): {g_ms:.3f} ms per 8M-atom evaluation")
+        part["graph_halo"] = {"value": round(s8.n_atoms / (g_ms * 1e-3), 1), "ms_per_step": round(g_ms, 3),
+                              "halo_growth_H": round(float(og["parts"][:, 0].sum()) / s8.n_atoms - 1.0, 4)}
+        # halo growth of one share against depth: geometric K r_cut vs K hops
+        hg = {}
+        for Kh in (2, 6):
+            gp, _, _, no = M.slab_share(p8, sp8, s8.cell, n_parts, 0, Kh * hp8.r_cut)
+            nl_geo = int(gp.shape[0])
+            del gp
+            nl_bfs = int(M.bfs_share(p8, sp8, s8.cell, n_parts, 0, Kh, hp8.r_cut)[0].shape[0])
+            hg[f"K{Kh}"] = {"geometric": round((nl_geo - no) / no, 4), "graph": round((nl_bfs - no) / no, 4)}
+        part["halo_growth_vs_K"] = hg
+        del model8, p8, sp8, o8, og
     line = {"metric": METRIC, "value": results[head]["value"], "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": results[head]["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,

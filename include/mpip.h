@@ -195,11 +195,37 @@ mpip_status mpip_slab_share(const double* positions, const int32_t* species, int
                             int64_t capacity, double* out_positions, int32_t* out_species,
                             int32_t* out_index, int64_t* n_local, int64_t* n_owned);
 
+/* One partition with a graph halo (Methods "Graph Partitioning", stage 2:
+ * each subgraph grown by a breadth-first expansion of depth K so that every
+ * root atom keeps its K-hop neighbourhood).  The roots are the atoms of slab
+ * `part` of n_parts along `axis` (the stage-1 rule of mpip_slab_share); the
+ * halo holds every atom within K hops of a root in the neighbour graph of
+ * the whole structure at cutoff r_cut, as the image that lies within K r_cut
+ * of the slab.  Equivalently: the share mpip_slab_share builds with halo
+ * K r_cut, without the images of atoms more than K hops from every root
+ * (same row order: roots by index, then halo images by image shift and
+ * index).  sys: the whole structure (orthorhombic, periodic along `axis`,
+ * n_owned ignored); the slab plus 2 K r_cut must not exceed the cell length
+ * along `axis` (one image per atom; else EUNSUPPORTED).  max_edges: capacity
+ * of the whole structure's list (ECAPACITY with *n_edges = the count when
+ * exceeded); capacity: rows of the outputs (ECAPACITY with *n_local set when
+ * exceeded).  Workspace: mpip_bfs_share_workspace_size bytes (device).
+ * Synchronous.  The halo growth factor of the share is
+ * (*n_local - *n_owned) / *n_owned. */
+size_t mpip_bfs_share_workspace_size(int64_t n_atoms, double axis_length, int32_t K, double r_cut,
+                                     int64_t max_edges);
+mpip_status mpip_bfs_share(const mpip_system* sys, double r_cut, int32_t axis, int32_t n_parts, int32_t part,
+                           int32_t K, void* stream, void* workspace, size_t workspace_bytes, int64_t max_edges,
+                           int64_t capacity, double* out_positions, int32_t* out_species, int32_t* out_index,
+                           int64_t* n_local, int64_t* n_owned, int64_t* n_edges);
+
 /* Sequential evaluation of a whole structure in n_parts partitions on one GPU
  * (the one-GPU mode of the paper's pipeline: Methods "Graph Partitioning"
  * and "Global Output Integration").  For part = 0 .. n_parts-1: the slab and
- * its halo of depth `halo` along `axis` are built on the device as by
- * mpip_slab_share, evaluated as a share (its root atoms owned, pbc[axis] = 0,
+ * its halo along `axis` are built on the device, as by mpip_slab_share with
+ * depth `halo` (graph_edges < 0) or as by mpip_bfs_share with K hops
+ * (graph_edges >= 0: the capacity of the whole structure's neighbour list,
+ * built once for all parts; `halo` is then unused), evaluated as a share (its root atoms owned, pbc[axis] = 0,
  * receptive-field trimming as in mpip_evaluate), and integrated into `out`:
  * energy and virial summed over parts, every share row's partial force added
  * to the atom it copies, root-atom energies stored (atom_energy optional).
@@ -214,16 +240,18 @@ mpip_status mpip_slab_share(const double* positions, const int32_t* species, int
  * roots, directed edges): halo growth H = rows / roots - 1.
  * Synchronous (each share's size and status are read back).  Errors: those of
  * mpip_slab_share (ECAPACITY: a share has more than max_local rows, its size
- * in part_sizes) and of mpip_evaluate / mpip_workspace_status (ECAPACITY: more
- * than max_edges edges, the count in part_sizes); the outputs are then
+ * in part_sizes), of mpip_bfs_share (ECAPACITY: the whole structure's list
+ * has more than graph_edges edges, the count in part_sizes[2]) and of
+ * mpip_evaluate / mpip_workspace_status (ECAPACITY: a share has more than
+ * max_edges edges, the count in part_sizes); the outputs are then
  * incomplete. */
 mpip_status mpip_partitioned_workspace_size(const mpip_model* model, const mpip_system* sys,
                                             mpip_precision prec, int32_t K, int32_t n_parts, int32_t axis,
-                                            double halo, int64_t max_local, int64_t max_edges,
-                                            size_t* bytes);
+                                            double halo, int64_t graph_edges, int64_t max_local,
+                                            int64_t max_edges, size_t* bytes);
 mpip_status mpip_evaluate_partitioned(mpip_model* model, const mpip_system* sys, mpip_precision prec,
-                                      int32_t K, int32_t n_parts, int32_t axis, double halo, void* stream,
-                                      void* workspace, size_t workspace_bytes, int64_t max_local,
+                                      int32_t K, int32_t n_parts, int32_t axis, double halo, int64_t graph_edges,
+                                      void* stream, void* workspace, size_t workspace_bytes, int64_t max_local,
                                       int64_t max_edges, const mpip_outputs* out, int64_t* part_sizes);
 
 /* Output integration (Methods "Global Output Integration"): dst[index[k]]

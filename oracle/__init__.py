@@ -28,4 +28,4 @@ from .sh import real_sh, real_sh_grad                          # noqa: F401
 from .gaunt import gaunt_tensor, coupling_tensor, layer_paths  # noqa: F401
 from .weights import parse_weights                             # noqa: F401
 from .model import evaluate, Result                            # noqa: F401
-from .partition import slab_share, evaluate_partitioned, local_cluster  # noqa: F401
+from .partition import slab_share, bfs_share, hop_distance, evaluate_partitioned, local_cluster  # noqa: F401

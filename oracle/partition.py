@@ -4,11 +4,12 @@ Methods, "Graph Partitioning", stage 1 (spatial grid): the scaled position
 of each atom along the split axis is binned into P equal bins; the atoms of
 bin p are the root ("owned") atoms of partition p.  Stage 2 extends each
 root set so that every root atom keeps the K-hop neighbourhood it has in the
-full structure.  The oracle uses a geometric halo: every periodic image of
-every atom whose coordinate along the split axis lies within ``halo`` of the
-slab (and outside it) is added as a ghost at its unwrapped position.  A
+full structure.  ``slab_share`` uses a geometric halo: every periodic image
+of every atom whose coordinate along the split axis lies within ``halo`` of
+the slab (and outside it) is added as a ghost at its unwrapped position.  A
 halo of depth K*r_cut contains the K-hop set (each hop is shorter than
-r_cut), so root energies are exact.
+r_cut), so root energies are exact.  ``bfs_share`` keeps exactly the K-hop
+set (the paper's breadth-first expansion).
 
 Methods, "Global Output Integration": the energy is the sum of root-atom
 energies over partitions; for gradient (conservative) models the force is
@@ -22,6 +23,7 @@ from __future__ import annotations
 import numpy as np
 
 from .model import evaluate
+from .neighbors import neighbor_list
 
 
 def slab_share(positions, species, cell, n_parts: int, part: int, halo: float, axis: int = 0):
@@ -59,6 +61,43 @@ def slab_share(positions, species, cell, n_parts: int, part: int, halo: float, a
     pbc = np.array([True, True, True])
     pbc[axis] = False
     return lp, np.asarray(species)[gi].astype(np.int32), pbc, owned.size, gi
+
+
+def hop_distance(positions, cell, pbc, roots, r_cut: float, K: int):
+    """Graph distance from the root set in the neighbour graph at r_cut
+    (number of edges on a shortest path), capped at K + 1: level h + 1 is the
+    set of neighbours of level h not reached before (breadth-first search,
+    Methods "Graph Partitioning", stage 2)."""
+    pos = np.asarray(positions, dtype=np.float64)
+    i, j, _ = neighbor_list(pos, cell, pbc, r_cut)
+    hop = np.full(pos.shape[0], K + 1, dtype=np.int64)
+    hop[np.asarray(roots, dtype=np.int64)] = 0
+    for h in range(K):
+        nxt = j[hop[i] == h]
+        hop[nxt] = np.minimum(hop[nxt], h + 1)
+    return hop
+
+
+def bfs_share(positions, species, cell, n_parts: int, part: int, K: int, r_cut: float, axis: int = 0,
+              pbc=(True, True, True)):
+    """Local system of one slab partition with a graph halo (Methods "Graph
+    Partitioning": stage 1 grid, stage 2 expansion of each subgraph by K
+    hops).  The roots are those of ``slab_share``; the halo is every atom
+    within K hops of a root in the neighbour graph of the whole structure,
+    placed at its image within K*r_cut of the slab (each hop is shorter
+    than r_cut), which is unique when the slab plus 2*K*r_cut fits in the
+    cell.  Same row order as ``slab_share`` with halo K*r_cut, whose rows of
+    atoms farther than K hops are dropped.  Returns (local_positions,
+    local_species, pbc, n_owned, global_index)."""
+    cell = np.asarray(cell, dtype=np.float64)
+    Lx = cell[axis, axis]
+    if Lx / n_parts + 2.0 * K * r_cut > Lx:
+        raise ValueError("slab plus halo wider than the cell")
+    lp, ls, lpbc, n_own, gi = slab_share(positions, species, cell, n_parts, part, K * r_cut, axis)
+    hop = hop_distance(positions, cell, pbc, gi[:n_own], r_cut, K)
+    keep = np.ones(lp.shape[0], dtype=bool)
+    keep[n_own:] = hop[gi[n_own:]] <= K
+    return lp[keep], ls[keep], lpbc, n_own, gi[keep]
 
 
 def evaluate_partitioned(positions, species, cell, blob, hp, K: int, n_parts: int,

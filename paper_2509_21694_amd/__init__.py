@@ -110,11 +110,16 @@ def _load():
     lib.mpip_md_run.argtypes = [V, P(SystemC), V, V, V, V, P(MdParamsC), I32, I32, V, V, SZ, I64, V, V]
     lib.mpip_md_run.restype = I32
     lib.mpip_partitioned_workspace_size.argtypes = [V, P(SystemC), I32, I32, I32, I32, ctypes.c_double, I64, I64,
-                                                    P(SZ)]
+                                                    I64, P(SZ)]
     lib.mpip_partitioned_workspace_size.restype = I32
-    lib.mpip_evaluate_partitioned.argtypes = [V, P(SystemC), I32, I32, I32, I32, ctypes.c_double, V, V, SZ, I64,
-                                              I64, P(OutputsC), P(I64)]
+    lib.mpip_evaluate_partitioned.argtypes = [V, P(SystemC), I32, I32, I32, I32, ctypes.c_double, I64, V, V, SZ,
+                                              I64, I64, P(OutputsC), P(I64)]
     lib.mpip_evaluate_partitioned.restype = I32
+    lib.mpip_bfs_share_workspace_size.argtypes = [I64, ctypes.c_double, I32, ctypes.c_double, I64]
+    lib.mpip_bfs_share_workspace_size.restype = SZ
+    lib.mpip_bfs_share.argtypes = [P(SystemC), ctypes.c_double, I32, I32, I32, I32, V, V, SZ, I64, I64, V, V, V,
+                                   P(I64), P(I64), P(I64)]
+    lib.mpip_bfs_share.restype = I32
     lib.mpip_last_error.argtypes = []
     lib.mpip_last_error.restype = ctypes.c_char_p
     return lib
@@ -127,7 +132,8 @@ EXPORTED = ["mpip_weights_count", "mpip_model_create", "mpip_model_destroy", "mp
             "mpip_neighbor_list", "mpip_coupling_tensor", "mpip_timing_enable", "mpip_timing_read",
             "mpip_slab_workspace_size", "mpip_slab_share", "mpip_accumulate_rows",
             "mpip_batch_workspace_size", "mpip_evaluate_batch", "mpip_md_workspace_size", "mpip_md_run",
-            "mpip_partitioned_workspace_size", "mpip_evaluate_partitioned", "mpip_last_error"]
+            "mpip_partitioned_workspace_size", "mpip_evaluate_partitioned", "mpip_bfs_share_workspace_size",
+            "mpip_bfs_share", "mpip_last_error"]
 
 
 def _check(st: int):
@@ -307,12 +313,14 @@ class Model:
         return epot[:n_steps], ekin[:n_steps], forces
 
     def evaluate_partitioned(self, positions, species, cell, pbc=(True, True, True), *, n_parts: int,
-                             axis: int = 0, halo: Optional[float] = None, K: Optional[int] = None,
-                             precision="fp32", atom_energy: bool = False, max_local: Optional[int] = None,
-                             max_edges: Optional[int] = None, stream=None):
+                             axis: int = 0, halo: Optional[float] = None, graph_halo: bool = False,
+                             K: Optional[int] = None, precision="fp32", atom_energy: bool = False,
+                             max_local: Optional[int] = None, max_edges: Optional[int] = None, stream=None):
         """Whole structure in ``n_parts`` slab partitions along ``axis``,
         evaluated one after the other on this GPU with one reused workspace
-        (mpip_evaluate_partitioned); ``halo`` defaults to K r_cut.  Returns a
+        (mpip_evaluate_partitioned); the halo is geometric with depth
+        ``halo`` (default K r_cut), or the K-hop graph halo when
+        ``graph_halo`` is set.  Returns a
         dict of cuda tensors (energy [1], forces [N,3], virial [3,3],
         atom_energy [N]) and ``parts``: numpy int64 [n_parts, 3] of (rows,
         roots, directed edges) per share.  Retries once with larger share
@@ -341,18 +349,23 @@ class Model:
         sysc = _system(positions, species, cell, pbc, None)
         sp = _stream_ptr(torch, self.device, stream)
         parts = np.zeros((n_parts, 3), dtype=np.int64)
+        graph_edges = estimate_edges(N, cell, self.hp.r_cut) if graph_halo else -1
         for attempt in range(2):
             need = ctypes.c_size_t()
             _check(lib.mpip_partitioned_workspace_size(self._h, ctypes.byref(sysc), prec, K, n_parts, axis,
-                                                       float(halo), max_local, max_edges, ctypes.byref(need)))
+                                                       float(halo), graph_edges, max_local, max_edges,
+                                                       ctypes.byref(need)))
             if self._ws is None or self._ws.numel() < need.value:
                 self._ws = None
                 self._ws = torch.empty(int(need.value), dtype=torch.uint8, device=self.device)
             st = lib.mpip_evaluate_partitioned(self._h, ctypes.byref(sysc), prec, K, n_parts, axis, float(halo),
-                                               ctypes.c_void_p(sp), ctypes.c_void_p(self._ws.data_ptr()),
+                                               graph_edges, ctypes.c_void_p(sp), ctypes.c_void_p(self._ws.data_ptr()),
                                                self._ws.numel(), max_local, max_edges, ctypes.byref(oc),
                                                parts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
             if st == ECAPACITY and attempt == 0:
+                if graph_halo and parts[:, 0].sum() == 0:     # the whole structure's list overflowed
+                    graph_edges = max(graph_edges, int(parts[0, 2] * 1.05) + 1024)
+                    continue
                 max_local = max(max_local, int(parts[:, 0].max() * 1.05) + 1024)
                 max_edges = max(max_edges, int(parts[:, 2].max() * 1.05) + 1024)
                 continue
@@ -494,6 +507,45 @@ def slab_share(positions, species, cell, n_parts: int, part: int, halo: float, a
                                  ctypes.byref(nl), ctypes.byref(no))
         if st == ECAPACITY and attempt == 0 and nl.value > capacity:
             capacity = int(nl.value)
+            continue
+        _check(st)
+        n = int(nl.value)
+        return op[:n], osp[:n], oix[:n], int(no.value)
+    raise MpipError(ECAPACITY, "share capacity")
+
+
+def bfs_share(positions, species, cell, n_parts: int, part: int, K: int, r_cut: float, axis: int = 0,
+              pbc=(True, True, True), capacity: Optional[int] = None, max_edges: Optional[int] = None,
+              stream=None):
+    """One slab partition with a graph halo (atoms within K hops of a root),
+    built on the GPU.  Returns (positions [n,3] f64, species [n] i32, input
+    index [n] i32, n_owned) as cuda tensors; root atoms first.  Evaluate it
+    with pbc[axis] = False."""
+    import torch
+    dev = positions.device
+    N = int(positions.shape[0])
+    c = np.asarray(cell, dtype=np.float64).reshape(3, 3)
+    Lax = float(c[axis, axis])
+    if capacity is None:
+        capacity = int(N / n_parts + 2 * N * K * r_cut / Lax) + 1024
+    if max_edges is None:
+        max_edges = estimate_edges(N, cell, r_cut)
+    sysc = _system(positions, species, cell, pbc, None)
+    for attempt in range(2):
+        nbytes = int(lib.mpip_bfs_share_workspace_size(N, Lax, int(K), float(r_cut), max_edges))
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        op = torch.empty((capacity, 3), dtype=torch.float64, device=dev)
+        osp = torch.empty(capacity, dtype=torch.int32, device=dev)
+        oix = torch.empty(capacity, dtype=torch.int32, device=dev)
+        nl, no, ne = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        st = lib.mpip_bfs_share(ctypes.byref(sysc), float(r_cut), axis, n_parts, part, int(K),
+                                ctypes.c_void_p(_stream_ptr(torch, dev, stream)), ctypes.c_void_p(ws.data_ptr()),
+                                nbytes, max_edges, capacity, ctypes.c_void_p(op.data_ptr()),
+                                ctypes.c_void_p(osp.data_ptr()), ctypes.c_void_p(oix.data_ptr()),
+                                ctypes.byref(nl), ctypes.byref(no), ctypes.byref(ne))
+        if st == ECAPACITY and attempt == 0:
+            capacity = max(capacity, int(nl.value))
+            max_edges = max(max_edges, int(ne.value * 1.05) + 1024)
             continue
         _check(st)
         n = int(nl.value)

@@ -1081,10 +1081,13 @@ size_t mpip_slab_workspace_size(int64_t n, double L, double halo) {
   return cur + 256;
 }
 
-mpip_status mpip_slab_share(const double* pos, const int32_t* spec, int64_t n, const double* cell, int32_t axis,
-                            int32_t n_parts, int32_t part, double halo, void* stream, void* ws, size_t ws_bytes,
-                            int64_t capacity, double* out_pos, int32_t* out_spec, int32_t* out_idx,
-                            int64_t* n_local, int64_t* n_owned) {
+// the share of slab `part`; hop (input order, device) != null keeps only the
+// halo images of atoms within max_hop hops of a root
+static mpip_status slab_share_impl(const double* pos, const int32_t* spec, int64_t n, const double* cell, int32_t axis,
+                                   int32_t n_parts, int32_t part, double halo, void* stream, void* ws,
+                                   size_t ws_bytes, int64_t capacity, double* out_pos, int32_t* out_spec,
+                                   int32_t* out_idx, int64_t* n_local, int64_t* n_owned, const int32_t* hop,
+                                   int max_hop) {
   if (!pos || !spec || !cell || !ws || !n_local || !n_owned) return fail(MPIP_EINVAL, "null argument");
   if (n < 1 || axis < 0 || axis > 2 || n_parts < 1 || part < 0 || part >= n_parts || !(halo >= 0.0))
     return fail(MPIP_EINVAL, "bad partition arguments");
@@ -1098,6 +1101,8 @@ mpip_status mpip_slab_share(const double* pos, const int32_t* spec, int64_t n, c
   SlabArgs sa;
   sa.axis = axis; sa.P = n_parts; sa.part = part; sa.nimg = slab_nimg(L, halo); sa.L = L; sa.halo = halo;
   sa.capacity = capacity;
+  sa.hop = hop;
+  sa.max_hop = max_hop;
   const int ncat = 2 * sa.nimg + 2;
   size_t cur = 0;
   char* w = (char*)ws;
@@ -1125,6 +1130,103 @@ mpip_status mpip_slab_share(const double* pos, const int32_t* spec, int64_t n, c
   return MPIP_OK;
 }
 
+mpip_status mpip_slab_share(const double* pos, const int32_t* spec, int64_t n, const double* cell, int32_t axis,
+                            int32_t n_parts, int32_t part, double halo, void* stream, void* ws, size_t ws_bytes,
+                            int64_t capacity, double* out_pos, int32_t* out_spec, int32_t* out_idx,
+                            int64_t* n_local, int64_t* n_owned) {
+  return slab_share_impl(pos, spec, n, cell, axis, n_parts, part, halo, stream, ws, ws_bytes, capacity, out_pos,
+                         out_spec, out_idx, n_local, n_owned, nullptr, 0);
+}
+
+// graph (K-hop) halo: the full structure's list at r_cut, K breadth-first
+// levels from the slab's atoms, then the geometric share of depth K r_cut
+// restricted to atoms within K hops
+namespace {
+struct BfsLayout {
+  Plan nbr;
+  size_t o_nbr, o_slab, o_hop, o_hin, total, slab_bytes;
+};
+BfsLayout bfs_layout(int64_t n, double L, int K, double r_cut, int64_t max_edges) {
+  BfsLayout q;
+  size_t cur = 0;
+  q.nbr = make_plan(n, max_edges, nullptr, 0);
+  q.o_nbr = take(cur, q.nbr.total);
+  q.slab_bytes = mpip_slab_workspace_size(n, L, K * r_cut);
+  q.o_slab = take(cur, q.slab_bytes);
+  q.o_hop = take(cur, sizeof(int32_t) * n);
+  q.o_hin = take(cur, sizeof(int32_t) * n);
+  q.total = cur + 256;
+  return q;
+}
+}  // namespace
+
+size_t mpip_bfs_share_workspace_size(int64_t n_atoms, double axis_length, int32_t K, double r_cut,
+                                     int64_t max_edges) {
+  if (n_atoms < 1 || !(axis_length > 0.0) || K < 1 || !(r_cut > 0.0) || max_edges < 0) return 0;
+  return bfs_layout(n_atoms, axis_length, K, r_cut, max_edges).total;
+}
+
+namespace {
+mpip_status check_bfs(const mpip_system* sys, CellInfo* ci, double r_cut, int32_t axis, int32_t n_parts, int32_t K,
+                      int64_t max_edges) {
+  mpip_status st = check_system(sys, ci, r_cut, 1 << 30);
+  if (st != MPIP_OK) return st;
+  if (axis < 0 || axis > 2 || n_parts < 1 || K < 1 || !(r_cut > 0.0)) return fail(MPIP_EINVAL, "bad partition arguments");
+  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  if (!sys->pbc[axis]) return fail(MPIP_EUNSUPPORTED, "the split axis must be periodic");
+  const double L = sys->cell[4 * axis];
+  // one image per atom: the slab and both halo layers must fit in the box
+  if (L / n_parts + 2.0 * K * r_cut > L) return fail(MPIP_EUNSUPPORTED, "slab plus halo wider than the cell");
+  return MPIP_OK;
+}
+
+// the whole structure's list at r_cut (once for every part); *n_edges = its size
+mpip_status bfs_build(const mpip_system* sys, const CellInfo& ci, const BfsLayout& q, char* w, int64_t max_edges,
+                      hipStream_t s, int64_t* n_edges) {
+  NbrBuffers b = nbr_buffers(w + q.o_nbr, q.nbr);
+  launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
+  build_neighbors(b, *sys, ci, max_edges, s);
+  HIPCHK(hipGetLastError());
+  int64_t ne = 0;
+  mpip_status st = mpip_workspace_status(w + q.o_nbr, s, &ne);
+  if (n_edges) *n_edges = ne;
+  return st;
+}
+
+// hops from the roots of slab `part` over the built list, then the share
+mpip_status bfs_part(const mpip_system* sys, double r_cut, const BfsLayout& q, char* w, int32_t axis, int32_t n_parts,
+                     int32_t part, int32_t K, int64_t max_edges, hipStream_t s, int64_t capacity, double* out_pos,
+                     int32_t* out_spec, int32_t* out_idx, int64_t* n_local, int64_t* n_owned) {
+  NbrBuffers b = nbr_buffers(w + q.o_nbr, q.nbr);
+  SlabArgs sa;
+  sa.axis = axis; sa.P = n_parts; sa.part = part; sa.L = sys->cell[4 * axis]; sa.nimg = 0; sa.halo = 0.0;
+  sa.capacity = 0;
+  int32_t* hop_in = (int32_t*)(w + q.o_hin);
+  bfs_hops_launch(b, sys->n_atoms, sa, K, max_edges, (int32_t*)(w + q.o_hop), hop_in, s);
+  HIPCHK(hipGetLastError());
+  return slab_share_impl(sys->positions, sys->species, sys->n_atoms, sys->cell, axis, n_parts, part, K * r_cut, s,
+                         w + q.o_slab, q.slab_bytes, capacity, out_pos, out_spec, out_idx, n_local, n_owned, hop_in, K);
+}
+}  // namespace
+
+mpip_status mpip_bfs_share(const mpip_system* sys, double r_cut, int32_t axis, int32_t n_parts, int32_t part,
+                           int32_t K, void* stream, void* ws, size_t ws_bytes, int64_t max_edges, int64_t capacity,
+                           double* out_pos, int32_t* out_spec, int32_t* out_idx, int64_t* n_local,
+                           int64_t* n_owned, int64_t* n_edges) {
+  CellInfo ci;
+  mpip_status st = check_bfs(sys, &ci, r_cut, axis, n_parts, K, max_edges);
+  if (st != MPIP_OK) return st;
+  if (!ws || !n_local || !n_owned) return fail(MPIP_EINVAL, "null argument");
+  if (part < 0 || part >= n_parts) return fail(MPIP_EINVAL, "bad partition arguments");
+  const BfsLayout q = bfs_layout(sys->n_atoms, sys->cell[4 * axis], K, r_cut, max_edges);
+  if (ws_bytes < q.total) return fail(MPIP_ECAPACITY, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  st = bfs_build(sys, ci, q, (char*)ws, max_edges, s, n_edges);
+  if (st != MPIP_OK) return st;
+  return bfs_part(sys, r_cut, q, (char*)ws, axis, n_parts, part, K, max_edges, s, capacity, out_pos, out_spec,
+                  out_idx, n_local, n_owned);
+}
+
 mpip_status mpip_accumulate_rows(const double* src, const int32_t* index, int64_t n_rows, int64_t n_dst,
                                  double* dst, void* stream) {
   if (n_rows < 0 || n_dst < 0) return fail(MPIP_EINVAL, "negative size");
@@ -1140,13 +1242,19 @@ namespace {
 struct PartLayout {
   size_t o_slab, o_pos, o_spec, o_idx, o_e, o_w, o_f, o_ae, o_eval, total;
   size_t slab_bytes, eval_bytes;
+  BfsLayout bfs;   // graph halo: the whole structure's list and hops (in the o_slab region)
 };
 
 PartLayout part_layout(const mpip_model* m, int64_t N, double L, double halo, int64_t max_local, int64_t max_edges,
-                       int K) {
+                       int K, int64_t full_edges) {
   PartLayout q;
   size_t cur = 0;
-  q.slab_bytes = mpip_slab_workspace_size(N, L, halo);
+  if (full_edges >= 0) {
+    q.bfs = bfs_layout(N, L, K, m->hp.r_cut, full_edges);
+    q.slab_bytes = q.bfs.total;
+  } else {
+    q.slab_bytes = mpip_slab_workspace_size(N, L, halo);
+  }
   q.o_slab = take(cur, q.slab_bytes);
   q.o_pos = take(cur, sizeof(double) * 3 * max_local);
   q.o_spec = take(cur, sizeof(int32_t) * max_local);
@@ -1178,25 +1286,32 @@ mpip_status check_partitioned(const mpip_model* m, const mpip_system* sys, int32
 
 mpip_status mpip_partitioned_workspace_size(const mpip_model* m, const mpip_system* sys, mpip_precision prec,
                                             int32_t K, int32_t n_parts, int32_t axis, double halo,
-                                            int64_t max_local, int64_t max_edges, size_t* bytes) {
+                                            int64_t graph_edges, int64_t max_local, int64_t max_edges,
+                                            size_t* bytes) {
   (void)prec;
   mpip_status st = check_partitioned(m, sys, K, n_parts, axis, halo, max_local, max_edges);
   if (st != MPIP_OK) return st;
   if (!bytes) return fail(MPIP_EINVAL, "null argument");
-  *bytes = part_layout(m, sys->n_atoms, sys->cell[4 * axis], halo, max_local, max_edges, K).total;
+  *bytes = part_layout(m, sys->n_atoms, sys->cell[4 * axis], halo, max_local, max_edges, K, graph_edges).total;
   return MPIP_OK;
 }
 
 mpip_status mpip_evaluate_partitioned(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K,
-                                      int32_t n_parts, int32_t axis, double halo, void* stream, void* ws,
-                                      size_t ws_bytes, int64_t max_local, int64_t max_edges,
+                                      int32_t n_parts, int32_t axis, double halo, int64_t graph_edges, void* stream,
+                                      void* ws, size_t ws_bytes, int64_t max_local, int64_t max_edges,
                                       const mpip_outputs* out, int64_t* part_sizes) {
   mpip_status st = check_partitioned(m, sys, K, n_parts, axis, halo, max_local, max_edges);
   if (st != MPIP_OK) return st;
   if (!out || !out->energy || !out->forces || !out->virial) return fail(MPIP_EINVAL, "null output buffer");
   if (!ws) return fail(MPIP_EINVAL, "null workspace");
   const int64_t N = sys->n_atoms;
-  const PartLayout q = part_layout(m, N, sys->cell[4 * axis], halo, max_local, max_edges, K);
+  const bool graph = graph_edges >= 0;
+  CellInfo cib;
+  if (graph) {
+    st = check_bfs(sys, &cib, m->hp.r_cut, axis, n_parts, K, graph_edges);
+    if (st != MPIP_OK) return st;
+  }
+  const PartLayout q = part_layout(m, N, sys->cell[4 * axis], halo, max_local, max_edges, K, graph_edges);
   if (ws_bytes < q.total) return fail(MPIP_ECAPACITY, "workspace too small");
   int cur = 0;
   HIPCHK(hipGetDevice(&cur));
@@ -1218,10 +1333,23 @@ mpip_status mpip_evaluate_partitioned(mpip_model* m, const mpip_system* sys, mpi
     if (cur != m->device) hipSetDevice(cur);
     return r;
   };
+  if (graph) {
+    // graph halo: the whole structure's list once, hops per part
+    int64_t ne = 0;
+    st = bfs_build(sys, cib, q.bfs, w + q.o_slab, graph_edges, s, &ne);
+    if (st != MPIP_OK) {
+      if (part_sizes) part_sizes[2] = ne;
+      return done(st);
+    }
+  }
   for (int part = 0; part < n_parts; ++part) {
     int64_t nl = 0, no = 0;
-    st = mpip_slab_share(sys->positions, sys->species, N, sys->cell, axis, n_parts, part, halo, s, w + q.o_slab,
-                         q.slab_bytes, max_local, lpos, lspec, lidx, &nl, &no);
+    if (graph)
+      st = bfs_part(sys, m->hp.r_cut, q.bfs, w + q.o_slab, axis, n_parts, part, K, graph_edges, s, max_local, lpos,
+                    lspec, lidx, &nl, &no);
+    else
+      st = mpip_slab_share(sys->positions, sys->species, N, sys->cell, axis, n_parts, part, halo, s, w + q.o_slab,
+                           q.slab_bytes, max_local, lpos, lspec, lidx, &nl, &no);
     if (part_sizes) { part_sizes[3 * part] = nl; part_sizes[3 * part + 1] = no; part_sizes[3 * part + 2] = 0; }
     if (st != MPIP_OK) return done(st);
     if (nl == 0) continue;

@@ -40,6 +40,7 @@ __global__ void k_slab_flags(const double* __restrict__ pos, int64_t n, SlabArgs
     const double xs = __dadd_rn(x, __dmul_rn((double)s, sa.L));
     bool in = ((xs >= __dsub_rn(lo, sa.halo)) && (xs < lo)) || ((xs >= hi) && (xs < __dadd_rn(hi, sa.halo)));
     if (s == 0 && b == sa.part) in = false;
+    if (sa.hop && sa.hop[a] > sa.max_hop) in = false;
     flags[(int64_t)(1 + k) * n + a] = in ? 1 : 0;
   }
 }
@@ -93,6 +94,31 @@ void accumulate_rows_launch(const double* src, const int32_t* index, int64_t n, 
                             hipStream_t s) {
   if (n <= 0) return;
   k_accumulate_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, index, n, n_dst, dst);
+}
+
+// graph halo (Methods "Graph Partitioning", stage 2 as a breadth-first
+// expansion): hop 0 on the atoms of slab sa.part, K + 1 elsewhere (sorted rows)
+__global__ void k_bfs_roots(const double* __restrict__ pos_s, int64_t n, SlabArgs sa, int K, int32_t* __restrict__ hop) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double x;
+  int b;
+  slab_wrap(pos_s[3 * r + sa.axis], sa.L, sa.P, &x, &b);
+  hop[r] = (b == sa.part) ? 0 : K + 1;
+}
+
+__global__ void k_hop_to_input(int64_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ hop_sorted,
+                               int32_t* __restrict__ hop_in) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r < n) hop_in[perm[r]] = hop_sorted[r];
+}
+
+void bfs_hops_launch(const NbrBuffers& b, int64_t n, const SlabArgs& sa, int K, int64_t capacity, int32_t* hop_sorted,
+                     int32_t* hop_in, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  k_bfs_roots<<<g, 256, 0, s>>>(b.pos_s, n, sa, K, hop_sorted);
+  for (int h = 0; h < K; ++h) hop_sweep_launch(b, n, h, capacity, hop_sorted, s);
+  k_hop_to_input<<<g, 256, 0, s>>>(n, b.perm, hop_sorted, hop_in);
 }
 
 // E += e, W += w: one partition's root energy and virial into the totals

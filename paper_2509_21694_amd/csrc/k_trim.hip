@@ -217,6 +217,10 @@ __global__ void k_zero_edges_from(float4* __restrict__ g, const int32_t* __restr
 
 int trim_max_layers() { return kMaxClass - 1; }
 
+void hop_sweep_launch(const NbrBuffers& b, int64_t n, int h, int64_t capacity, int32_t* hop, hipStream_t s) {
+  k_hop_sweep<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, b.e_src, capacity, b.status, h, hop);
+}
+
 const int64_t* trim_classes(const NbrBuffers& b, int64_t n, int K, int64_t capacity, hipStream_t s) {
   const TrimScratch t = trim_scratch(b, n);
   const unsigned g1 = (unsigned)((n + 255) / 256), gw = (unsigned)((n + 3) / 4);

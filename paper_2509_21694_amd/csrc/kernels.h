@@ -62,6 +62,8 @@ void trim_permute(const NbrBuffers& b, int64_t n, int64_t capacity, float4* tmp,
 // g[e] = 0 for the edges of rows row0 .. n-1
 void zero_edges_from(float4* g, const int32_t* row_ptr, int64_t row0, int64_t n, int64_t capacity, hipStream_t s);
 int trim_max_layers();
+// one breadth-first level: neighbours of rows at hop h get min(hop, h + 1)
+void hop_sweep_launch(const NbrBuffers& b, int64_t n, int h, int64_t capacity, int32_t* hop, hipStream_t s);
 constexpr int64_t trim_min_atoms() { return 64; }
 
 int64_t scan_tmp_elems(int64_t n);
@@ -317,7 +319,16 @@ struct SlabArgs {
   double L;       // cell length along the axis
   double halo;    // halo depth
   int64_t capacity;
+  // graph halo: keep a halo image only if its atom is within max_hop hops of
+  // a root (hop per input atom); null: every image in the geometric halo
+  const int32_t* hop = nullptr;
+  int max_hop = 0;
 };
+// hop distances for a graph halo over a built list (sorted rows): roots =
+// atoms of slab sa.part; K breadth-first levels; result per input atom in
+// hop_in (K + 1 = farther than K hops)
+void bfs_hops_launch(const NbrBuffers& b, int64_t n, const SlabArgs& sa, int K, int64_t capacity, int32_t* hop_sorted,
+                     int32_t* hop_in, hipStream_t s);
 void slab_share_launch(const double* pos, const int32_t* spec, int64_t n, const SlabArgs& sa, int32_t* flags,
                        int32_t* offs, int32_t* scan_tmp, hipStream_t s);
 void slab_write_launch(const double* pos, const int32_t* spec, int64_t n, const SlabArgs& sa, const int32_t* flags,

@@ -203,3 +203,73 @@ def test_partitioned_driver_8m(torch, M):
               f"|dF|={dF:.2e} |F|={np.abs(r.forces[c]).max():.2e}")
         assert abs(ae[a] - r.atom_energy[c]) <= 1e-3
         assert dF <= max(5e-3, 5e-2 * np.abs(r.forces[c]).max())
+
+
+# graph (K-hop) halo: a 5,120-atom box, 182 x 18.2 x 18.2 A, 4 slabs along x
+@pytest.fixture(scope="module")
+def bfs_case():
+    return W.slab_full_system(80, 8, 8, 411, 412)
+
+
+@pytest.mark.parametrize("K", [1, 2, 6])
+def test_bfs_share_matches_oracle(torch, M, K, bfs_case):
+    """The graph-halo share built on the GPU (whole-structure list, K
+    breadth-first levels, masked slab share) equals the oracle's bit for bit."""
+    s = bfs_case
+    pos = torch.tensor(s.positions, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    for part in (0, 2):
+        print(f"[bfs share] K={K} part {part}", flush=True)
+        lp, ls, pbc, n_own, gi = oracle.bfs_share(s.positions, s.species, s.cell, 4, part, K, RC)
+        gp, gs, gx, gn = M.bfs_share(pos, sp, s.cell, 4, part, K, RC)
+        assert gn == n_own
+        assert np.array_equal(gx.cpu().numpy(), gi)
+        assert np.array_equal(gp.cpu().numpy(), lp)
+        assert np.array_equal(gs.cpu().numpy(), ls)
+        n_geo = oracle.slab_share(s.positions, s.species, s.cell, 4, part, K * RC)[0].shape[0]
+        print(f"[bfs share] K={K} part {part}: H graph {(lp.shape[0] - n_own) / n_own:.3f} "
+              f"geometric {(n_geo - n_own) / n_own:.3f}")
+        assert lp.shape[0] <= n_geo
+
+
+@pytest.fixture(scope="module")
+def bfs_full(bfs_case):
+    hp = W.HP_MPDP
+    blob = W.make_weights(hp, W.WEIGHT_SEEDS["slab8m"])
+    s = bfs_case
+    return blob, oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, hp, K=2)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_graph_halo_driver(torch, M, prec, bfs_case, bfs_full):
+    """mpip_evaluate_partitioned with the graph halo (4 parts, K = 2): the
+    whole 5,120-atom box's energy, forces, virial and atom energies from the
+    oracle."""
+    s = bfs_case
+    blob, ref = bfs_full
+    model = M.Model(W.HP_MPDP, blob)
+    pos = torch.tensor(s.positions, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    print(f"[graph driver] {prec}", flush=True)
+    o = model.evaluate_partitioned(pos, sp, s.cell, s.pbc, n_parts=4, K=2, graph_halo=True, precision=prec,
+                                   atom_energy=True)
+    parts = o["parts"]
+    for p in range(4):
+        lp, _, _, n_own, _ = oracle.bfs_share(s.positions, s.species, s.cell, 4, p, 2, RC)
+        assert parts[p, 0] == lp.shape[0] and parts[p, 1] == n_own
+    E = float(o["energy"].cpu()[0])
+    F = o["forces"].cpu().numpy()
+    Wv = o["virial"].cpu().numpy()
+    ae = o["atom_energy"].cpu().numpy()
+    dE = abs(E - ref.energy) / s.n_atoms
+    dF = np.abs(F - ref.forces)
+    rms, frms = np.sqrt(np.mean(dF ** 2)), np.sqrt(np.mean(ref.forces ** 2))
+    dW = np.abs(Wv - ref.virial).max() / abs(np.linalg.det(s.cell))
+    dae = np.abs(ae - ref.atom_energy).max()
+    print(f"[graph driver] {prec}: H={parts[:, 0].sum() / s.n_atoms - 1:.3f} dE/N={dE:.2e} max|dF|={dF.max():.2e} "
+          f"rms={rms:.2e} |dW|/V={dW:.2e} max|dE_i|={dae:.2e}")
+    if prec == "fp32":
+        assert dE <= 1e-6 and dF.max() <= 1e-4 and dF.max() <= 1e-5 * np.abs(ref.forces).max()
+        assert dW <= 1e-8 and dae <= 1e-6
+    else:
+        assert dE <= 1e-3 and rms <= 5e-3 and rms <= 2e-2 * frms and dW <= 1e-5 and dae <= 1e-3

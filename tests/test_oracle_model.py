@@ -281,6 +281,69 @@ def test_partition_root_energies_and_force_sum():
     assert np.allclose(Wv, full.virial, atol=1e-10)
 
 
+def _reach(s, roots, K):
+    """Atoms within K hops of the roots from powers of the adjacency matrix
+    of a brute-force minimum-image distance matrix (no neighbour list, no
+    breadth-first levels)."""
+    L = np.diag(s.cell)
+    d = s.positions[:, None, :] - s.positions[None, :, :]
+    d -= np.round(d / L) * L
+    A = (np.sqrt((d ** 2).sum(-1)) < RC).astype(np.int64)
+    np.fill_diagonal(A, 0)
+    r = np.zeros(s.n_atoms, dtype=np.int64)
+    r[roots] = 1
+    for _ in range(K):
+        r = ((r + A @ r) > 0).astype(np.int64)
+    return r.astype(bool)
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_bfs_share_is_the_k_hop_set(K):
+    """The graph halo (stage-2 breadth-first expansion): the halo atoms are
+    exactly the atoms within K hops of a root, each once, in the rows of the
+    geometric K*r_cut share (same positions, same order)."""
+    s, _, _ = _slab_case()
+    for part in (0, 5):
+        lp, ls, pbc, n_own, gi = oracle.bfs_share(s.positions, s.species, s.cell, 8, part, K, RC)
+        gp, gs, _, g_own, ggi = oracle.slab_share(s.positions, s.species, s.cell, 8, part, K * RC)
+        assert n_own == g_own and np.array_equal(gi[:n_own], ggi[:n_own])
+        want = _reach(s, gi[:n_own], K)
+        want[gi[:n_own]] = False
+        assert np.array_equal(np.sort(gi[n_own:]), np.flatnonzero(want))
+        keep = np.isin(np.arange(gp.shape[0]), np.arange(g_own)) | want[ggi]
+        assert np.array_equal(lp, gp[keep]) and np.array_equal(gi, ggi[keep]) and np.array_equal(ls, gs[keep])
+        assert not pbc[0] and pbc[1] and pbc[2]
+
+
+def test_bfs_share_partition_rule():
+    """Graph-halo partitions reproduce the full system: root-atom energies,
+    and forces / virials summed over partitions with ghost rows returned to
+    their owners; the graph halo is smaller than the geometric one."""
+    s, hp, blob = _slab_case()
+    full = oracle.evaluate(s.positions, s.species, s.cell, s.pbc, blob, hp)
+    F = np.zeros_like(full.forces)
+    E, Wv, rows_bfs, rows_geo = 0.0, np.zeros((3, 3)), 0, 0
+    for part in range(8):
+        lp, ls, pbc, n_own, gi = oracle.bfs_share(s.positions, s.species, s.cell, 8, part, 2, RC)
+        rows_bfs += lp.shape[0]
+        rows_geo += oracle.slab_share(s.positions, s.species, s.cell, 8, part, 2 * RC)[0].shape[0]
+        r = oracle.evaluate(lp, ls, s.cell, pbc, blob, hp, K=2, n_owned=n_own)
+        assert np.allclose(r.atom_energy[:n_own], full.atom_energy[gi[:n_own]], atol=1e-12)
+        np.add.at(F, gi, r.forces)
+        E += r.energy
+        Wv += r.virial
+    assert E == pytest.approx(full.energy, abs=1e-9)
+    assert np.allclose(F, full.forces, atol=1e-12)
+    assert np.allclose(Wv, full.virial, atol=1e-10)
+    assert rows_bfs < rows_geo
+
+
+def test_bfs_share_rejects_wrapped_halo():
+    s, _, _ = _slab_case()
+    with pytest.raises(ValueError):
+        oracle.bfs_share(s.positions, s.species, s.cell, 2, 0, 6, RC)
+
+
 def test_partition_alone_needs_double_halo():
     """(iii) one partition on its own reproduces its root atoms' forces only
     if its halo is 2*K*r_cut deep and the energy is summed over the root
