@@ -662,14 +662,13 @@ mpip_status mpip_neighbor_list(const mpip_system* sys, double r_cut, void* strea
 }  // extern "C"
 
 // Layers forward, readout and the adjoint of all layers on a built CSR:
-// leaves dE/dr_e in the workspace (g) and per-atom energies (atom_e).
-// Returns the buffer holding the last layer's part of the edge gradients
-// when it is kept apart from g (see FastArgs::g2p), else null.
+// leaves dE/dr_e, or the equivalent h_e of FastArgs::g2p, in the workspace
+// (g) and per-atom energies (atom_e).
 // rows: null, or rows[t] (t = 0..K) = the row prefix that layer t updates on
 // a share whose rows are sorted by hop class (receptive-field trimming):
 // layer t's receivers are rows < rows[t], and the passes that act on senders
 // (features into layer t, the adjoint's pull) cover rows < rows[t - 1].
-static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b, int64_t N,
+static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b, int64_t N,
                                mpip_precision prec, int32_t K, int64_t max_edges, hipStream_t s,
                                const int64_t* rows = nullptr) {
   const mpip_hparams& hp = m->hp;
@@ -780,6 +779,10 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
       for (int l = 0; l <= L; ++l)
         gemm(h + l * l * C, (int64_t)nlm * C, C, at(ht, l * l * C, fast ? ht_bf16 : 0), (int64_t)nlm * C, C,
              R(t - 1) * (2 * l + 1), 2 * l + 1, C, C, C, d.up_t[l], 0, fast ? ht_bf16 : 0);
+    // trimmed: the generic adjoint of layer t walks rows up to R(t - 1) and
+    // reads the features of their neighbours (times a zero dA where the
+    // receiver is outside layer t); rows it was not given must be finite
+    if (rows && t >= 2 && !node1 && !fast) zero_rows(ht, R(t - 1), (int64_t)nlm * C);
     T.begin("edge_fwd_t" + std::to_string(t), s);
     if (fast) {
       set_fast(d, role);
@@ -944,12 +947,11 @@ static const float4* run_model(mpip_model* m, const Plan& p, char* w, const NbrB
              2 * l + 1, C, C, C, d.up[l], 1);
   }
   if (rows && fa.g2p) {
-    // g (layer 1) and g2p (last layer) are written, not accumulated, on the
-    // rows the passes walked; the rest must read as zero
+    // g is written, not accumulated, on the rows the first layer's adjoint
+    // walked (it reads g2p there only, where the last layer's adjoint wrote
+    // it); the rest must read as zero
     zero_edges_from(g, b.row_ptr, R(1), N, max_edges, s);
-    zero_edges_from(fa.g2p, b.row_ptr, R(K - 1), N, max_edges, s);
   }
-  return fa.g2p;
 }
 
 
@@ -958,9 +960,9 @@ static void eval_on_list(mpip_model* m, const Plan& p, char* w, const NbrBuffers
                          int32_t K, int64_t max_edges, hipStream_t s, const mpip_outputs* out,
                          const int64_t* rows = nullptr) {
   PhaseTimer& T = m->timer;
-  const float4* g2p = run_model(m, p, w, b, N, prec, K, max_edges, s, rows);
+  run_model(m, p, w, b, N, prec, K, max_edges, s, rows);
   OutArgs oa;
-  oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = (float4*)(w + p.o_g); oa.g2p = g2p; oa.e_rev = b.e_rev;
+  oa.n = N; oa.row_ptr = b.row_ptr; oa.e_vec = b.e_vec; oa.g = (float4*)(w + p.o_g); oa.e_rev = b.e_rev;
   oa.perm = b.perm; oa.owned_s = b.owned_s; oa.atom_e = (double*)(w + p.o_atom_e); oa.capacity = max_edges;
   oa.status = b.status; oa.partials = (double*)(w + p.o_partials); oa.nblocks = p.nblocks_out;
   oa.forces = out->forces; oa.atom_energy = out->atom_energy; oa.energy = out->energy; oa.virial = out->virial;
@@ -1456,9 +1458,9 @@ mpip_status mpip_evaluate_batch(mpip_model* m, int32_t B, const int64_t* atom_pt
   T.begin("neighbors", s);
   build_neighbors_batch(b, bb, B, positions, species, N, hp.n_species, hp.r_cut, max_edges, s);
   T.end(s);
-  const float4* g2p = run_model(m, p, w, b, N, prec, K, max_edges, s);
+  run_model(m, p, w, b, N, prec, K, max_edges, s);
   T.begin("outputs", s);
-  launch_batch_outputs(N, B, b, (const float4*)(w + p.o_g), g2p, (const double*)(w + p.o_atom_e), bb, max_edges,
+  launch_batch_outputs(N, B, b, (const float4*)(w + p.o_g), (const double*)(w + p.o_atom_e), bb, max_edges,
                        forces, energy, virial, s);
   T.end(s);
   hipError_t e = hipGetLastError();

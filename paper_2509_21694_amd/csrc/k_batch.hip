@@ -141,7 +141,6 @@ void build_neighbors_batch(const NbrBuffers& b, const BatchBuffers& bb, int B, c
 // one block per structure: forces of its atoms, its energy and virial (FP64, fixed order)
 __global__ __launch_bounds__(256) void k_batch_out(int64_t n, const int32_t* __restrict__ row_ptr,
                                                    const float4* __restrict__ e_vec, const float4* __restrict__ g,
-                                                   const float4* __restrict__ g2p,
                                                    const int32_t* __restrict__ e_rev, const double* __restrict__ atom_e,
                                                    const int64_t* __restrict__ ptr, int64_t capacity,
                                                    const int64_t* __restrict__ status, double* __restrict__ forces,
@@ -157,15 +156,8 @@ __global__ __launch_bounds__(256) void k_batch_out(int64_t n, const int32_t* __r
       double F[3] = {0.0, 0.0, 0.0};
       for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
         const int rv = e_rev[e];
-        float4 ge = g[e];
-        float4 gr = rv >= 0 ? g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
-        if (g2p) {
-          // dE/dr_e = g[e] + g2p[rev(e)] (the last layer's part kept in the reverse edge's slot)
-          const float4 he = g2p[e];
-          const float4 hr = rv >= 0 ? g2p[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
-          ge.x += hr.x; ge.y += hr.y; ge.z += hr.z;
-          gr.x += he.x; gr.y += he.y; gr.z += he.z;
-        }
+        const float4 ge = g[e];
+        const float4 gr = rv >= 0 ? g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
         const float4 r = e_vec[e];
         F[0] += (double)ge.x - (double)gr.x;
         F[1] += (double)ge.y - (double)gr.y;
@@ -195,10 +187,10 @@ __global__ __launch_bounds__(256) void k_batch_out(int64_t n, const int32_t* __r
   if (threadIdx.x < 9) virial[9 * b + threadIdx.x] = -sh[1 + threadIdx.x][0];
 }
 
-void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g, const float4* g2p,
+void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g,
                           const double* atom_e, const BatchBuffers& bb, int64_t capacity, double* forces,
                           double* energy, double* virial, hipStream_t s) {
-  k_batch_out<<<B, 256, 0, s>>>(n, nb.row_ptr, nb.e_vec, g, g2p, nb.e_rev, atom_e, bb.ptr, capacity, nb.status, forces,
+  k_batch_out<<<B, 256, 0, s>>>(n, nb.row_ptr, nb.e_vec, g, nb.e_rev, atom_e, bb.ptr, capacity, nb.status, forces,
                                 energy, virial);
 }
 

@@ -553,8 +553,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + sp * NLM + k];
         yc_last_adj<L>(cgd, ycb, Yb);
         if (a.g2p) {
-          // this layer's part only; the outputs add the last layer's from g2p
-          a.g[e] = edge_grad(geo, eb, Yb);
+          // h_e = (this layer's dE/dr_e) - g2p[e], where g2p[e] is the last
+          // layer's dE/dr of the reverse edge: then F_i = sum_e h_e - h_rev(e)
+          // and the virial is -sum_e r_e (x) h_e (r_rev(e) = -r_e), so the
+          // outputs gather one array through the reverse edges instead of two
+          const float4 d = edge_grad(geo, eb, Yb);
+          const float4 q = a.g2p[e];
+          a.g[e] = make_float4(d.x - q.x, d.y - q.y, d.z - q.z, 0.f);
         } else {
           add_edge_grad(a.g, e, geo, eb, Yb);
         }

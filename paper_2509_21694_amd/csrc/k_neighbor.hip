@@ -131,13 +131,19 @@ __global__ void k_bounds(const double* __restrict__ pos, const int32_t* __restri
 
 __global__ void k_grid(const double* __restrict__ part, int nparts, CellInfo ci, int max_bins,
                        GridParams* __restrict__ gp, int64_t* __restrict__ status) {
-  if (threadIdx.x != 0) return;
+  // min / max over the partial bounds: lane-strided, then a butterfly (exact in any order)
   double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-  for (int b = 0; b < nparts; ++b)
+  for (int b = threadIdx.x; b < nparts; b += 64)
     for (int d = 0; d < 3; ++d) {
       mn[d] = fmin(mn[d], part[b * 6 + d]);
       mx[d] = fmax(mx[d], part[b * 6 + 3 + d]);
     }
+  for (int off = 32; off > 0; off >>= 1)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = fmin(mn[d], __shfl_xor(mn[d], off));
+      mx[d] = fmax(mx[d], __shfl_xor(mx[d], off));
+    }
+  if (threadIdx.x != 0) return;
   const double wmin = ci.rc * (1.0 + 1e-6);
   GridParams g;
   for (int d = 0; d < 3; ++d) {

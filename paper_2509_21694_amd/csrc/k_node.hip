@@ -281,8 +281,9 @@ void launch_gate_bwd(const NodeArgs& a, int last, int init_hbar, hipStream_t s) 
 // ------------------------------------------------------------ outputs
 
 // Per atom: F_i = sum_{e in row i} G_e - G_rev(e) (FP64), written in input
-// order, with G_e = g[e] (+ g2p[rev(e)] when the last layer's part is kept
-// apart); per block: sum of root energies and of r_e (x) G_e, fixed order.
+// order, with G_e = g[e] (dE/dr_e, or the h_e of FastArgs::g2p, which gives
+// the same sums); per block: sum of root energies and of r_e (x) G_e, fixed
+// order.
 // A wave takes 64 rows, 4 at a time with 16 lanes over each row's edges and
 // a 16-lane butterfly per row; each lane keeps its virial partial sums.
 __global__ __launch_bounds__(256) void k_forces(OutArgs a) {
@@ -300,14 +301,8 @@ __global__ __launch_bounds__(256) void k_forces(OutArgs a) {
       if (i < a.n) {
         for (int e = a.row_ptr[i] + el; e < a.row_ptr[i + 1]; e += 16) {
           const int rv = a.e_rev[e];
-          float4 ge = a.g[e];
-          float4 gr = rv >= 0 ? a.g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
-          if (a.g2p) {
-            const float4 he = a.g2p[e];
-            const float4 hr = rv >= 0 ? a.g2p[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
-            ge.x += hr.x; ge.y += hr.y; ge.z += hr.z;
-            gr.x += he.x; gr.y += he.y; gr.z += he.z;
-          }
+          const float4 ge = a.g[e];
+          const float4 gr = rv >= 0 ? a.g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
           const float4 r = a.e_vec[e];
           F[0] += (double)ge.x - (double)gr.x;
           F[1] += (double)ge.y - (double)gr.y;

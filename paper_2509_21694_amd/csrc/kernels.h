@@ -197,10 +197,13 @@ struct FastArgs {
   float4* g;
   void* msg;             // last layer forward, BF16 form: messages [E][C] bf16 in CSR order
   // When set (two specialised layers, BF16 form): the fused last-layer adjoint
-  // writes dE/dr of each edge's reverse into the edge's own slot of g2p and
-  // the first-layer adjoint writes its own part to g (so g needs no
-  // clearing); the outputs combine dE/dr_e = g[e] + g2p[rev(e)].  Otherwise
-  // both accumulate into g.
+  // writes dE/dr of each edge's reverse into the edge's own slot of g2p, and
+  // the first-layer adjoint, which runs after it, writes h_e = (its own
+  // dE/dr_e) - g2p[e] to g (so g needs no clearing).  With
+  // dE/dr_e = g1_e + g2p[rev(e)] and r_rev(e) = -r_e, the forces
+  // sum_e (dE/dr_e - dE/dr_rev(e)) equal sum_e (h_e - h_rev(e)) and the virial
+  // -sum_e r_e (x) dE/dr_e equals -sum_e r_e (x) h_e: the outputs read g as
+  // when both layers accumulate into it.  Otherwise both accumulate into g.
   float4* g2p;
 };
 
@@ -275,8 +278,7 @@ struct OutArgs {
   int64_t n;
   const int32_t* row_ptr;
   const float4* e_vec;
-  const float4* g;
-  const float4* g2p;      // null, or the last layer's part of dE/dr of each edge's reverse (see FastArgs)
+  const float4* g;        // dE/dr_e, or h_e (see FastArgs::g2p): same forces and virial
   const int32_t* e_rev;
   const int32_t* perm;
   const uint8_t* owned_s;
@@ -306,7 +308,7 @@ struct BatchBuffers {
 };
 void build_neighbors_batch(const NbrBuffers& b, const BatchBuffers& bb, int B, const double* pos,
                            const int32_t* spec, int64_t n, int n_species, double rc, int64_t capacity, hipStream_t s);
-void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g, const float4* g2p,
+void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g,
                           const double* atom_e, const BatchBuffers& bb, int64_t capacity, double* forces,
                           double* energy, double* virial, hipStream_t s);
 
