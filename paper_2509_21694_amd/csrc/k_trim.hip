@@ -61,16 +61,16 @@ __global__ void k_hop_init(int64_t n, const uint8_t* __restrict__ owned_s, int K
 }
 
 // one level of the breadth-first expansion: the neighbours of atoms at hop h
-// get hop h + 1 unless they are closer already.  One wave per row.  Several
-// waves may store the same value h + 1 into one entry; an entry at hop h is
+// get hop h + 1 unless they are closer already.  16 lanes per row.  Several
+// lanes may store the same value h + 1 into one entry; an entry at hop h is
 // never written in this level, so the frontier test is not disturbed.
 __global__ __launch_bounds__(256) void k_hop_sweep(int64_t n, const int32_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ e_src, int64_t capacity,
                                                    const int64_t* __restrict__ status, int h, int32_t* hop) {
-  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
   if (i >= n || list_bad(row_ptr, n, capacity, status)) return;
   if (hop[i] != h) return;
-  for (int e = row_ptr[i] + (threadIdx.x & 63); e < row_ptr[i + 1]; e += 64) {
+  for (int e = row_ptr[i] + (threadIdx.x & 15); e < row_ptr[i + 1]; e += 16) {
     const int j = e_src[e];
     if (hop[j] > h + 1) hop[j] = h + 1;
   }
@@ -175,18 +175,18 @@ __global__ void k_save_vec(const int32_t* __restrict__ rp_o, int64_t n, int64_t 
   tmp[e] = e_vec[e];
 }
 
-// one wave per old row: its edges move, in order, to the new row; senders
+// 16 lanes per old row: its edges move, in order, to the new row; senders
 // and reverse edges are renumbered (the reverse of an edge keeps its offset
 // within the sender's row)
 __global__ __launch_bounds__(256) void k_perm_edges(int64_t n, int64_t capacity, TrimScratch t,
                                                     const int32_t* __restrict__ row_ptr, const int4* __restrict__ tmp,
                                                     int32_t* __restrict__ e_src, uint32_t* __restrict__ e_shift,
                                                     int32_t* __restrict__ e_rev) {
-  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
   if (i >= n || (int64_t)t.rp_o[n] > capacity) return;
   const int r0 = t.rp_o[i], r1 = t.rp_o[i + 1];
   const int d0 = row_ptr[t.newidx[i]];
-  for (int e = r0 + (threadIdx.x & 63); e < r1; e += 64) {
+  for (int e = r0 + (threadIdx.x & 15); e < r1; e += 16) {
     const int4 v = tmp[e];
     const int jn = t.newidx[v.x];
     const int ed = d0 + (e - r0);
@@ -199,11 +199,11 @@ __global__ __launch_bounds__(256) void k_perm_edges(int64_t n, int64_t capacity,
 __global__ __launch_bounds__(256) void k_perm_vec(int64_t n, int64_t capacity, TrimScratch t,
                                                   const int32_t* __restrict__ row_ptr, const float4* __restrict__ tmp,
                                                   float4* __restrict__ e_vec) {
-  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
   if (i >= n || (int64_t)t.rp_o[n] > capacity) return;
   const int r0 = t.rp_o[i], r1 = t.rp_o[i + 1];
   const int d0 = row_ptr[t.newidx[i]];
-  for (int e = r0 + (threadIdx.x & 63); e < r1; e += 64) e_vec[d0 + (e - r0)] = tmp[e];
+  for (int e = r0 + (threadIdx.x & 15); e < r1; e += 16) e_vec[d0 + (e - r0)] = tmp[e];
 }
 
 __global__ void k_zero_edges_from(float4* __restrict__ g, const int32_t* __restrict__ row_ptr, int64_t row0, int64_t n,
@@ -218,12 +218,12 @@ __global__ void k_zero_edges_from(float4* __restrict__ g, const int32_t* __restr
 int trim_max_layers() { return kMaxClass - 1; }
 
 void hop_sweep_launch(const NbrBuffers& b, int64_t n, int h, int64_t capacity, int32_t* hop, hipStream_t s) {
-  k_hop_sweep<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, b.e_src, capacity, b.status, h, hop);
+  k_hop_sweep<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(n, b.row_ptr, b.e_src, capacity, b.status, h, hop);
 }
 
 const int64_t* trim_classes(const NbrBuffers& b, int64_t n, int K, int64_t capacity, hipStream_t s) {
   const TrimScratch t = trim_scratch(b, n);
-  const unsigned g1 = (unsigned)((n + 255) / 256), gw = (unsigned)((n + 3) / 4);
+  const unsigned g1 = (unsigned)((n + 255) / 256), gw = (unsigned)((n + 15) / 16);
   k_hop_init<<<g1, 256, 0, s>>>(n, b.owned_s, K, t.hop);
   for (int h = 0; h + 1 < K; ++h)
     k_hop_sweep<<<gw, 256, 0, s>>>(n, b.row_ptr, b.e_src, capacity, b.status, h, t.hop);
@@ -240,7 +240,7 @@ const int64_t* trim_classes(const NbrBuffers& b, int64_t n, int K, int64_t capac
 
 void trim_permute(const NbrBuffers& b, int64_t n, int64_t capacity, float4* tmp, hipStream_t s) {
   const TrimScratch t = trim_scratch(b, n);
-  const unsigned g1 = (unsigned)((n + 256) / 256), gw = (unsigned)((n + 3) / 4);
+  const unsigned g1 = (unsigned)((n + 256) / 256), gw = (unsigned)((n + 15) / 16);
   const unsigned ge = (unsigned)((capacity + 255) / 256);
   k_save_nodes<<<g1, 256, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, b.owned_s, b.perm, b.row_ptr, t);
   k_perm_nodes<<<g1, 256, 0, s>>>(n, t, b.pos_s, b.info_s, b.spec_s, b.owned_s, b.perm, b.inv_perm, b.cnt);
