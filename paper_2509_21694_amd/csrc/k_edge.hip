@@ -24,6 +24,17 @@ namespace mpip {
 
 // ------------------------------------------------------------ forward
 
+// Weights and coupling coefficients are the same for every tile; left
+// visible, their loads (the radial MLP and W3 of every path: hundreds of
+// registers at l_max = 2) are hoisted ahead of the row loop and held there,
+// which spills.  Hiding the pointers from the optimiser once per tile keeps
+// each load next to its use, served from cache.
+template <class T>
+__device__ __forceinline__ T* opaque_ptr(T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 template <int PREC, int C, int L, int KIND>
 __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
   typedef PathList<L, KIND> PL;
@@ -62,7 +73,7 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
           constexpr int pi = decltype(PI)::value;
           constexpr P3 pp = PL::get(pi);
           constexpr int n1 = 2 * pp.l1 + 1, n2 = 2 * pp.l2 + 1, n3 = 2 * pp.l3 + 1;
-          const float* cg = a.cg + PL::cg_off(pi);
+          const float* cg = opaque_ptr(a.cg + PL::cg_off(pi));
 #pragma unroll
           for (int m1 = 0; m1 < n1; ++m1)
             for (int m3 = 0; m3 < n3; ++m3) {
@@ -73,7 +84,8 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
         });
       }
       f32x4 p1[4], p2[4], a2[4];
-      mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
+      const void* w3f = opaque_ptr(a.w3f);
+      mlp_forward<PREC>(geo, lane, opaque_ptr(a.w1a), opaque_ptr(a.w2a), p1, p2);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -83,7 +95,7 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
         constexpr P3 pp = PL::get(pi);
         constexpr int n1 = 2 * pp.l1 + 1, n3 = 2 * pp.l3 + 1;
         __syncthreads();
-        radial_out<PREC, C>(a2, lane, a.w3f, pi, sR, RS);
+        radial_out<PREC, C>(a2, lane, w3f, pi, sR, RS);
         __syncthreads();
         for (int ee = eg; ee < kTileE; ee += EPL) {
           if (t0 + ee >= e1) break;
@@ -132,7 +144,6 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
   constexpr int CPL = C / CW;
   constexpr int EPL = 64 / CW;
   constexpr int RS = C + 1;
-  constexpr int CB = C / 4;                // channel block of pass B
   constexpr bool SPECIES_IN = (KIND == KIND_ONLY || KIND == KIND_FIRST);
   __shared__ float sR[kTileE * RS];
   __shared__ float sRb[kTileE * RS];
@@ -172,7 +183,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
           constexpr int pi = decltype(PI)::value;
           constexpr P3 pp = PL::get(pi);
           constexpr int n1 = 2 * pp.l1 + 1, n2 = 2 * pp.l2 + 1, n3 = 2 * pp.l3 + 1;
-          const float* cg = a.cg + PL::cg_off(pi);
+          const float* cg = opaque_ptr(a.cg + PL::cg_off(pi));
 #pragma unroll
           for (int m1 = 0; m1 < n1; ++m1)
             for (int m3 = 0; m3 < n3; ++m3) {
@@ -183,7 +194,9 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         });
       }
       f32x4 p1[4], p2[4], a2[4], ab2[4];
-      mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
+      const void* w3f = opaque_ptr(a.w3f);
+      const void* w3b = opaque_ptr(a.w3b);
+      mlp_forward<PREC>(geo, lane, opaque_ptr(a.w1a), opaque_ptr(a.w2a), p1, p2);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -197,10 +210,14 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         constexpr int n1 = 2 * pp.l1 + 1, n2 = 2 * pp.l2 + 1, n3 = 2 * pp.l3 + 1;
         constexpr int ob = (NOUT == 1) ? 0 : pp.l3 * pp.l3;
         constexpr float sgn = (pp.l2 & 1) ? -1.f : 1.f;
+        // one path at a time: interleaving the unrolled paths spills
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
-        radial_out<PREC, C>(a2, lane, a.w3f, pi, sR, RS);
+        radial_out<PREC, C>(a2, lane, w3f, pi, sR, RS);
         __syncthreads();
-        // pass A: lanes own channels, walk the edges
+        // pass A: lanes own channels, walk the edges (rolled: unrolled, the
+        // loads of all 16 edges are hoisted and the registers spill)
+#pragma unroll 1
         for (int ee = eg; ee < kTileE; ee += EPL) {
           const bool ok = (t0 + ee) < e1;
           const int j = sj[ee];
@@ -232,21 +249,39 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
             sRb[ee * RS + c] = rb;
           }
         }
-        // pass B: lanes own (edge el, channel block g); dE/dY of the edge
+        // pass B: lanes own (edge el, quarter g of every 16 channels); dE/dY
+        // of the edge.  Lane g takes channels 16 q + 4 g .. + 3, so the four
+        // lanes of an edge read 64 contiguous bytes of the sender's row.
         {
           const bool ok = valid;
           float W[5][5];
           for (int m1 = 0; m1 < n1; ++m1)
             for (int m3 = 0; m3 < n3; ++m3) W[m1][m3] = 0.f;
           if (ok) {
-            for (int cc = 0; cc < CB; ++cc) {
-              const int c = g * CB + cc;
-              const float R = sR[el * RS + c];
-              for (int m1 = 0; m1 < n1; ++m1) {
-                const float hv = SPECIES_IN ? a.ht[(int64_t)jme * C + c]
-                                            : a.ht[((int64_t)jme * NLM + pp.l1 * pp.l1 + m1) * C + c];
-                const float Rh = R * hv;
-                for (int m3 = 0; m3 < n3; ++m3) W[m1][m3] += Rh * sAi[(ob + m3) * C + c];
+            // channels outermost (rolled), so only one float4 of features per
+            // degree and one channel's dA are live at a time
+            const float* hrow = SPECIES_IN ? a.ht + (int64_t)jme * C
+                                           : a.ht + ((int64_t)jme * NLM + pp.l1 * pp.l1) * C;
+#pragma unroll 1
+            for (int q = 0; q < C / 16; ++q) {
+              float4 hv4[n1];
+#pragma unroll
+              for (int m1 = 0; m1 < n1; ++m1)
+                hv4[m1] = *(const float4*)(hrow + (SPECIES_IN ? 0 : m1 * C) + 16 * q + 4 * g);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int c = 16 * q + 4 * g + u;
+                const float R = sR[el * RS + c];
+                float A3[n3];
+#pragma unroll
+                for (int m3 = 0; m3 < n3; ++m3) A3[m3] = sAi[(ob + m3) * C + c];
+#pragma unroll
+                for (int m1 = 0; m1 < n1; ++m1) {
+                  const float hv = u == 0 ? hv4[m1].x : (u == 1 ? hv4[m1].y : (u == 2 ? hv4[m1].z : hv4[m1].w));
+                  const float Rh = R * hv;
+#pragma unroll
+                  for (int m3 = 0; m3 < n3; ++m3) W[m1][m3] += Rh * A3[m3];
+                }
               }
             }
           }
@@ -257,7 +292,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
               w += __shfl_xor(w, 32);
               W[m1][m3] = w;
             }
-          const float* cg = a.cg + PL::cg_off(pi);
+          const float* cg = opaque_ptr(a.cg + PL::cg_off(pi));
           for (int m2 = 0; m2 < n2; ++m2) {
             float s = 0.f;
             for (int m1 = 0; m1 < n1; ++m1)
@@ -271,7 +306,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
           for (int kc = 0; kc < O::kch(C); ++kc)
-            ab2[mt] = O::mma(O::ldt(a.w3b, (pi * 4 + mt) * O::kch(C) + kc, lane),
+            ab2[mt] = O::mma(O::ldt(w3b, (pi * 4 + mt) * O::kch(C) + kc, lane),
                              O::from_row(sRb + el * RS, kc, g), ab2[mt]);
         }
       });
@@ -286,7 +321,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kc = 0; kc < O::KC64; ++kc)
-          acc = O::mma(O::ldt(a.w2b, mt * O::KC64 + kc, lane), O::from_tiles(pb2, kc), acc);
+          acc = O::mma(O::ldt(opaque_ptr(a.w2b), mt * O::KC64 + kc, lane), O::from_tiles(pb2, kc), acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
       }
@@ -294,7 +329,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kc = 0; kc < O::KC64; ++kc)
-          acc = O::mma(O::ldt(a.w1b, kc, lane), O::from_tiles(pb1, kc), acc);
+          acc = O::mma(O::ldt(opaque_ptr(a.w1b), kc, lane), O::from_tiles(pb1, kc), acc);
         __syncthreads();
         if (g < 2) {
 #pragma unroll
