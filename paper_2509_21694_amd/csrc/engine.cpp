@@ -739,6 +739,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   fa.inv_n = (float)hp.inv_avg_neighbors; fa.Q = qp; fa.P = qp; fa.g = g; fa.htbar = htbar;
   fa.msg = p.o_msg ? (void*)(w + p.o_msg) : nullptr;
   fa.g2p = nullptr;
+  fa.row_end = nullptr;
+  // trimmed share: rows list the edges to root atoms first (ends in b.cnt)
+  const int32_t* root_end = rows ? b.cnt : nullptr;
   auto set_fast = [&](const LayerDev& d, int role) {
     fa.w1a = d.w1a; fa.w2a = d.w2a; fa.w2b = d.w2b; fa.w1b = d.w1b; fa.w2f = d.w2f;
     fa.w3f = d.w3fp[role]; fa.w3t = d.w3t[role]; fa.w3b = d.w3bp[role]; fa.cg = d.cg[role];
@@ -793,7 +796,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         fa.ht = ht; fa.A = A;
         if (ht_bf16 && fa.msg) {
           fa.n = R(K - 1);   // sender-side: rows whose features feed the roots
+          fa.row_end = root_end;
           launch_l2(prec, C, L, 4, fa, s);
+          fa.row_end = nullptr;
           T.end(s);
           T.begin("edge_sum_t" + std::to_string(t), s);
           fa.n = R(K);
@@ -922,7 +927,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         fa.ht = ht; fa.Abar = A;
         if (ht_bf16) {
           fa.n = R(K - 1);   // sender-side
+          fa.row_end = root_end;
           launch_l2(prec, C, L, 3, fa, s);
+          fa.row_end = nullptr;
         } else {
           fa.n = R(K);       // edge-parallel over the roots' edges
           launch_l2(prec, C, L, 1, fa, s);

@@ -1083,7 +1083,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     for (int j = 0; j < 8; ++j) sel[tt][j] = (__bf16)((8 * g + j == 2 * el + tt) ? 1.f : 0.f);
   const RowWalk rw = row_walk<NW>(a.n);
   for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+    const int e0 = a.row_ptr[i], e1 = a.row_end ? a.row_end[i] : a.row_ptr[i + 1];
     const unsigned short* hi = ht + (int64_t)i * NLM * C;
     // the row's features, transposed: sh[c][lm] (degrees NLM .. HT-1 zero)
 #pragma unroll
@@ -1243,6 +1243,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }
       }
     }
+    // edges of the row past the walked prefix carry no gradient (their
+    // receivers have dA = 0); their slots are read by the outputs
+    if (a.g2p)
+      for (int e = e1 + lane; e < a.row_ptr[i + 1]; e += 64) a.g2p[e] = make_float4(0.f, 0.f, 0.f, 0.f);
     // htbar_i: D rows lm = 4g + r, column el of half tt = channel 32k + 2 el + tt
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1293,7 +1297,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
   unsigned short* M = (unsigned short*)a.msg;
   const RowWalk rw = row_walk<NW>(a.n);
   for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+    const int e0 = a.row_ptr[i], e1 = a.row_end ? a.row_end[i] : a.row_ptr[i + 1];
     const unsigned short* hi = ht + (int64_t)i * NLM * C;
     // the row's features, transposed: sh[c][lm] (degrees NLM .. HT-1 zero)
 #pragma unroll

@@ -10,10 +10,13 @@
 // order), which turns "atoms with hop <= K - t" into the row prefix
 // [0, n_t) of the receiver CSR; the layer kernels then run over prefixes.
 //
+// Inside every row the edges whose neighbour is a root are put first, so the
+// sender-side last layer (only messages into roots matter) walks a prefix.
+//
 // Scratch: the per-row stencil blocks (dead once the list is built) hold the
 // old node arrays, hop classes and new indices; the rank-count arrays hold
 // the per-block class counts; the edge-gradient buffer stages the old edge
-// arrays.
+// arrays and the receiver array the new edge positions.
 #include "kernels.h"
 
 namespace mpip {
@@ -175,35 +178,56 @@ __global__ void k_save_vec(const int32_t* __restrict__ rp_o, int64_t n, int64_t 
   tmp[e] = e_vec[e];
 }
 
-// 16 lanes per old row: its edges move, in order, to the new row; senders
-// and reverse edges are renumbered (the reverse of an edge keeps its offset
-// within the sender's row)
-__global__ __launch_bounds__(256) void k_perm_edges(int64_t n, int64_t capacity, TrimScratch t,
-                                                    const int32_t* __restrict__ row_ptr, const int4* __restrict__ tmp,
-                                                    int32_t* __restrict__ e_src, uint32_t* __restrict__ e_shift,
-                                                    int32_t* __restrict__ e_rev) {
+// new position of every edge (epos), 16 lanes per old row: inside its new
+// row, the edges whose neighbour is a root come first, each group in the old
+// order; root_end[new row] = end of the root group.  The whole wave takes
+// part in every ballot (rows of one wave may differ in length).
+__global__ __launch_bounds__(256) void k_edge_pos(int64_t n, int64_t capacity, TrimScratch t,
+                                                  const int32_t* __restrict__ row_ptr, const int4* __restrict__ tmp,
+                                                  int32_t* __restrict__ epos, int32_t* __restrict__ root_end) {
   const int64_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
-  if (i >= n || (int64_t)t.rp_o[n] > capacity) return;
-  const int r0 = t.rp_o[i], r1 = t.rp_o[i + 1];
-  const int d0 = row_ptr[t.newidx[i]];
-  for (int e = r0 + (threadIdx.x & 15); e < r1; e += 16) {
-    const int4 v = tmp[e];
-    const int jn = t.newidx[v.x];
-    const int ed = d0 + (e - r0);
-    e_src[ed] = jn;
-    e_shift[ed] = (uint32_t)v.y;
-    e_rev[ed] = row_ptr[jn] + (v.z - t.rp_o[v.x]);
+  const int l16 = threadIdx.x & 15, seg = (threadIdx.x & 63) >> 4;
+  const bool ok = i < n && (int64_t)t.rp_o[n] <= capacity;
+  const int r0 = ok ? t.rp_o[i] : 0, len = ok ? t.rp_o[i + 1] - r0 : 0;
+  const int d0 = ok ? row_ptr[t.newidx[i]] : 0;
+  int nr = 0;
+  for (int k = l16; k < len; k += 16) nr += (t.hop[tmp[r0 + k].x] == 0) ? 1 : 0;
+  for (int off = 8; off > 0; off >>= 1) nr += __shfl_xor(nr, off, 16);
+  int top = len;
+  top = max(top, __shfl_xor(top, 16));
+  top = max(top, __shfl_xor(top, 32));
+  const unsigned lt = (1u << l16) - 1u;
+  int cr = 0, co = 0;
+  for (int b = 0; b < top; b += 16) {
+    const bool v = b + l16 < len;
+    const bool root = v && t.hop[tmp[r0 + b + l16].x] == 0;
+    const unsigned mr = (unsigned)(__ballot(root) >> (16 * seg)) & 0xffffu;
+    const unsigned mv = (unsigned)(__ballot(v) >> (16 * seg)) & 0xffffu;
+    if (v) epos[r0 + b + l16] = d0 + (root ? cr + __popc(mr & lt) : nr + co + __popc(mv & ~mr & lt));
+    cr += __popc(mr);
+    co += __popc(mv & ~mr);
   }
+  if (ok && l16 == 0) root_end[t.newidx[i]] = d0 + nr;
 }
 
-__global__ __launch_bounds__(256) void k_perm_vec(int64_t n, int64_t capacity, TrimScratch t,
-                                                  const int32_t* __restrict__ row_ptr, const float4* __restrict__ tmp,
-                                                  float4* __restrict__ e_vec) {
-  const int64_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
-  if (i >= n || (int64_t)t.rp_o[n] > capacity) return;
-  const int r0 = t.rp_o[i], r1 = t.rp_o[i + 1];
-  const int d0 = row_ptr[t.newidx[i]];
-  for (int e = r0 + (threadIdx.x & 15); e < r1; e += 16) e_vec[d0 + (e - r0)] = tmp[e];
+// every edge to its new slot; senders renumbered, reverse edges through epos
+__global__ void k_perm_edges(int64_t n, int64_t capacity, TrimScratch t, const int4* __restrict__ tmp,
+                             const int32_t* __restrict__ epos, int32_t* __restrict__ e_src,
+                             uint32_t* __restrict__ e_shift, int32_t* __restrict__ e_rev) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if ((int64_t)t.rp_o[n] > capacity || e >= t.rp_o[n]) return;
+  const int4 v = tmp[e];
+  const int ed = epos[e];
+  e_src[ed] = t.newidx[v.x];
+  e_shift[ed] = (uint32_t)v.y;
+  e_rev[ed] = v.z >= 0 ? epos[v.z] : -1;
+}
+
+__global__ void k_perm_vec(int64_t n, int64_t capacity, TrimScratch t, const float4* __restrict__ tmp,
+                           const int32_t* __restrict__ epos, float4* __restrict__ e_vec) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if ((int64_t)t.rp_o[n] > capacity || e >= t.rp_o[n]) return;
+  e_vec[epos[e]] = tmp[e];
 }
 
 __global__ void k_zero_edges_from(float4* __restrict__ g, const int32_t* __restrict__ row_ptr, int64_t row0, int64_t n,
@@ -246,10 +270,13 @@ void trim_permute(const NbrBuffers& b, int64_t n, int64_t capacity, float4* tmp,
   k_perm_nodes<<<g1, 256, 0, s>>>(n, t, b.pos_s, b.info_s, b.spec_s, b.owned_s, b.perm, b.inv_perm, b.cnt);
   exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
   if (ge == 0) return;
+  // epos in e_dst (rebuilt later where needed), root-group ends in cnt (the
+  // row lengths there are consumed by the scan above)
   k_save_edges<<<ge, 256, 0, s>>>(t.rp_o, n, capacity, b.e_src, b.e_shift, b.e_rev, (int4*)tmp);
-  k_perm_edges<<<gw, 256, 0, s>>>(n, capacity, t, b.row_ptr, (const int4*)tmp, b.e_src, b.e_shift, b.e_rev);
+  k_edge_pos<<<gw, 256, 0, s>>>(n, capacity, t, b.row_ptr, (const int4*)tmp, b.e_dst, b.cnt);
+  k_perm_edges<<<ge, 256, 0, s>>>(n, capacity, t, (const int4*)tmp, b.e_dst, b.e_src, b.e_shift, b.e_rev);
   k_save_vec<<<ge, 256, 0, s>>>(t.rp_o, n, capacity, b.e_vec, tmp);
-  k_perm_vec<<<gw, 256, 0, s>>>(n, capacity, t, b.row_ptr, tmp, b.e_vec);
+  k_perm_vec<<<ge, 256, 0, s>>>(n, capacity, t, tmp, b.e_dst, b.e_vec);
 }
 
 void zero_edges_from(float4* g, const int32_t* row_ptr, int64_t row0, int64_t n, int64_t capacity, hipStream_t s) {

@@ -56,8 +56,10 @@ void compact_list(const NbrBuffers& b, const NbrBuffers& sup, int64_t sup_cap, i
 // first row of each class in the class-sorted order, n, and 1 if the list is
 // unusable (then nothing may be permuted).  Needs n >= trim_min_atoms().
 const int64_t* trim_classes(const NbrBuffers& b, int64_t n, int K, int64_t capacity, hipStream_t s);
-// re-orders the rows (node arrays, CSR, senders, reverse edges) by class;
-// tmp: [capacity] float4 scratch
+// re-orders the rows (node arrays, CSR, senders, reverse edges) by class,
+// and inside every row puts the edges whose neighbour is a root first; the
+// end of that group per row is left in b.cnt.  tmp: [capacity] float4
+// scratch (b.e_dst is used as scratch too)
 void trim_permute(const NbrBuffers& b, int64_t n, int64_t capacity, float4* tmp, hipStream_t s);
 // g[e] = 0 for the edges of rows row0 .. n-1
 void zero_edges_from(float4* g, const int32_t* row_ptr, int64_t row0, int64_t n, int64_t capacity, hipStream_t s);
@@ -205,6 +207,10 @@ struct FastArgs {
   // -sum_e r_e (x) dE/dr_e equals -sum_e r_e (x) h_e: the outputs read g as
   // when both layers accumulate into it.  Otherwise both accumulate into g.
   float4* g2p;
+  // null, or per row the end of the edges whose receivers need the last
+  // layer (a trimmed share's rows list them first): the sender-side last
+  // layer (messages and fused adjoint) walks [row_ptr[i], row_end[i])
+  const int32_t* row_end;
 };
 
 void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s);
