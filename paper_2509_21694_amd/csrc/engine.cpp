@@ -928,6 +928,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         if (ht_bf16) {
           fa.n = R(K - 1);   // sender-side
           fa.row_end = root_end;
+          // the walked prefix gets its gradient slots written; the rest of
+          // those rows (receivers with dA = 0) must read as zero
+          if (root_end && fa.g2p) zero_row_tails(fa.g2p, b.row_ptr, root_end, R(K - 1), N, max_edges, s);
           launch_l2(prec, C, L, 3, fa, s);
           fa.row_end = nullptr;
         } else {

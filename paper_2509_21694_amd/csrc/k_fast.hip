@@ -1243,10 +1243,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }
       }
     }
-    // edges of the row past the walked prefix carry no gradient (their
-    // receivers have dA = 0); their slots are read by the outputs
-    if (a.g2p)
-      for (int e = e1 + lane; e < a.row_ptr[i + 1]; e += 64) a.g2p[e] = make_float4(0.f, 0.f, 0.f, 0.f);
     // htbar_i: D rows lm = 4g + r, column el of half tt = channel 32k + 2 el + tt
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

@@ -237,9 +237,23 @@ __global__ void k_zero_edges_from(float4* __restrict__ g, const int32_t* __restr
   g[e] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// g[e] = 0 for the edges past row_end[i] in rows i < n (16 lanes per row)
+__global__ __launch_bounds__(256) void k_zero_row_tails(float4* __restrict__ g, const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ row_end, int64_t n, int64_t rows_all,
+                                                        int64_t capacity) {
+  const int64_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
+  if (i >= n || (int64_t)row_ptr[rows_all] > capacity) return;
+  for (int e = row_end[i] + (threadIdx.x & 15); e < row_ptr[i + 1]; e += 16) g[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 }  // namespace
 
 int trim_max_layers() { return kMaxClass - 1; }
+
+void zero_row_tails(float4* g, const int32_t* row_ptr, const int32_t* row_end, int64_t n, int64_t rows_all,
+                    int64_t capacity, hipStream_t s) {
+  if (n > 0) k_zero_row_tails<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(g, row_ptr, row_end, n, rows_all, capacity);
+}
 
 void hop_sweep_launch(const NbrBuffers& b, int64_t n, int h, int64_t capacity, int32_t* hop, hipStream_t s) {
   k_hop_sweep<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(n, b.row_ptr, b.e_src, capacity, b.status, h, hop);

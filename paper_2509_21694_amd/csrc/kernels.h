@@ -64,6 +64,9 @@ void trim_permute(const NbrBuffers& b, int64_t n, int64_t capacity, float4* tmp,
 // g[e] = 0 for the edges of rows row0 .. n-1
 void zero_edges_from(float4* g, const int32_t* row_ptr, int64_t row0, int64_t n, int64_t capacity, hipStream_t s);
 int trim_max_layers();
+// g[e] = 0 for the edges of rows i < n past row_end[i] (rows_all: rows of the list)
+void zero_row_tails(float4* g, const int32_t* row_ptr, const int32_t* row_end, int64_t n, int64_t rows_all,
+                    int64_t capacity, hipStream_t s);
 // one breadth-first level: neighbours of rows at hop h get min(hop, h + 1)
 void hop_sweep_launch(const NbrBuffers& b, int64_t n, int h, int64_t capacity, int32_t* hop, hipStream_t s);
 constexpr int64_t trim_min_atoms() { return 64; }
