@@ -533,15 +533,18 @@ __global__ void k_check_capacity(const int32_t* __restrict__ row_ptr, int64_t n,
   }
 }
 
-// reverse edge of e = (i, j, S) is (j, i, -S) in row j; one wave per row i,
-// one lane per edge of the row (rows longer than 64 loop)
+// Reverse edges, one search per pair: of the two edges (i, j, S) and
+// (j, i, -S), the one whose sender index is larger (for an atom's own image,
+// the one whose first nonzero shift component is positive) finds its partner
+// in the sender's row and writes both entries (e_rev starts at -1).  16
+// lanes per row.
 __global__ __launch_bounds__(256) void k_nbr_rev(int64_t n, const int32_t* __restrict__ row_ptr,
                                                  const int32_t* __restrict__ e_src,
                                                  const uint32_t* __restrict__ e_shift, const int4* __restrict__ info_s,
                                                  const GridParams* __restrict__ gp, const int32_t* __restrict__ blk,
                                                  int64_t capacity, int32_t* __restrict__ e_rev) {
-  const int64_t i = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int l16 = threadIdx.x & 15;
   if (i >= n) return;
   if (row_ptr[n] > capacity) return;
   const GridParams g = *gp;
@@ -551,10 +554,12 @@ __global__ __launch_bounds__(256) void k_nbr_rev(int64_t n, const int32_t* __res
     const int bin = info_s[i].w;
     bi[0] = bin % g.nb[0]; bi[1] = (bin / g.nb[0]) % g.nb[1]; bi[2] = bin / (g.nb[0] * g.nb[1]);
   }
-  for (int e = row_ptr[i] + lane; e < row_ptr[i + 1]; e += 64) {
+  for (int e = row_ptr[i] + l16; e < row_ptr[i + 1]; e += 16) {
     const int j = e_src[e];
     const uint32_t sh = e_shift[e];
     const int S0 = (int8_t)(sh & 0xff), S1 = (int8_t)((sh >> 8) & 0xff), S2 = (int8_t)((sh >> 16) & 0xff);
+    const bool owner = (j != (int)i) ? (j > (int)i) : (S0 != 0 ? S0 > 0 : (S1 != 0 ? S1 > 0 : S2 > 0));
+    if (!owner) continue;
     const uint32_t want = (uint32_t)((-S0) & 0xff) | ((uint32_t)((-S1) & 0xff) << 8) | ((uint32_t)((-S2) & 0xff) << 16);
     int f0 = row_ptr[j], f1 = row_ptr[j + 1];
     if (stencil3) {
@@ -576,6 +581,7 @@ __global__ __launch_bounds__(256) void k_nbr_rev(int64_t n, const int32_t* __res
     for (int f = f0; f < f1; ++f)
       if (e_src[f] == (int)i && e_shift[f] == want) { r = f; break; }
     e_rev[e] = r;
+    if (r >= 0) e_rev[r] = e;
   }
 }
 
@@ -750,8 +756,9 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
                                    b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.status);
   k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
-  k_nbr_rev<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.info_s, b.grid, b.blk,
-                                                     capacity, b.e_rev);
+  hipMemsetAsync(b.e_rev, 0xff, sizeof(int32_t) * (size_t)capacity, s);
+  k_nbr_rev<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.info_s, b.grid, b.blk,
+                                                       capacity, b.e_rev);
 }
 
 // receiver of every edge, one wave per row
