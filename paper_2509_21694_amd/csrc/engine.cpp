@@ -479,7 +479,7 @@ namespace {
 struct Plan {
   size_t total = 0;
   size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_rcount, o_rstart, o_scan, o_info, o_perm, o_iperm, o_pos,
-      o_info_s, o_spec, o_owned, o_cnt, o_row, o_blk, o_esrc, o_eshift, o_evec, o_erev, o_edst, o_g;
+      o_info_s, o_spec, o_owned, o_cnt, o_row, o_blk, o_cmask, o_esrc, o_eshift, o_evec, o_erev, o_edst, o_g;
   size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
   size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
   size_t o_msg = 0; // last-layer messages of the BF16 form, [max_edges][C] bf16
@@ -517,6 +517,7 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
   p.o_cnt = take(cur, sizeof(int32_t) * N);
   p.o_row = take(cur, sizeof(int32_t) * (N + 1));
   p.o_blk = take(cur, sizeof(int32_t) * 28 * N);
+  p.o_cmask = take(cur, sizeof(uint64_t) * kCandWords * N);
   p.o_esrc = take(cur, sizeof(int32_t) * cap);
   p.o_eshift = take(cur, sizeof(uint32_t) * cap);
   p.o_evec = take(cur, sizeof(float4) * cap);
@@ -591,6 +592,7 @@ NbrBuffers nbr_buffers(char* ws, const Plan& p) {
   b.cnt = (int32_t*)(ws + p.o_cnt);
   b.row_ptr = (int32_t*)(ws + p.o_row);
   b.blk = (int32_t*)(ws + p.o_blk);
+  b.cmask = (uint64_t*)(ws + p.o_cmask);
   b.e_src = (int32_t*)(ws + p.o_esrc);
   b.e_shift = (uint32_t*)(ws + p.o_eshift);
   b.e_vec = (float4*)(ws + p.o_evec);

@@ -91,7 +91,7 @@ int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; 
 void exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s) {
   int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 0) {
-    hipMemsetAsync(out, 0, sizeof(int32_t), s);
+    (void)hipMemsetAsync(out, 0, sizeof(int32_t), s);
     return;
   }
   k_scan_partials<<<nb, kScanBlock, 0, s>>>(in, n, tmp);
@@ -410,6 +410,24 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
 // predicate, and the passing ones are compacted with a ballot so each row
 // is written contiguously.  Edge order (stencil block, then bin order) and
 // the per-block offsets blk are those of k_nbr.
+// position of the r-th (from 0) set bit of x; x has more than r set bits
+__device__ __forceinline__ int nth_set_bit(unsigned long long x, int r) {
+  int pos = 0;
+#pragma unroll
+  for (int sh = 32; sh > 0; sh >>= 1) {
+    const unsigned long long lo = x & ((1ull << sh) - 1ull);
+    const int c = __popcll(lo);
+    if (r >= c) {
+      r -= c;
+      x >>= sh;
+      pos += sh;
+    } else {
+      x = lo;
+    }
+  }
+  return pos;
+}
+
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restrict__ pos_s,
                                                const int4* __restrict__ info_s, const int32_t* __restrict__ spec_s,
@@ -419,7 +437,7 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
                                                int32_t* __restrict__ cnt, const int32_t* __restrict__ row_ptr,
                                                int64_t capacity, int32_t* __restrict__ e_src,
                                                uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec,
-                                               int64_t* __restrict__ status) {
+                                               uint64_t* __restrict__ cmask, int64_t* __restrict__ status) {
   __shared__ int sPre[4][28], sStart[4][27], sShift[4][27], sCnt[4][27];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = blockIdx.x * 4 + wv;
@@ -473,6 +491,69 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
   const double rc2 = ci.rc * ci.rc;
   const int64_t out = FILL ? row_ptr[i] : 0;
   int count = 0, coincident = 0;
+  // candidate f: stencil block k (last with pre[k] <= f; empty bins share the
+  // prefix of the next one), atom j, shift S; pass / dx from the FP64 test
+  auto candidate = [&](int f, int& j, int& k, int* S, double* dx) -> bool {
+    k = 0;
+#pragma unroll
+    for (int step = 16; step > 0; step >>= 1)
+      if (k + step < 27 && sPre[wv][k + step] <= f) k += step;
+    j = sStart[wv][k] + (f - sPre[wv][k]);
+    const int sc = sShift[wv][k];
+    const int Sp[3] = {(sc & 3) - 1, ((sc >> 2) & 3) - 1, ((sc >> 4) & 3) - 1};
+    const int4 oj = info_s[j];
+    S[0] = ci.pbc[0] ? Sp[0] - oj.x + me.x : 0;
+    S[1] = ci.pbc[1] ? Sp[1] - oj.y + me.y : 0;
+    S[2] = ci.pbc[2] ? Sp[2] - oj.z + me.z : 0;
+    if (j == i && S[0] == 0 && S[1] == 0 && S[2] == 0) return false;
+    const double xj[3] = {pos_s[3 * (int64_t)j], pos_s[3 * (int64_t)j + 1], pos_s[3 * (int64_t)j + 2]};
+    return pair_test(xi, xj, ci, S[0], S[1], S[2], rc2, dx);
+  };
+  if (FILL && total <= 64 * kCandWords) {
+    // the counting pass kept which candidates passed: lane q takes the q-th
+    // passing candidate (ascending f, the order of the full scan) and only
+    // the passing pairs are evaluated again (for their FP64 difference)
+    const int nw = (total + 63) >> 6;
+    const unsigned long long mine = lane < nw ? cmask[(int64_t)i * kCandWords + lane] : 0ull;
+    int incl = __popcll(mine);
+#pragma unroll
+    for (int o = 1; o < kCandWords; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    unsigned long long wd[kCandWords];
+    int ex[kCandWords];
+#pragma unroll
+    for (int t = 0; t < kCandWords; ++t) {
+      wd[t] = __shfl(mine, t);
+      ex[t] = __shfl(incl, t) - __popcll(wd[t]);
+    }
+    const int npass = __shfl(incl, kCandWords - 1);
+    for (int q0 = 0; q0 < npass; q0 += 64) {
+      const int q = q0 + lane;
+      bool pass = false;
+      int j = 0, k = 0, S[3] = {0, 0, 0};
+      double dx[3] = {0.0, 0.0, 0.0};
+      if (q < npass) {
+        int w = 0;
+        unsigned long long word = wd[0];
+        int rank = q - ex[0];
+#pragma unroll
+        for (int t = 1; t < kCandWords; ++t)
+          if (t < nw && ex[t] <= q) { w = t; word = wd[t]; rank = q - ex[t]; }
+        pass = candidate(64 * w + nth_set_bit(word, rank), j, k, S, dx);
+        if (pass && dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+      }
+      if (pass) {
+        const int64_t eidx = out + q;
+        e_src[eidx] = j;
+        e_shift[eidx] = (uint32_t)(S[0] & 0xff) | ((uint32_t)(S[1] & 0xff) << 8) | ((uint32_t)(S[2] & 0xff) << 16);
+        e_vec[eidx] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], __int_as_float(spec_s[j]));
+        atomicAdd(&sCnt[wv][k], 1);
+      }
+    }
+    count = npass;
+  } else
   for (int base = 0; base < total; base += 64) {
     const int f = base + lane;
     bool pass = false;
@@ -497,6 +578,7 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
       }
     }
     const unsigned long long m = __ballot(pass);
+    if (!FILL && lane == 0 && (base >> 6) < kCandWords) cmask[(int64_t)i * kCandWords + (base >> 6)] = m;
     if (FILL && pass) {
       const int64_t eidx = out + count + __popcll(m & ((1ull << lane) - 1ull));
       e_src[eidx] = j;
@@ -729,13 +811,13 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   if (nparts > kBoundsParts) nparts = kBoundsParts;
   k_bounds<<<nparts, 256, 0, s>>>(sys.positions, sys.species, n, ci.n_species, b.bounds, b.status);
   k_grid<<<1, 64, 0, s>>>(b.bounds, nparts, ci, b.max_bins, b.grid, b.status);
-  hipMemsetAsync(b.bin_count, 0, sizeof(int32_t) * (b.max_bins + 1), s);
-  hipMemsetAsync(b.bin_cursor, 0, sizeof(int32_t) * (b.max_bins + 1), s);
+  (void)hipMemsetAsync(b.bin_count, 0, sizeof(int32_t) * (b.max_bins + 1), s);
+  (void)hipMemsetAsync(b.bin_cursor, 0, sizeof(int32_t) * (b.max_bins + 1), s);
   const int ga = (int)((n + nblk - 1) / nblk);
   k_bin_assign<<<ga, nblk, 0, s>>>(sys.positions, n, ci, b.grid, b.info, b.bin_count);
   // bins laid out along a Morton curve: counts in rank order, scan, back to bins
   const int64_t nr = 8 * (int64_t)b.max_bins;
-  hipMemsetAsync(b.rank_count, 0, sizeof(int32_t) * (nr + 1), s);
+  (void)hipMemsetAsync(b.rank_count, 0, sizeof(int32_t) * (nr + 1), s);
   const unsigned gb = (unsigned)((b.max_bins + 255) / 256);
   k_rank_count<<<gb, 256, 0, s>>>(b.grid, b.bin_count, b.rank_count);
   exclusive_scan(b.rank_count, nr, b.rank_start, b.scan_tmp, s);
@@ -747,16 +829,16 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   // one of each pair does the work: k_nbr_w when all dimensions use the 27-bin stencil, else k_nbr
   const unsigned gw = (unsigned)((n + 3) / 4);
   k_nbr_w<false><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt,
-                                    nullptr, capacity, nullptr, nullptr, nullptr, b.status);
+                                    nullptr, capacity, nullptr, nullptr, nullptr, b.cmask, b.status);
   k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt, nullptr,
                                    capacity, nullptr, nullptr, nullptr, b.status);
   exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
   k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
   k_nbr_w<true><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr,
-                                   b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.status);
+                                   b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.cmask, b.status);
   k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
-  hipMemsetAsync(b.e_rev, 0xff, sizeof(int32_t) * (size_t)capacity, s);
+  (void)hipMemsetAsync(b.e_rev, 0xff, sizeof(int32_t) * (size_t)capacity, s);
   k_nbr_rev<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.info_s, b.grid, b.blk,
                                                        capacity, b.e_rev);
 }
