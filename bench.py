@@ -15,6 +15,11 @@ the FP64 oracle (at atoms whose oracle forces are exact, from a local
 cluster) are extra fields.  `roofline` is for the kernel with the largest
 share of the step (HIP-event durations from the timed steps);
 `cpu_baseline` times the FP64 oracle on a bounded cluster of the same box.
+Extra fields: `md` (on-device MD steps with neighbour-list reuse),
+`depth_pruning` (a 13,824-atom box, one 6-layer weight set run to K = 6
+and to K = 2) and `partitioned` (a whole 8,000,000-atom box evaluated as 8
+slab partitions one after the other, geometric and graph halos, with the
+halo growth against depth).
 """
 from __future__ import annotations
 
@@ -185,6 +190,8 @@ def main():
                          "traffic for scaling hardware byte counters)")
     ap.add_argument("--md-steps", type=int, default=10,
                     help="also time this many on-device MD steps (first precision; 0: skip)")
+    ap.add_argument("--depth-steps", type=int, default=5,
+                    help="also time the 13,824-atom box at K=6 and K=2 of one 6-layer weight set (0: skip)")
     ap.add_argument("--partitioned-steps", type=int, default=2,
                     help="also time this many evaluations of the 8M-atom box as 8 slab partitions (0: skip)")
     args = ap.parse_args()
@@ -287,6 +294,33 @@ def main():
               "us_per_atom_step": round(md_ms * 1e3 / N, 6), "ms_per_step": round(md_ms, 4),
               "steps": args.md_steps, "dtype": head,
               "energy_drift_per_atom": float(np.abs(et - et[0]).max() / N)}
+    depth = None
+    if args.depth_steps > 0:
+        # message-passing depth pruning: the same 6-layer weight set evaluated
+        # to K = 6 and truncated to K = 2 (13,824-atom box, l_max = 2, C = 64)
+        sd, hpd = W.mpdp_system(), W.HP_MPDP
+        modeld = M.Model(hpd, W.make_weights(hpd, W.WEIGHT_SEEDS["mpdp"]))
+        pd = torch.tensor(sd.positions, dtype=torch.float64, device=dev)
+        spd = torch.tensor(sd.species, dtype=torch.int32, device=dev)
+        depth = {"metric": "ms per E+F evaluation of a 13,824-atom box, one 6-layer weight set run to K layers",
+                 "n_atoms": sd.n_atoms, "steps": args.depth_steps}
+        for prec in precs:
+            row = {}
+            for Kd in (6, 2):
+                o = modeld.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec)
+                cap = int(o["n_edges"] * 1.02) + 4096
+                modeld.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec, max_edges=cap, out=o, check=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.depth_steps):
+                    modeld.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec, max_edges=cap, out=o,
+                                    check=False)
+                torch.cuda.synchronize()
+                row[f"K{Kd}_ms"] = round((time.perf_counter() - t0) / args.depth_steps * 1e3, 3)
+            row["K6_over_K2"] = round(row["K6_ms"] / row["K2_ms"], 2)
+            depth[prec] = row
+            log(f"depth pruning ({prec}): K=6 {row['K6_ms']} ms, K=2 {row['K2_ms']} ms")
+        del modeld, pd, spd
     part = None
     if args.partitioned_steps > 0:
         # one-GPU partitioned mode: the whole 200^3 box in 8 slabs along x,
@@ -352,6 +386,7 @@ def main():
             "cpu_baseline": base or None,
             "forms": results,
             "md": md,
+            "depth_pruning": depth,
             "partitioned": part}
     if "bf16" in results and "fp32" in results:
         line["bf16_speedup_over_fp32"] = round(results["fp32"]["ms_per_step"] / results["bf16"]["ms_per_step"], 3)
