@@ -483,6 +483,7 @@ struct Plan {
   size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
   size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
   size_t o_msg = 0; // last-layer messages of the BF16 form, [max_edges][C] bf16
+  size_t o_part = 0; // middle-layer adjoint: per-edge sums between its launches, [max_edges][kPartStride]
   std::vector<size_t> o_ht, o_z0, o_zl;  // per layer 1..K (index t-1)
   int max_bins;
   int nblocks_out;
@@ -539,6 +540,7 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
     if ((C == 64 || C == 128) && S * nlm <= 64 && K >= 2)
       p.o_qp = take(cur, sizeof(float) * N * nlm * 64 * S);
     if ((C == 64 || C == 128) && K >= 2) p.o_msg = take(cur, sizeof(uint16_t) * cap * C);
+    if (K >= 3) p.o_part = take(cur, sizeof(float) * kPartStride * cap);
     p.o_atom_e = take(cur, sizeof(double) * N);
     p.nblocks_out = (int)((N + 255) / 256);
     p.o_partials = take(cur, sizeof(double) * 10 * p.nblocks_out);
@@ -704,6 +706,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   ea.envelope_p = hp.envelope_p;
   ea.g = g;
   ea.htbar = htbar;
+  ea.part = p.o_part ? (float*)(w + p.o_part) : nullptr;
 
   NodeArgs na;
   na.n = N; na.C = C; na.L = L; na.nlm = nlm;

@@ -133,7 +133,14 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
 
 // ------------------------------------------------------------ backward
 
-template <int PREC, int C, int L, int KIND, bool HTBAR>
+// PG >= 0 (middle layers): only the paths with input degree l1 = PG, one
+// launch per degree in increasing order.  All paths in one kernel need more
+// registers than a wave has (about 40 per path stay live), so the launches
+// hand the two per-edge sums over paths (the MLP adjoint's input and dE/dY)
+// on through a.part; the last launch (PG = L) finishes the edge gradient.
+// Each launch writes only its own degree's block of htbar.  PG = -1: all
+// paths in one launch.
+template <int PREC, int C, int L, int KIND, bool HTBAR, int PG = -1>
 __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
   typedef PathList<L, KIND> PL;
   typedef Op<PREC> O;
@@ -145,6 +152,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
   constexpr int EPL = 64 / CW;
   constexpr int RS = C + 1;
   constexpr bool SPECIES_IN = (KIND == KIND_ONLY || KIND == KIND_FIRST);
+  constexpr bool FROM_PART = PG > 0, TO_PART = PG >= 0 && PG < L;
   __shared__ float sR[kTileE * RS];
   __shared__ float sRb[kTileE * RS];
   __shared__ float syc[kTileE * NYC];
@@ -182,6 +190,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         static_for<NP>([&](auto PI) {
           constexpr int pi = decltype(PI)::value;
           constexpr P3 pp = PL::get(pi);
+          if constexpr (PG >= 0 && pp.l1 != PG) return;
           constexpr int n1 = 2 * pp.l1 + 1, n2 = 2 * pp.l2 + 1, n3 = 2 * pp.l3 + 1;
           const float* cg = opaque_ptr(a.cg + PL::cg_off(pi));
 #pragma unroll
@@ -204,9 +213,22 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
       float Ybar[kMaxNlm];
 #pragma unroll
       for (int k = 0; k < kMaxNlm; ++k) Ybar[k] = 0.f;
+      // the sums over the earlier launches' paths (edge el; ab2 row 16 mt + 4 g + r)
+      float* pe = (PG >= 0) ? a.part + (int64_t)(valid ? e : 0) * kPartStride : nullptr;
+      if constexpr (FROM_PART) {
+        if (valid) {
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ab2[mt][r] = pe[16 * mt + 4 * g + r];
+#pragma unroll
+          for (int k = 0; k < NLM; ++k) Ybar[k] = pe[64 + k];
+        }
+      }
       static_for<NP>([&](auto PI) {
         constexpr int pi = decltype(PI)::value;
         constexpr P3 pp = PL::get(pi);
+        if constexpr (PG >= 0 && pp.l1 != PG) return;
         constexpr int n1 = 2 * pp.l1 + 1, n2 = 2 * pp.l2 + 1, n3 = 2 * pp.l3 + 1;
         constexpr int ob = (NOUT == 1) ? 0 : pp.l3 * pp.l3;
         constexpr float sgn = (pp.l2 & 1) ? -1.f : 1.f;
@@ -310,6 +332,19 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
                              O::from_row(sRb + el * RS, kc, g), ab2[mt]);
         }
       });
+      if constexpr (TO_PART) {
+        if (valid) {
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pe[16 * mt + 4 * g + r] = ab2[mt][r];
+          if (g == 0) {
+#pragma unroll
+            for (int k = 0; k < NLM; ++k) pe[64 + k] = Ybar[k];
+          }
+        }
+        continue;
+      }
       // remaining MLP backward: silu'(p2) -> W2 -> silu'(p1) -> W1
       f32x4 pb2[4], pb1[4];
 #pragma unroll
@@ -357,6 +392,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
       for (int o = 0; o < NIN; ++o)
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
+          if (PG >= 0 && (o < PG * PG || o >= (PG + 1) * (PG + 1))) continue;
           float vv = hb[o][k];
           if constexpr (EPL == 2) vv += __shfl_down(vv, 32);
           if (eg == 0) a.htbar[((int64_t)i * NIN + o) * C + cl + k * CW] = vv;
@@ -389,7 +425,12 @@ static void bwd_kind(int kind, const EdgeArgs& a, hipStream_t s) {
   switch (kind) {
     case KIND_ONLY: k_edge_bwd<PREC, C, L, KIND_ONLY, false><<<gr, 64, 0, s>>>(a); break;
     case KIND_FIRST: k_edge_bwd<PREC, C, L, KIND_FIRST, false><<<gr, 64, 0, s>>>(a); break;
-    case KIND_MID: k_edge_bwd<PREC, C, L, KIND_MID, true><<<gr, 64, 0, s>>>(a); break;
+    case KIND_MID:
+      // one launch per input degree (see k_edge_bwd)
+      k_edge_bwd<PREC, C, L, KIND_MID, true, 0><<<gr, 64, 0, s>>>(a);
+      k_edge_bwd<PREC, C, L, KIND_MID, true, 1><<<gr, 64, 0, s>>>(a);
+      if constexpr (L >= 2) k_edge_bwd<PREC, C, L, KIND_MID, true, 2><<<gr, 64, 0, s>>>(a);
+      break;
     default: k_edge_bwd<PREC, C, L, KIND_LAST, true><<<gr, 64, 0, s>>>(a); break;
   }
 }

@@ -248,7 +248,9 @@ struct EdgeArgs {
   const float* Abar;       // backward input [N][nlm_out][C] (scaled by inv_n in-kernel)
   float* htbar;            // backward output [N][nlm][C] (t >= 2)
   float4* g;               // backward: dE/dr_e accumulated over layers [cap]
+  float* part;             // middle-layer adjoint: per-edge sums handed between launches [cap][kPartStride]
 };
+constexpr int kPartStride = 80;   // 64 MLP-adjoint inputs + up to 16 dE/dY
 
 void launch_edge_fwd(int prec, int C, int L, int kind, const EdgeArgs& a, hipStream_t s);
 void launch_edge_bwd(int prec, int C, int L, int kind, const EdgeArgs& a, hipStream_t s);
