@@ -133,14 +133,15 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
 
 // ------------------------------------------------------------ backward
 
-// PG >= 0 (middle layers): only the paths with input degree l1 = PG, one
-// launch per degree in increasing order.  All paths in one kernel need more
-// registers than a wave has (about 40 per path stay live), so the launches
-// hand the two per-edge sums over paths (the MLP adjoint's input and dE/dY)
-// on through a.part; the last launch (PG = L) finishes the edge gradient.
-// Each launch writes only its own degree's block of htbar.  PG = -1: all
-// paths in one launch.
-template <int PREC, int C, int L, int KIND, bool HTBAR, int PG = -1>
+// Paths [P0, P1) of the layer's path list (sorted by input degree l1), one
+// launch per range in increasing order.  All paths of a middle layer in one
+// kernel need more registers than a wave has (about 40 per path stay live),
+// so the launches hand the two per-edge sums over paths (the MLP adjoint's
+// input and dE/dY) on through a.part, and the last launch finishes the edge
+// gradient (FIN; it may have no paths of its own).  A launch writes the
+// htbar blocks of its paths' degrees, adding to a block an earlier launch
+// began.  Default: all paths in one launch.
+template <int PREC, int C, int L, int KIND, bool HTBAR, int P0 = 0, int P1 = 64, bool FIN = true>
 __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
   typedef PathList<L, KIND> PL;
   typedef Op<PREC> O;
@@ -152,7 +153,14 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
   constexpr int EPL = 64 / CW;
   constexpr int RS = C + 1;
   constexpr bool SPECIES_IN = (KIND == KIND_ONLY || KIND == KIND_FIRST);
-  constexpr bool FROM_PART = PG > 0, TO_PART = PG >= 0 && PG < L;
+  constexpr int PE = P1 < NP ? P1 : NP;
+  constexpr bool FROM_PART = P0 > 0, TO_PART = !FIN;
+  // first path of each input degree: a launch starting after it adds to its block
+  constexpr auto first_of = [](int l1) {
+    for (int k = 0; k < PL::count(); ++k)
+      if (PL::get(k).l1 == l1) return k;
+    return PL::count();
+  };
   __shared__ float sR[kTileE * RS];
   __shared__ float sRb[kTileE * RS];
   __shared__ float syc[kTileE * NYC];
@@ -190,7 +198,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
         static_for<NP>([&](auto PI) {
           constexpr int pi = decltype(PI)::value;
           constexpr P3 pp = PL::get(pi);
-          if constexpr (PG >= 0 && pp.l1 != PG) return;
+          if constexpr (pi < P0 || pi >= PE) return;
           constexpr int n1 = 2 * pp.l1 + 1, n2 = 2 * pp.l2 + 1, n3 = 2 * pp.l3 + 1;
           const float* cg = opaque_ptr(a.cg + PL::cg_off(pi));
 #pragma unroll
@@ -214,7 +222,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
 #pragma unroll
       for (int k = 0; k < kMaxNlm; ++k) Ybar[k] = 0.f;
       // the sums over the earlier launches' paths (edge el; ab2 row 16 mt + 4 g + r)
-      float* pe = (PG >= 0) ? a.part + (int64_t)(valid ? e : 0) * kPartStride : nullptr;
+      float* pe = (FROM_PART || TO_PART) ? a.part + (int64_t)(valid ? e : 0) * kPartStride : nullptr;
       if constexpr (FROM_PART) {
         if (valid) {
 #pragma unroll
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
       static_for<NP>([&](auto PI) {
         constexpr int pi = decltype(PI)::value;
         constexpr P3 pp = PL::get(pi);
-        if constexpr (PG >= 0 && pp.l1 != PG) return;
+        if constexpr (pi < P0 || pi >= PE) return;
         constexpr int n1 = 2 * pp.l1 + 1, n2 = 2 * pp.l2 + 1, n3 = 2 * pp.l3 + 1;
         constexpr int ob = (NOUT == 1) ? 0 : pp.l3 * pp.l3;
         constexpr float sgn = (pp.l2 & 1) ? -1.f : 1.f;
@@ -392,10 +400,16 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
       for (int o = 0; o < NIN; ++o)
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          if (PG >= 0 && (o < PG * PG || o >= (PG + 1) * (PG + 1))) continue;
+          const int lo = o < 1 ? 0 : (o < 4 ? 1 : 2);      // input degree of row o
+          const int f = first_of(lo);
+          // blocks of degrees with no path in this launch are left alone
+          bool mine = false;
+          for (int q = P0; q < PE; ++q) mine = mine || PL::get(q).l1 == lo;
+          if ((P0 > 0 || PE < NP) && !mine) continue;
           float vv = hb[o][k];
           if constexpr (EPL == 2) vv += __shfl_down(vv, 32);
-          if (eg == 0) a.htbar[((int64_t)i * NIN + o) * C + cl + k * CW] = vv;
+          float* dst = a.htbar + ((int64_t)i * NIN + o) * C + cl + k * CW;
+          if (eg == 0) *dst = (f < P0) ? *dst + vv : vv;
         }
     }
   }
@@ -426,10 +440,21 @@ static void bwd_kind(int kind, const EdgeArgs& a, hipStream_t s) {
     case KIND_ONLY: k_edge_bwd<PREC, C, L, KIND_ONLY, false><<<gr, 64, 0, s>>>(a); break;
     case KIND_FIRST: k_edge_bwd<PREC, C, L, KIND_FIRST, false><<<gr, 64, 0, s>>>(a); break;
     case KIND_MID:
-      // one launch per input degree (see k_edge_bwd)
-      k_edge_bwd<PREC, C, L, KIND_MID, true, 0><<<gr, 64, 0, s>>>(a);
-      k_edge_bwd<PREC, C, L, KIND_MID, true, 1><<<gr, 64, 0, s>>>(a);
-      if constexpr (L >= 2) k_edge_bwd<PREC, C, L, KIND_MID, true, 2><<<gr, 64, 0, s>>>(a);
+      // a few paths per launch (see k_edge_bwd); path order (l1, l2, l3):
+      // l_max = 2: 000 011 022 | 101 110 | 112 121 | 202 211 | 220 | 222 | finish
+      // l_max = 1: 000 011 | 101 110 (finishes)
+      if constexpr (L >= 2) {
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 0, 3, false><<<gr, 64, 0, s>>>(a);
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 3, 5, false><<<gr, 64, 0, s>>>(a);
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 5, 7, false><<<gr, 64, 0, s>>>(a);
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 7, 9, false><<<gr, 64, 0, s>>>(a);
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 9, 10, false><<<gr, 64, 0, s>>>(a);
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 10, 11, false><<<gr, 64, 0, s>>>(a);
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 11, 11, true><<<gr, 64, 0, s>>>(a);
+      } else {
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 0, 2, false><<<gr, 64, 0, s>>>(a);
+        k_edge_bwd<PREC, C, L, KIND_MID, true, 2, 4, true><<<gr, 64, 0, s>>>(a);
+      }
       break;
     default: k_edge_bwd<PREC, C, L, KIND_LAST, true><<<gr, 64, 0, s>>>(a); break;
   }
