@@ -1273,7 +1273,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 // written in BF16 to the receiver-side slot M[rev(e')] in row i of the CSR.
 // A_i = sum_{e in row i} m_e / n_avg is then a contiguous segmented sum.
 template <int C, int L, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void k_l2_msg(FastArgs a) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4))) void k_l2_msg(FastArgs a) {
   typedef Op<1> O;
   constexpr int NLM = (L + 1) * (L + 1);
   constexpr int NK = C / 32, CN = C / 16;
@@ -1481,7 +1481,7 @@ static void l2_launch(int which, const FastArgs& a, hipStream_t s) {
   else if (which == 2) k_l2_bwd_b<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
   else if constexpr (PREC == 1) {
     if (which == 3) k_l2_adj<C, L, 8><<<l2_grid(a.n, 8, 32), 64 * 8, 0, s>>>(a);
-    else if (which == 4) k_l2_msg<C, L, 12><<<l2_grid(a.n, 12, C == 128 ? 32 : 64), 64 * 12, 0, s>>>(a);
+    else if (which == 4) k_l2_msg<C, L, 16><<<l2_grid(a.n, 16, C == 128 ? 32 : 64), 64 * 16, 0, s>>>(a);
     else k_l2_msum<C><<<(unsigned)((a.n + 3) / 4), 256, 0, s>>>(a);
   }
 }
