@@ -41,7 +41,11 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
   constexpr int NP = PL::count();
   constexpr int NIN = PL::nin(), NOUT = PL::nout(), NYC = PL::nyc();
   constexpr int NLM = (L + 1) * (L + 1);
-  constexpr int CW = C < 64 ? C : 64;      // lanes per edge group
+  // BF16 form: 16 lanes per edge group, 4 edges of the tile in flight, each
+  // lane holding C/16 channels (16 lanes read 64 contiguous bytes of a
+  // sender's row); the FP32 form (more registers per channel) keeps one or
+  // two edges at a time
+  constexpr int CW = PREC == 1 ? 16 : (C < 64 ? C : 64);   // lanes per edge group
   constexpr int CPL = C / CW;              // channels per lane
   constexpr int EPL = 64 / CW;             // edge groups
   constexpr int RS = C + 1;
@@ -125,7 +129,8 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
 #pragma unroll
       for (int k = 0; k < CPL; ++k) {
         float vv = acc[o][k];
-        if constexpr (EPL == 2) vv += __shfl_down(vv, 32);
+#pragma unroll
+        for (int off = 32; off >= CW; off >>= 1) vv += __shfl_xor(vv, off);
         if (eg == 0) a.A[((int64_t)i * NOUT + o) * C + cl + k * CW] = a.inv_n * vv;
       }
   }
