@@ -82,7 +82,7 @@ def compare(o, ref, n, prec, label, volume, n_owned=None):
 
 # ----------------------------------------------------------- neighbour list
 
-NBR_CASES = ["small", "mpdp", "slab_pbc011", "thin_cell", "unwrapped", "cluster"]
+NBR_CASES = ["small", "mpdp", "slab_pbc011", "thin_cell", "unwrapped", "cluster", "dense", "three_bins"]
 
 
 def nbr_case(name):
@@ -107,6 +107,19 @@ def nbr_case(name):
     if name == "cluster":
         rng = np.random.default_rng(7)
         return rng.uniform(0, 14, (300, 3)), np.eye(3) * 14, np.array([False, False, False])
+    if name == "dense":
+        # 0.41 atoms/A^3: about 1,700 candidates per atom in the 27 bins, more
+        # than the counting pass keeps masks for, so the fill tests them again
+        a = 1.35
+        pos = W.lattice_positions(12, 12, 12, a, 8, jitter=0.05)
+        return pos, np.eye(3) * 12 * a, np.array([True, True, True])
+    if name == "three_bins":
+        # 0.15 atoms/A^3 in three 5 A bins per direction: about 500 candidates
+        # per atom (on both sides of the kept-mask limit) and about 78
+        # neighbours, more than one 64-lane round of the fill
+        a = 1.8825
+        pos = W.lattice_positions(8, 8, 8, a, 9, jitter=0.1)
+        return pos, np.eye(3) * 8 * a, np.array([True, True, True])
     raise KeyError(name)
 
 
