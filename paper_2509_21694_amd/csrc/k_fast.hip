@@ -1442,9 +1442,9 @@ static int l2_grid(int64_t n, int nw, int per_xcd) {
 
 template <int PREC, int L>
 static void l1_launch(bool fwd, int mq, const FastArgs& a, hipStream_t s) {
-  // 4 waves per workgroup; forward 3 waves per SIMD, adjoint 2
+  // 4 waves per workgroup; forward 4 waves per SIMD, adjoint 2
   constexpr int NW = 4;
-  const int gf = l2_grid(a.n, NW, PREC == 1 ? 96 : 128), gb = l2_grid(a.n, NW, PREC == 1 ? 64 : 128);
+  const int gf = l2_grid(a.n, NW, 128), gb = l2_grid(a.n, NW, PREC == 1 ? 64 : 128);
 #define MPIP_L1(MQ)                                                        \
   if (fwd) k_l1_fwd<PREC, L, MQ, NW><<<gf, 64 * NW, 0, s>>>(a);              \
   else k_l1_bwd<PREC, L, MQ, NW><<<gb, 64 * NW, 0, s>>>(a);
