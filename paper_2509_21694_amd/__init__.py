@@ -337,7 +337,8 @@ class Model:
         if max_local is None:
             max_local = min(int(N * (1.0 / n_parts + 2.0 * halo / Lax) * 1.05) + 1024,
                             N * (2 * (int(math.ceil(halo / Lax)) + 1) + 1))
-        if max_edges is None:
+        edges_given = max_edges is not None
+        if not edges_given:
             max_edges = estimate_edges(N, cell, self.hp.r_cut) * max_local // N + 1024
         prec = PRECISIONS[precision]
         o = {"energy": torch.empty(1, dtype=torch.float64, device=self.device),
@@ -368,6 +369,8 @@ class Model:
                     continue
                 max_local = max(max_local, int(parts[:, 0].max() * 1.05) + 1024)
                 max_edges = max(max_edges, int(parts[:, 2].max() * 1.05) + 1024)
+                if not edges_given:   # the default edge capacity follows the row capacity
+                    max_edges = max(max_edges, estimate_edges(N, cell, self.hp.r_cut) * max_local // N + 1024)
                 continue
             _check(st)
             o["parts"] = parts

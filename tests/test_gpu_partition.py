@@ -273,3 +273,27 @@ def test_graph_halo_driver(torch, M, prec, bfs_case, bfs_full):
         assert dW <= 1e-8 and dae <= 1e-6
     else:
         assert dE <= 1e-3 and rms <= 5e-3 and rms <= 2e-2 * frms and dW <= 1e-5 and dae <= 1e-3
+
+
+@pytest.mark.parametrize("which", ["rows", "edges"])
+def test_partitioned_driver_capacity_retry(torch, M, which):
+    """A share capacity (rows or directed edges) that is too small stops the
+    driver with ECAPACITY and the size it needed; the binding's retry with
+    that size gives the whole box's oracle result."""
+    path = os.path.join(GOLDEN, "slab20k_K2.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing (tests/golden/make_golden.py)")
+    g = np.load(path)
+    s = W.slab_downscale_full()
+    hp = W.HP_MPDP
+    model = M.Model(hp, W.make_weights(hp, W.WEIGHT_SEEDS["slab8m"]))
+    pos = torch.tensor(s.positions, dtype=torch.float64, device="cuda")
+    sp = torch.tensor(s.species, dtype=torch.int32, device="cuda")
+    kw = {"max_local": 1000} if which == "rows" else {"max_edges": 1000}
+    print(f"[driver retry] {which}", flush=True)
+    o = model.evaluate_partitioned(pos, sp, s.cell, s.pbc, n_parts=8, K=2, precision="fp32", **kw)
+    F = o["forces"].cpu().numpy()
+    dE = abs(float(o["energy"].cpu()[0]) - float(g["energy"])) / s.n_atoms
+    dF = np.abs(F - g["forces"]).max()
+    print(f"[driver retry] {which}: dE/N={dE:.2e} max|dF|={dF:.2e}")
+    assert dE <= 1e-6 and dF <= 1e-4
