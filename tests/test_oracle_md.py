@@ -112,3 +112,17 @@ def test_langevin_equipartition():
     kT = md.BOLTZMANN_EV * T
     ratio = (m[:, None] * tr.velocities[-1] ** 2 / md.ACCEL).mean() / kT
     assert 0.85 < ratio < 1.15
+
+
+def test_accel_unit_factor_from_faraday_constant():
+    """The force/mass -> acceleration factor, pinned by a value the code does
+    not derive it from: e/u equals the Faraday constant over the molar mass
+    constant, F = 96485.33212 C/mol (CODATA 2018) and M_u = 1e-3 kg/mol (to
+    4e-10 relative), so 1 eV/(A amu) = F / M_u * 1e10 m/s^2, and
+    1 m/s^2 = 1e-20 A/fs^2; the textbook form of the same fact is
+    1 amu A^2/fs^2 = 103.6427 eV."""
+    faraday, molar_mass_const = 96485.33212, 1e-3
+    want = faraday / molar_mass_const * 1e10 * 1e-20
+    assert md.ACCEL == pytest.approx(want, rel=1e-9)
+    assert md.ACCEL == pytest.approx(9.648533e-3, rel=1e-6)
+    assert 1.0 / md.ACCEL == pytest.approx(103.6427, rel=1e-6)

@@ -378,3 +378,197 @@ def test_local_cluster_force():
         res = oracle.evaluate(lp, ls, np.eye(3), [False] * 3, blob, hp, K=2, n_owned=n_own)
         assert np.allclose(res.forces[c], full.forces[a], atol=1e-12)
         assert res.atom_energy[c] == pytest.approx(full.atom_energy[a], abs=1e-12)
+
+
+# ------------------------------------------------- every middle-layer path (K = 3, l_max = 2)
+
+def _scipy_real_harmonics(l, v):
+    """A real orthonormal basis of the degree-l harmonics built from scipy's
+    complex ones (its own phase convention): sqrt(2) Re Y_l^m for m > 0,
+    Y_l^0, sqrt(2) Im Y_l^|m| for m < 0, scaled by sqrt(4 pi) to the
+    component normalisation.  It differs from the oracle's basis by an
+    orthogonal matrix per degree, which leaves every energy unchanged when the
+    coupling tensors are built from the same basis."""
+    from scipy.special import sph_harm_y
+    x, y, z = v
+    theta = math.acos(max(-1.0, min(1.0, z)))
+    phi = math.atan2(y, x)
+    out = []
+    for m in range(-l, l + 1):
+        c = complex(sph_harm_y(l, abs(m), theta, phi))
+        out.append(c.real if m == 0 else math.sqrt(2) * (c.real if m > 0 else c.imag))
+    return math.sqrt(4 * math.pi) * np.array(out)
+
+
+def _scipy_couplings(L):
+    """C = G / ||G||_F of the Gaunt integrals in the scipy basis, by a product
+    rule (12 Gauss-Legendre nodes in cos(theta) x 24 in phi: exact to degree
+    23, the integrands have degree <= 6)."""
+    zs, wz = np.polynomial.legendre.leggauss(12)
+    pts, wts = [], []
+    for z, wzz in zip(zs, wz):
+        for k in range(24):
+            ph = 2 * math.pi * k / 24
+            s = math.sqrt(1 - z * z)
+            pts.append((s * math.cos(ph), s * math.sin(ph), z))
+            wts.append(wzz * 2 * math.pi / 24)
+    Ys = [{l: _scipy_real_harmonics(l, p) for l in range(L + 1)} for p in pts]
+    out = {}
+    for a, b, c in _paths2(L):
+        G = sum(wq * np.einsum("x,y,z->xyz", Yq[a], Yq[b], Yq[c]) for wq, Yq in zip(wts, Ys))
+        out[(a, b, c)] = G / np.linalg.norm(G)
+    return out
+
+
+def independent_atom_energies(pos, sp, hp, blob, K):
+    """The layer equations written out edge by edge for a non-periodic
+    cluster: every path at every layer (dead ones included), every gate, the
+    radial basis and envelope retyped from their definitions, the harmonics and
+    couplings from scipy in its own basis; shares only the blob layout."""
+    w = _unpack(blob, hp)
+    C, L = hp.channels, hp.l_max
+    rc, nb, inv_n, N = hp.r_cut, hp.n_basis, 1.0 / hp.avg_neighbors, len(pos)
+    cpl = _scipy_couplings(L)
+
+    def radial(t, d):
+        x = d / rc
+        env = 1 - 28 * x ** 6 + 48 * x ** 7 - 21 * x ** 8
+        e = np.array([env * math.sqrt(2 / rc) * math.sin(n * math.pi * d / rc) / d for n in range(1, nb + 1)])
+        return _silu(_silu(e @ w[f"L{t}.W1"]) @ w[f"L{t}.W2"]) @ w[f"L{t}.W3"]
+
+    nbr = []
+    for i in range(N):
+        row = []
+        for j in range(N):
+            r = pos[j] - pos[i]
+            d = math.sqrt(r @ r)
+            if i != j and d < rc:
+                row.append((j, r / d, d))
+        nbr.append(row)
+    h = {l: np.zeros((N, 2 * l + 1, C)) for l in range(L + 1)}
+    h[0][:, 0, :] = w["W_emb"][sp]
+    for t in range(1, K + 1):
+        l_in = [0] if t == 1 else list(range(L + 1))
+        paths = [p for p in _paths2(L) if p[0] in l_in]
+        ht = {l: h[l] @ w[f"L{t}.W_up{l}"] for l in l_in}
+        A = {l: np.zeros((N, 2 * l + 1, C)) for l in range(L + 1)}
+        for i in range(N):
+            for j, u, d in nbr[i]:
+                R = radial(t, d).reshape(len(paths), C)
+                Y = {l: _scipy_real_harmonics(l, u) for l in range(L + 1)}
+                for q, (a, b, c) in enumerate(paths):
+                    A[c][i] += inv_n * R[q] * np.einsum("xyz,xk,y->zk", cpl[(a, b, c)], ht[a][j], Y[b])
+        z0 = A[0][:, 0, :] @ w[f"L{t}.W_down0"]
+        hn = {0: h[0] + _silu(z0[:, :C])[:, None, :]}
+        for l in range(1, L + 1):
+            gate = _sig(z0[:, l * C:(l + 1) * C])
+            hn[l] = h[l] + gate[:, None, :] * (A[l] @ w[f"L{t}.W_down{l}"])
+        h = hn
+    return w["e0"][sp] + h[0][:, 0, :] @ w["w_read"]
+
+
+def test_independent_deep_forward_every_path():
+    """K = 3, l_max = 2: the middle layer runs all 11 coupling paths, and its
+    per-atom energies equal the independent edge-by-edge evaluation."""
+    pos, sp = cluster(9, 41, box=6.0, dmin=1.5)
+    hp = hp_of(2, 4, 3)
+    blob = W.make_weights(hp, 17, e0=[0.2, -0.1, 0.05])
+    ref = independent_atom_energies(pos, sp, hp, blob, 3)
+    res = ev(pos, sp, hp, blob, K=3, forces=False)
+    assert np.allclose(res.atom_energy, ref, rtol=0, atol=1e-12)
+    # every middle-layer path contributes: dropping any one moves the energy
+    base = res.energy
+    for p in _paths2(2):
+        if p == (0, 0, 0):
+            continue
+        with _planted_coupling(p, lambda Cp: 0.0 * Cp):
+            dropped = ev(pos, sp, hp, blob, K=3, forces=False).energy
+        assert abs(dropped - base) > 1e-10, p
+
+
+class _planted_coupling:
+    """Replace the oracle's coupling tensor of one path inside a with-block
+    (a deliberate mistake, to show that a pin notices it)."""
+
+    def __init__(self, path, fn):
+        self.path, self.fn = path, fn
+
+    def __enter__(self):
+        import oracle.model as om
+        self.om, self.orig = om, om.coupling_tensor
+
+        def patched(a, b, c):
+            Cp = self.orig(a, b, c)
+            return self.fn(np.array(Cp)) if (a, b, c) == self.path else Cp
+        om.coupling_tensor = patched
+        return self
+
+    def __exit__(self, *exc):
+        self.om.coupling_tensor = self.orig
+        return False
+
+
+def _o3_deviation(pos, sp, cell, pbc, hp, blob, K):
+    """Largest relative deviation of E, E_i, F and W from their required
+    behaviour under a proper rotation, the inversion, a translation and a
+    permutation."""
+    base = oracle.evaluate(pos, sp, cell, pbc, blob, hp, K=K)
+    fs = max(np.abs(base.forces).max(), 1e-30)
+    es = max(np.abs(base.atom_energy).max(), 1e-30)
+    ws = max(np.abs(base.virial).max(), 1e-30)
+    rng = np.random.default_rng(3)
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    Q = q @ np.diag(np.sign(np.diag(r)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    dev = 0.0
+    for M in (Q, -np.eye(3), -Q):
+        o = oracle.evaluate(pos @ M.T, sp, cell @ M.T, pbc, blob, hp, K=K)
+        dev = max(dev, np.abs(o.atom_energy - base.atom_energy).max() / es,
+                  np.abs(o.forces - base.forces @ M.T).max() / fs,
+                  np.abs(o.virial - M @ base.virial @ M.T).max() / ws)
+    tr = oracle.evaluate(pos + np.array([1.7, -2.9, 40.3]), sp, cell, pbc, blob, hp, K=K)
+    dev = max(dev, np.abs(tr.atom_energy - base.atom_energy).max() / es,
+              np.abs(tr.forces - base.forces).max() / fs)
+    perm = rng.permutation(len(pos))
+    pe = oracle.evaluate(pos[perm], sp[perm], cell, pbc, blob, hp, K=K)
+    dev = max(dev, np.abs(pe.atom_energy - base.atom_energy[perm]).max() / es,
+              np.abs(pe.forces - base.forces[perm]).max() / fs)
+    return dev
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_rotation_inversion_translation_deep(periodic):
+    """O(3) invariance of E and E_i, equivariance of F and W, at T = K = 3,
+    l_max = 2, so the paths (1,0,1) (1,1,2) (1,2,1) (2,0,2) (2,1,1) (2,2,2)
+    of the middle layer carry features of degree 1 and 2 into it."""
+    hp = hp_of(2, 8, 3)
+    blob = W.make_weights(hp, 23)
+    if periodic:
+        rng = np.random.default_rng(12)
+        box = 10.5
+        pos = W.lattice_positions(4, 4, 4, box / 4, 31)
+        sp = rng.integers(0, 3, 64).astype(np.int32)
+        cell, pbc = np.eye(3) * box, (True, True, True)
+    else:
+        pos, sp = cluster(20, 77, box=8.0, dmin=1.5)
+        cell, pbc = np.eye(3) * 100.0, (False, False, False)
+    assert _o3_deviation(pos, sp, cell, np.array(pbc), hp, blob, 3) < 1e-11
+
+
+@pytest.mark.parametrize("path", [(1, 1, 2), (1, 2, 1), (2, 1, 1), (2, 2, 2)])
+def test_deep_pins_notice_a_planted_mistake(path):
+    """A wrong m order in one middle-layer coupling (a cyclic shift of its
+    first index, as a mis-ordered harmonic block would give) breaks both the
+    O(3) pin and the independent forward."""
+    pos, sp = cluster(9, 41, box=6.0, dmin=1.5)
+    hp = hp_of(2, 4, 3)
+    blob = W.make_weights(hp, 17)
+    ref = independent_atom_energies(pos, sp, hp, blob, 3)
+    with _planted_coupling(path, lambda Cp: np.roll(Cp, 1, axis=0)):
+        bad = ev(pos, sp, hp, blob, K=3, forces=False)
+        dev = _o3_deviation(pos, sp, np.eye(3) * 100.0, np.array([False] * 3), hp, blob, 3)
+    # the clean oracle agrees to 1e-12 (energies) and 1e-11 (O(3) deviation);
+    # the planted mistake moves them by 3e-10 .. 6e-10 and 1.7e-7 .. 6.5e-7
+    assert np.abs(bad.atom_energy - ref).max() > 1e-10
+    assert dev > 1e-8
