@@ -200,10 +200,12 @@ class Model:
         self._ws = None
         self._ws_key = None
 
-    def __del__(self):
+    def __del__(self, _destroy=lib.mpip_model_destroy):
+        # the library function is bound at class creation: at interpreter
+        # shutdown the module global ``lib`` may already be None
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib.mpip_model_destroy(h)
+            _destroy(h)
             self._h = None
 
     def workspace_bytes(self, n_atoms: int, K: int, precision, max_edges: int) -> int:
@@ -254,6 +256,13 @@ class Model:
             _check(lib.mpip_evaluate(self._h, ctypes.byref(sysc), prec, K, ctypes.c_void_p(sp),
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), max_edges, ctypes.byref(oc)))
             if not check:
+                if stream is not None:
+                    # keep the caching allocator from handing the workspace or the
+                    # outputs to other work while this stream may still use them
+                    ws.record_stream(stream)
+                    for v in o.values():
+                        if isinstance(v, torch.Tensor):
+                            v.record_stream(stream)
                 return o
             ne = ctypes.c_int64()
             st = lib.mpip_workspace_status(ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(sp), ctypes.byref(ne))
@@ -288,8 +297,12 @@ class Model:
         if max_edges is None:
             max_edges = int(estimate_edges(N, cell, self.hp.r_cut) * 1.1)
         if forces is None:
-            forces = self.evaluate(positions, species, cell, pbc, K=K, precision=precision, max_edges=max_edges,
-                                   stream=stream)["forces"]
+            first = self.evaluate(positions, species, cell, pbc, K=K, precision=precision, max_edges=max_edges,
+                                  stream=stream)
+            forces = first["forces"]
+            # the list of the starting positions sets a floor under the capacity
+            # (evaluate may have grown it on its retry)
+            max_edges = max(max_edges, int(first["n_edges"] * 1.1) + 1024)
         prec = PRECISIONS[precision]
         sysc = _system(positions, species, cell, pbc, None)
         prm = MdParamsC(float(dt), int(n_steps), float(friction), float(temperature), int(seed), float(skin))
@@ -351,7 +364,12 @@ class Model:
         sp = _stream_ptr(torch, self.device, stream)
         parts = np.zeros((n_parts, 3), dtype=np.int64)
         graph_edges = estimate_edges(N, cell, self.hp.r_cut) if graph_halo else -1
-        for attempt in range(2):
+        # the driver stops at the first share that outgrows the capacities and
+        # reports that share's sizes (later shares read zero), so a later,
+        # larger share can overflow again: up to four retries, each growing
+        # the capacities to at least what the last overflow needed
+        attempts = 5
+        for attempt in range(attempts):
             need = ctypes.c_size_t()
             _check(lib.mpip_partitioned_workspace_size(self._h, ctypes.byref(sysc), prec, K, n_parts, axis,
                                                        float(halo), graph_edges, max_local, max_edges,
@@ -363,7 +381,7 @@ class Model:
                                                graph_edges, ctypes.c_void_p(sp), ctypes.c_void_p(self._ws.data_ptr()),
                                                self._ws.numel(), max_local, max_edges, ctypes.byref(oc),
                                                parts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
-            if st == ECAPACITY and attempt == 0:
+            if st == ECAPACITY and attempt + 1 < attempts:
                 if graph_halo and parts[:, 0].sum() == 0:     # the whole structure's list overflowed
                     graph_edges = max(graph_edges, int(parts[0, 2] * 1.05) + 1024)
                     continue

@@ -74,6 +74,10 @@ struct DevArena {
 
 }  // namespace
 
+// Events created when timing is enabled: two per phase, about 12 phases per
+// evaluation, so 170 timed evaluations between two reads need no new event.
+constexpr size_t kTimingEvents = 4096;
+
 // Event-pair timer of evaluation phases (enabled on request only).
 struct PhaseTimer {
   bool on = false;
@@ -83,22 +87,30 @@ struct PhaseTimer {
   std::vector<std::string> names;
   std::vector<double> ms;
   std::vector<int64_t> calls;
-  hipEvent_t next() {
-    if (used == pool.size()) {
+  // events are created when timing is switched on (reserve), so a timed
+  // evaluation only records them; the pool grows here only past that reserve
+  void reserve(size_t n) {
+    while (pool.size() < n) {
       hipEvent_t e;
-      hipEventCreate(&e);
+      if (hipEventCreate(&e) != hipSuccess) break;
       pool.push_back(e);
     }
-    return pool[used++];
   }
+  // a phase takes its start and end events in begin(); if none can be
+  // created, timing switches itself off
   void begin(const std::string& name, hipStream_t s) {
     if (!on) return;
+    if (used + 2 > pool.size()) reserve(used + 64);
+    if (used + 2 > pool.size()) {
+      on = false;
+      return;
+    }
     pending.push_back({name, used});
-    hipEventRecord(next(), s);
+    hipEventRecord(pool[used++], s);
   }
   void end(hipStream_t s) {
     if (!on) return;
-    hipEventRecord(next(), s);
+    hipEventRecord(pool[used++], s);
   }
   ~PhaseTimer() {
     for (hipEvent_t e : pool) hipEventDestroy(e);
@@ -1047,6 +1059,7 @@ mpip_status mpip_timing_enable(mpip_model* m, int32_t on) {
   if (!m) return fail(MPIP_EINVAL, "null model");
   PhaseTimer& T = m->timer;
   T.on = on != 0;
+  if (T.on) T.reserve(kTimingEvents);
   T.used = 0;
   T.pending.clear();
   T.names.clear();
@@ -1593,16 +1606,39 @@ mpip_status mpip_md_run(mpip_model* m, const mpip_system* sys, double* positions
   out.atom_energy = nullptr;
   PhaseTimer& T = m->timer;
   launch_zero(sticky, sizeof(int64_t), s);
+  // the list of the starting positions is built once and its status read
+  // before anything moves: a capacity (or input) error returns here with the
+  // positions, velocities and forces untouched
+  if (prm->n_steps > 0) {
+    launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
+    if (!skin) build_neighbors(b, s2, ci, max_edges, s);
+    else build_neighbors(sup, s2, ci_list, sc.sup_cap, s);
+    int64_t st[ST_WORDS];
+    HIPCHK(hipMemcpyAsync(st, b.status, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st[ST_FLAGS] != 0) {
+      if (cur != m->device) hipSetDevice(cur);
+      if (st[ST_FLAGS] & FL_CAPACITY)
+        return fail(MPIP_ECAPACITY, "edge capacity exceeded by the starting positions (" +
+                                        std::to_string(st[ST_NEDGES]) + " edges needed); nothing was moved");
+      return fail(MPIP_EINVAL, "invalid starting positions or species; nothing was moved");
+    }
+  }
   bool rebuild = true;
   for (int64_t step = 0; step < prm->n_steps; ++step) {
     md_first(N, positions, velocities, forces, sys->species, masses, prm->dt, prm->friction, prm->temperature,
              prm->seed, step, xref, 0.25 * prm->skin * prm->skin, moved, s);
     if (skin && step > 0) {
-      // the rebuild decision needs the displacement flag on the host
-      int64_t f = 0;
-      HIPCHK(hipMemcpyAsync(&f, moved, sizeof(f), hipMemcpyDeviceToHost, s));
+      // the rebuild decision needs the displacement flag on the host; the
+      // errors of the steps so far are read with it, and the run stops after
+      // the first step whose list overflowed (positions and velocities are
+      // then those after that step)
+      int64_t f[2] = {0, 0};
+      HIPCHK(hipMemcpyAsync(&f[0], moved, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&f[1], sticky, sizeof(int64_t), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      rebuild = f != 0;
+      if (f[1] != 0) break;
+      rebuild = f[0] != 0;
     }
     launch_zero(b.status, sizeof(int64_t) * ST_WORDS, s);
     T.begin("neighbors", s);
