@@ -124,7 +124,7 @@ mpip_status mpip_workspace_size(const mpip_model* model, const mpip_system* sys,
  * once.  Data-dependent errors (edge capacity exceeded, species out of range,
  * non-finite positions, coincident atoms) are recorded in the workspace and
  * reported by mpip_workspace_status after the stream is synchronised; the
- * outputs are then undefined.  Orthorhombic cells only (else EUNSUPPORTED).
+ * energy and virial are then NaN and the other outputs undefined.  Orthorhombic cells only (else EUNSUPPORTED).
  *
  * Partition shares (0 < n_owned < n_atoms, n_atoms >= 64): the energy of the
  * root atoms after K layers depends only on their K-hop neighbourhood
@@ -138,6 +138,25 @@ mpip_status mpip_workspace_size(const mpip_model* model, const mpip_system* sys,
 mpip_status mpip_evaluate(mpip_model* model, const mpip_system* sys, mpip_precision prec,
                           int32_t K, void* stream, void* workspace, size_t workspace_bytes,
                           int64_t max_edges, const mpip_outputs* out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * evaluation of mpip_evaluate, with the workspace taken from a fixed array of
+ * MPIP_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on until the process ends.  The caller passes inputs and outputs only;
+ * the call allocates no device memory and clears what must start at zero
+ * itself.  Systems whose workspace (mpip_workspace_size for the same
+ * arguments) exceeds MPIP_NOALLOC_SCRATCH_BYTES are rejected with ECAPACITY
+ * before anything is enqueued.  Every call on one device shares that device's
+ * array: calls that overlap in time on one device (two streams, two threads,
+ * two models) race and give undefined outputs; serialise them.  A
+ * data-dependent error (as for mpip_evaluate, e.g. more than max_edges edges)
+ * leaves NaN in the energy and virial; the status word sits in the array, so
+ * mpip_workspace_status cannot read it.  Otherwise as mpip_evaluate
+ * (asynchronous on `stream`; partition shares synchronise once). */
+#define MPIP_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+mpip_status mpip_evaluate_noalloc(mpip_model* model, const mpip_system* sys, mpip_precision prec,
+                                  int32_t K, void* stream, int64_t max_edges, const mpip_outputs* out);
 
 /* Batched evaluation of B independent structures (atoms concatenated):
  * structure b owns atoms atom_ptr[b] .. atom_ptr[b+1]-1 (host int64 [B+1],

@@ -81,6 +81,8 @@ def _load():
     lib.mpip_workspace_size.restype = I32
     lib.mpip_evaluate.argtypes = [V, P(SystemC), I32, I32, V, V, SZ, I64, P(OutputsC)]
     lib.mpip_evaluate.restype = I32
+    lib.mpip_evaluate_noalloc.argtypes = [V, P(SystemC), I32, I32, V, I64, P(OutputsC)]
+    lib.mpip_evaluate_noalloc.restype = I32
     lib.mpip_workspace_status.argtypes = [V, V, P(I64)]
     lib.mpip_workspace_status.restype = I32
     lib.mpip_neighbor_workspace_size.argtypes = [I64, I64]
@@ -133,7 +135,10 @@ EXPORTED = ["mpip_weights_count", "mpip_model_create", "mpip_model_destroy", "mp
             "mpip_slab_workspace_size", "mpip_slab_share", "mpip_accumulate_rows",
             "mpip_batch_workspace_size", "mpip_evaluate_batch", "mpip_md_workspace_size", "mpip_md_run",
             "mpip_partitioned_workspace_size", "mpip_evaluate_partitioned", "mpip_bfs_share_workspace_size",
-            "mpip_bfs_share", "mpip_last_error"]
+            "mpip_bfs_share", "mpip_evaluate_noalloc", "mpip_last_error"]
+
+# size of the library's static workspace used by mpip_evaluate_noalloc (MPIP_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 def _check(st: int):
@@ -274,6 +279,29 @@ class Model:
             return o
         raise MpipError(ECAPACITY, "edge capacity")
 
+
+    def evaluate_noalloc(self, positions, species, cell, pbc, out, K: Optional[int] = None, precision="fp32",
+                         n_owned: Optional[int] = None, max_edges: Optional[int] = None, stream=None):
+        """mpip_evaluate_noalloc: the evaluation of ``evaluate`` with the
+        library's static workspace; ``out`` is a dict of preallocated cuda
+        tensors (energy [1], forces [N,3], virial [3,3], optional
+        atom_energy [N]).  Nothing is allocated and nothing synchronised
+        (except for partition shares, as in ``evaluate``); a data-dependent
+        error leaves NaN in the energy and virial."""
+        torch = self.torch
+        K = self.hp.n_layers if K is None else int(K)
+        N = int(positions.shape[0])
+        assert positions.dtype == torch.float64 and positions.is_cuda and positions.is_contiguous()
+        assert species.dtype == torch.int32 and species.is_cuda and species.is_contiguous()
+        if max_edges is None:
+            max_edges = estimate_edges(N, cell, self.hp.r_cut)
+        oc = OutputsC(out["energy"].data_ptr(), out["forces"].data_ptr(), out["virial"].data_ptr(),
+                      out["atom_energy"].data_ptr() if out.get("atom_energy") is not None else None)
+        sysc = _system(positions, species, cell, pbc, n_owned)
+        sp = _stream_ptr(torch, self.device, stream)
+        _check(lib.mpip_evaluate_noalloc(self._h, ctypes.byref(sysc), PRECISIONS[precision], K,
+                                         ctypes.c_void_p(sp), max_edges, ctypes.byref(oc)))
+        return out
 
     def md_run(self, positions, velocities, species, masses, cell, pbc=(True, True, True), *, dt: float,
                n_steps: int, forces=None, friction: float = 0.0, temperature: float = 0.0, seed: int = 0,

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -71,6 +72,35 @@ struct DevArena {
     for (void* p : ptrs) hipFree(p);
   }
 };
+
+}  // namespace
+
+// Workspace of mpip_evaluate_noalloc: one fixed-size array in every device's
+// copy of this code object, held until the process ends.  In host code its
+// name is only a stand-in; the device address is resolved once per device
+// (with that device current) and kept in scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = (size_t)MPIP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on device `dev`, which must be current
+mpip_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(MPIP_EUNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MPIP_EDEVICE, "hipGetSymbolAddress returned a null address for the static scratch");
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return MPIP_OK;
+}
 
 }  // namespace
 
@@ -471,6 +501,11 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
       }
     }
   }
+  {
+    // the static scratch of mpip_evaluate_noalloc, resolved once per device while it is current
+    void* sp = nullptr;
+    if ((st = scratch_address(device, &sp)) != MPIP_OK) goto done;
+  }
   HIPCHK(hipDeviceSynchronize());
 done:
   hipSetDevice(cur);
@@ -488,6 +523,14 @@ done:
 
 namespace {
 
+// per-layer workspace offsets; K <= 16 (the model limit)
+struct LayerOffsets {
+  size_t v[16] = {};
+  int n = 0;
+  void push_back(size_t x) { v[n++] = x; }
+  size_t operator[](int i) const { return v[i]; }
+};
+
 struct Plan {
   size_t total = 0;
   size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_rcount, o_rstart, o_scan, o_info, o_perm, o_iperm, o_pos,
@@ -496,7 +539,7 @@ struct Plan {
   size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
   size_t o_msg = 0; // last-layer messages of the BF16 form, [max_edges][C] bf16
   size_t o_part = 0; // middle-layer adjoint: per-edge sums between its launches, [max_edges][kPartStride]
-  std::vector<size_t> o_ht, o_z0, o_zl;  // per layer 1..K (index t-1)
+  LayerOffsets o_ht, o_z0, o_zl;  // per layer 1..K (index t-1)
   int max_bins;
   int nblocks_out;
 };
@@ -998,10 +1041,9 @@ static void eval_on_list(mpip_model* m, const Plan& p, char* w, const NbrBuffers
   T.end(s);
 }
 
-extern "C" {
-
-mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K, void* stream,
-                          void* ws, size_t ws_bytes, int64_t max_edges, const mpip_outputs* out) {
+static mpip_status evaluate_impl(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K,
+                                 void* stream, void* ws, size_t ws_bytes, int64_t max_edges,
+                                 const mpip_outputs* out) {
   if (!m) return fail(MPIP_EINVAL, "null model");
   const mpip_hparams& hp = m->hp;
   CellInfo ci;
@@ -1030,29 +1072,58 @@ mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision 
   build_neighbors(b, *sys, ci, max_edges, s);
   T.end(s);
   (void)atom_e;
-  std::vector<int64_t> rows;
+  int64_t rows[16 + 1];
+  bool trimmed = false;
   if (sys->n_owned > 0 && sys->n_owned < N && N >= trim_min_atoms() && K <= trim_max_layers()) {
     // receptive-field trimming of a partition share: hop classes from the
     // roots, read back once, then the rows are re-ordered by class
     T.begin("trim", s);
     const int64_t* d = trim_classes(b, N, K, max_edges, s);
     T.end(s);
-    std::vector<int64_t> hb(K + 3);
-    HIPCHK(hipMemcpyAsync(hb.data(), d, sizeof(int64_t) * (K + 3), hipMemcpyDeviceToHost, s));
+    int64_t hb[16 + 3];
+    HIPCHK(hipMemcpyAsync(hb, d, sizeof(int64_t) * (K + 3), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hb[K + 2] == 0) {   // else the list is unusable and every pass skips on the status word
       T.begin("trim", s);
       trim_permute(b, N, max_edges, g, s);
       T.end(s);
-      rows.resize(K + 1);
+      trimmed = true;
       for (int t = 0; t <= K; ++t) rows[t] = hb[K - t + 1];
     }
   }
-  eval_on_list(m, p, w, b, N, prec, K, max_edges, s, out, rows.empty() ? nullptr : rows.data());
+  eval_on_list(m, p, w, b, N, prec, K, max_edges, s, out, trimmed ? rows : nullptr);
   hipError_t e = hipGetLastError();
   if (cur != m->device) hipSetDevice(cur);
   if (e != hipSuccess) return fail(MPIP_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return MPIP_OK;
+}
+
+extern "C" {
+
+mpip_status mpip_evaluate(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K, void* stream,
+                          void* ws, size_t ws_bytes, int64_t max_edges, const mpip_outputs* out) {
+  return evaluate_impl(m, sys, prec, K, stream, ws, ws_bytes, max_edges, out);
+}
+
+mpip_status mpip_evaluate_noalloc(mpip_model* m, const mpip_system* sys, mpip_precision prec, int32_t K,
+                                  void* stream, int64_t max_edges, const mpip_outputs* out) {
+  if (!m) return fail(MPIP_EINVAL, "null model");
+  if (!sys || sys->n_atoms < 1) return fail(MPIP_EINVAL, "null system or n_atoms < 1");
+  if (K < 1 || K > m->hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
+  if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
+  const size_t need = make_plan(sys->n_atoms, max_edges, &m->hp, K).total;
+  if (need > kNoAllocScratchBytes)
+    return fail(MPIP_ECAPACITY, "mpip_evaluate_noalloc: this system needs " + std::to_string(need) +
+                                    " bytes of workspace; the static scratch holds " +
+                                    std::to_string(kNoAllocScratchBytes));
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != m->device) HIPCHK(hipSetDevice(m->device));
+  void* ws = nullptr;
+  const mpip_status st = scratch_address(m->device, &ws);
+  if (cur != m->device) hipSetDevice(cur);
+  if (st != MPIP_OK) return st;
+  return evaluate_impl(m, sys, prec, K, stream, ws, kNoAllocScratchBytes, max_edges, out);
 }
 
 mpip_status mpip_timing_enable(mpip_model* m, int32_t on) {

@@ -91,7 +91,7 @@ int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; 
 void exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* tmp, hipStream_t s) {
   int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 0) {
-    (void)hipMemsetAsync(out, 0, sizeof(int32_t), s);
+    launch_zero(out, sizeof(int32_t), s);
     return;
   }
   k_scan_partials<<<nb, kScanBlock, 0, s>>>(in, n, tmp);
@@ -811,13 +811,13 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   if (nparts > kBoundsParts) nparts = kBoundsParts;
   k_bounds<<<nparts, 256, 0, s>>>(sys.positions, sys.species, n, ci.n_species, b.bounds, b.status);
   k_grid<<<1, 64, 0, s>>>(b.bounds, nparts, ci, b.max_bins, b.grid, b.status);
-  (void)hipMemsetAsync(b.bin_count, 0, sizeof(int32_t) * (b.max_bins + 1), s);
-  (void)hipMemsetAsync(b.bin_cursor, 0, sizeof(int32_t) * (b.max_bins + 1), s);
+  launch_zero(b.bin_count, sizeof(int32_t) * (b.max_bins + 1), s);
+  launch_zero(b.bin_cursor, sizeof(int32_t) * (b.max_bins + 1), s);
   const int ga = (int)((n + nblk - 1) / nblk);
   k_bin_assign<<<ga, nblk, 0, s>>>(sys.positions, n, ci, b.grid, b.info, b.bin_count);
   // bins laid out along a Morton curve: counts in rank order, scan, back to bins
   const int64_t nr = 8 * (int64_t)b.max_bins;
-  (void)hipMemsetAsync(b.rank_count, 0, sizeof(int32_t) * (nr + 1), s);
+  launch_zero(b.rank_count, sizeof(int32_t) * (nr + 1), s);
   const unsigned gb = (unsigned)((b.max_bins + 255) / 256);
   k_rank_count<<<gb, 256, 0, s>>>(b.grid, b.bin_count, b.rank_count);
   exclusive_scan(b.rank_count, nr, b.rank_start, b.scan_tmp, s);
@@ -838,7 +838,7 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
                                    b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.cmask, b.status);
   k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
-  (void)hipMemsetAsync(b.e_rev, 0xff, sizeof(int32_t) * (size_t)capacity, s);
+  launch_fill32(b.e_rev, 0xffffffffu, sizeof(int32_t) * (size_t)capacity, s);
   k_nbr_rev<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.info_s, b.grid, b.blk,
                                                        capacity, b.e_rev);
 }

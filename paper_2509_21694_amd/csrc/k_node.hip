@@ -357,8 +357,12 @@ __global__ void k_final(OutArgs a) {
       for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.energy[0] = sh[0][0];
-  if (threadIdx.x < 9) a.virial[threadIdx.x] = -sh[1 + threadIdx.x][0];
+  // a data-dependent error (the passes skipped their work) leaves NaN in the
+  // energy and virial, visible to callers that cannot read the status word
+  const bool ok = (a.status[ST_FLAGS] == 0) && ((int64_t)a.row_ptr[a.n] <= a.capacity);
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  if (threadIdx.x == 0) a.energy[0] = ok ? sh[0][0] : nan;
+  if (threadIdx.x < 9) a.virial[threadIdx.x] = ok ? -sh[1 + threadIdx.x][0] : nan;
 }
 
 void launch_outputs(const OutArgs& a, hipStream_t s) {
@@ -366,17 +370,20 @@ void launch_outputs(const OutArgs& a, hipStream_t s) {
   k_final<<<1, 256, 0, s>>>(a);
 }
 
-__global__ void k_zero(uint32_t* p, int64_t n) {
+__global__ void k_fill(uint32_t* p, int64_t n, uint32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
+    p[i] = v;
 }
 
-void launch_zero(void* p, size_t bytes, hipStream_t s) {
+// a kernel rather than hipMemsetAsync, so that a captured graph holds only kernel nodes
+void launch_fill32(void* p, uint32_t value, size_t bytes, hipStream_t s) {
   const int64_t n = (int64_t)(bytes / 4);
   if (n <= 0) return;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  k_zero<<<(unsigned)blocks, 256, 0, s>>>((uint32_t*)p, n);
+  k_fill<<<(unsigned)blocks, 256, 0, s>>>((uint32_t*)p, n, value);
 }
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) { launch_fill32(p, 0u, bytes, s); }
 
 }  // namespace mpip

@@ -355,5 +355,7 @@ void add_energy_virial_launch(const double* e, const double* w, double* E, doubl
 void scatter_scalars_launch(const double* src, const int32_t* index, int64_t n, int64_t n_dst, double* dst,
                             hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+// fill `bytes` (a multiple of 4) with a 32-bit pattern
+void launch_fill32(void* p, uint32_t value, size_t bytes, hipStream_t s);
 
 }  // namespace mpip
