@@ -10,16 +10,21 @@ intermediates recomputed, forces, virial); inputs are resident in HBM and
 two slightly different position sets (+-0.01 A) alternate between steps.
 
 Prints ONE JSON line.  `value` is the BF16-form rate (atom-steps/s); the
-FP32-form rate, the BF16 speedup and the force error of both forms against
-the FP64 oracle (at atoms whose oracle forces are exact, from a local
-cluster) are extra fields.  `roofline` is for the kernel with the largest
-share of the step (HIP-event durations from the timed steps);
-`cpu_baseline` times the FP64 oracle on a bounded cluster of the same box.
-Extra fields: `md` (on-device MD steps with neighbour-list reuse),
-`depth_pruning` (a 13,824-atom box, one 6-layer weight set run to K = 6
-and to K = 2) and `partitioned` (a whole 8,000,000-atom box evaluated as 8
-slab partitions one after the other, geometric and graph halos, with the
-halo growth against depth).
+FP32-form rate, the BF16 speedup and the errors of both forms against stored
+FP64 oracle values (`errors_vs_fp64`: energies and forces of the 1M-atom box
+where local clusters give them exactly; energy, forces and stress of every
+atom of a 32,768-atom box with the same potential) are extra fields.
+`roofline` is for the kernel with the largest share of the step (HIP-event
+durations from the timed steps); `step_roofline` sums the roofline times of
+every phase of the step over the measured step time; `cpu_baseline` times the
+FP64 oracle on a periodic box of the same lattice and potential, on all host
+cores and on one.  Extra fields: `md` (on-device MD steps with
+neighbour-list reuse), `depth_pruning` (a 13,824-atom box, one 6-layer
+weight set run to K = 6 and to K = 2, with per-layer times), `partitioned`
+(a whole 8,000,000-atom box evaluated as 8 slab partitions one after the
+other, geometric and graph halos, the halo growth against depth, and one
+share evaluated at K = 2 and K = 6) and `batch512` (512 independent small
+cells evaluated together, both forms).
 """
 from __future__ import annotations
 
@@ -38,8 +43,11 @@ import workloads as W  # noqa: E402
 
 METRIC = "atom-steps/s (E+F) at 1M atoms, BF16 vs FP32 form on 1 GPU; force RMS vs FP64"
 
-# MI355X published peaks
-PEAK = {"hbm": 8.0e12, "mfma_bf16": 2.5e15, "mfma_fp32": 157.3e12, "alu_fp32": 157.3e12}
+# MI355X published peaks.  The published FP32 vector peak (157.3 TFLOP/s)
+# counts packed FMA; every kernel here is compiled with packed FP32 off, so
+# the VALU ceiling used is the unpacked rate: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flop x 2.4 GHz = 78.6 TFLOP/s.
+PEAK = {"hbm": 8.0e12, "mfma_bf16": 2.5e15, "mfma_fp32": 157.3e12, "alu_fp32": 78.6e12}
 
 
 def workload(name):
@@ -85,11 +93,31 @@ def phase_counts(hp, prec):
         del d["edge_pull_t2"]
         # forward as sender-side messages: full MLP, X_l = <h~_j,l , YC_l> on
         # MFMA (nlm MAC per channel), m = sum_l R_l X_l on the VALU (P FMA per
-        # channel); the message (C BF16) written once per edge; h~_j read once per atom
-        d["edge_fwd_t2"] = (2 * (mlp12 + mlp3) + 2.0 * nlm * C, 2.0 * P * C, ev + src + 2 * C,
+        # channel); h~_j read once per atom, e_vec, e_rev read per edge.  The
+        # per-edge messages this form writes (and the sum reads back) are
+        # not algorithmic bytes of the layer: they count in the measured
+        # traffic only
+        d["edge_fwd_t2"] = (2 * (mlp12 + mlp3) + 2.0 * nlm * C, 2.0 * P * C, ev + src,
                             8 + nlm * C * fb)
-        # A_i = sum over the row of the messages: C BF16 read per edge, C FP32 written per atom
-        d["edge_sum_t2"] = (0.0, 1.0 * C, 2 * C, 8 + 4 * C)
+        # A_i = sum over the row of the messages: C adds per edge; A_i (C FP32) written per atom
+        d["edge_sum_t2"] = (0.0, 1.0 * C, 0, 8 + 4 * C)
+        # fused node kernels between the two layers, forward and adjoint
+        # (one phase): z = Q (VW) and h~ = h W_up forward, h-bar = h~-bar W_up^T
+        # and P = z-bar (VW)^T backward; Q read twice, P written, h_0 (FP32) and
+        # h~ (BF16) written, h~-bar (BF16) read
+        KQ = 64 * S
+        zq = 2.0 * KQ * (C * (1 + L) + (nlm - 1) * C)
+        up = 2.0 * nlm * C * C
+        d["node_fused"] = (2 * (zq + up), 0.0, 0, 3 * nlm * KQ * 2 + 4 * C + 2 * nlm * C * 2)
+        # last-layer node update and its adjoint: A and h_0 read, dE/dA written over A,
+        # E_i written; z_0 = W_down^T A and dE/dA = W_down z-bar on MFMA
+        d["node_last"] = (2 * 2.0 * C * C, 0.0, 0, 3 * 4 * C + 8)
+    # neighbour list: positions and species read, the sorted copies, permutation
+    # and row pointers written per atom; sender, shift, vector and reverse index
+    # written per edge
+    d["neighbors"] = (0.0, 0.0, 4 + 4 + 16 + 4, 28 + 28 + 8 + 4)
+    # forces / virial: g, e_vec, e_rev read per edge; forces (FP64) and atom energy written per atom
+    d["outputs"] = (0.0, 0.0, 16 + 16 + 4, 24 + 8 + 4 + 8)
     return d
 
 
@@ -132,6 +160,29 @@ def measured_traffic(kernel_phase):
     return None
 
 
+def step_roofline(phases, steps, hp, n_edges, prec, n_atoms):
+    """Whole-step figure: sum over the step's phases of each one's roofline
+    time (largest of MFMA, VALU and HBM time of its algorithmic work) over
+    the measured step time.  Phases without an algorithmic count are listed
+    with their time and a roof of zero."""
+    counts = phase_counts(hp, prec)
+    peak_m = PEAK["mfma_bf16"] if prec == "bf16" else PEAK["mfma_fp32"]
+    per, roof_sum, t_sum = {}, 0.0, 0.0
+    for k, (ms_total, calls) in phases.items():
+        ms = ms_total / steps
+        t_sum += ms
+        if k in counts:
+            fm, fv, be, ba = counts[k]
+            roof = max(fm * n_edges / peak_m, fv * n_edges / PEAK["alu_fp32"],
+                       (be * n_edges + ba * n_atoms) / PEAK["hbm"]) * 1e3
+        else:
+            roof = 0.0
+        roof_sum += roof
+        per[k] = {"ms": round(ms, 4), "roof_ms": round(roof, 4), "frac": round(roof / ms, 4) if ms > 0 else None}
+    return {"sum_roof_ms": round(roof_sum, 4), "step_ms": round(t_sum, 4),
+            "frac": round(roof_sum / t_sum, 4) if t_sum > 0 else None, "phases": per}
+
+
 def roofline_entry(phases, hp, n_edges, prec, n_atoms):
     """Roofline of the edge kernel with the largest share of the step, plus
     the same figures for every specialised edge kernel."""
@@ -149,31 +200,87 @@ def roofline_entry(phases, hp, n_edges, prec, n_atoms):
     return top
 
 
-def cpu_baseline(s, hp, blob, K, radius):
-    """FP64 oracle on one non-periodic cluster cut from the same box.
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
-    Energies are summed over the atoms within radius - K r_c of the center
-    (their environments are complete); the forces of atoms within
-    radius - 2 K r_c are then exact full-system forces."""
-    import oracle
+
+def _force_errors(F, Fref):
+    d = F - Fref
+    ref_rms = float(np.sqrt(np.mean(Fref ** 2)))
+    rms = float(np.sqrt(np.mean(d ** 2)))
+    return {"rms": rms, "max": float(np.abs(d).max()), "ref_rms": ref_rms,
+            "rel_rms": rms / ref_rms if ref_rms > 0 else None}
+
+
+def errors_vs_fp64(name, model, prec, F, atom_e, K, dev):
+    """Errors of one form against stored FP64 oracle values (written by
+    tests/golden/make_golden.py from the oracle alone).  bulk1m: the atoms of
+    eight local clusters whose oracle energies (about 7,900) and forces
+    (about 180) equal the full-box values; bulk32k: a 32,768-atom periodic
+    box with the same potential, every atom, energy, forces and stress."""
+    import torch
+    out = {}
+    if name == "bulk1m":
+        path = os.path.join(GOLDEN, "bulk1m_clusters.npz")
+        if os.path.exists(path):
+            g = np.load(path)
+            dE = np.abs(atom_e[g["energy_index"]] - g["atom_energy"])
+            fe = _force_errors(F[g["force_index"]], g["forces"])
+            fe["atoms"] = int(g["force_index"].size)
+            out["bulk1m_clusters"] = {"atom_energy_abs_mean_eV": float(dE.mean()),
+                                      "atom_energy_abs_max_eV": float(dE.max()),
+                                      "atoms_energy": int(dE.size), "forces_eV_per_A": fe}
+    path = os.path.join(GOLDEN, "bulk32k_K2.npz")
+    if os.path.exists(path) and model.hp == W.HP_BULK and K == 2:
+        g = np.load(path)
+        sb = W.bulk_system(32, 311, 312)
+        pos = torch.tensor(sb.positions, dtype=torch.float64, device=dev)
+        sp = torch.tensor(sb.species, dtype=torch.int32, device=dev)
+        o = model.evaluate(pos, sp, sb.cell, sb.pbc, K=K, precision=prec)
+        vol = float(abs(np.linalg.det(sb.cell)))
+        Wg = o["virial"].cpu().numpy().reshape(3, 3)
+        dW = np.abs(Wg - g["virial"]).max() / vol
+        out["bulk32k"] = {"n_atoms": sb.n_atoms,
+                          "energy_abs_per_atom_eV": abs(float(o["energy"].cpu()[0]) - float(g["energy"])) / sb.n_atoms,
+                          "forces_eV_per_A": _force_errors(o["forces"].cpu().numpy(), g["forces"]),
+                          "stress_abs_max_eV_per_A3": float(dW),
+                          "stress_ref_max_eV_per_A3": float(np.abs(g["virial"]).max() / vol)}
+    return out
+
+
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    center = s.n_atoms // 2 + 17
-    lp, ls, n_in, gi, c = oracle.local_cluster(s.positions, s.species, s.cell, center, radius,
-                                               radius - K * hp.r_cut)
-    t0 = time.time()
-    res = oracle.evaluate(lp, ls, np.eye(3), [False] * 3, blob, hp, K=K, n_owned=n_in)
-    dt = time.time() - t0
-    dist = np.linalg.norm(lp - lp[c], axis=1)
-    exact = np.flatnonzero(dist <= radius - 2 * K * hp.r_cut)
-    return {"value": round(lp.shape[0] / dt, 3), "unit": "atom-steps/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{lp.shape[0]}-atom non-periodic cluster (radius {radius:g} A) cut from the "
-                      f"same box, FP64 energy+forces of all its atoms, {dt:.1f} s"}, \
-        (gi[exact], res.forces[exact])
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(hp, blob, K, n_side):
+    """The FP64 oracle on a periodic n_side^3 box of the same lattice,
+    density, species mix and potential (every atom fully coordinated, as in
+    the 1M-atom box): neighbour list, forward and analytic backward, timed
+    with BLAS on all host cores and again on one core."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    sb = W.bulk_system(n_side, 321, 322)
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+
+    def run():
+        t0 = time.time()
+        oracle.evaluate(sb.positions, sb.species, sb.cell, sb.pbc, blob, hp, K=K)
+        return time.time() - t0
+
+    dt_all = run()
+    with threadpool_limits(limits=1):
+        dt_one = run()
+    return {"value": round(sb.n_atoms / dt_all, 3), "unit": "atom-steps/s", "cores": int(threads),
+            "kind": "oracle", "value_1core": round(sb.n_atoms / dt_one, 3), "cpu_model": _cpu_model(),
+            "host_cpus": os.cpu_count(),
+            "sample": f"{sb.n_atoms}-atom periodic box ({n_side}^3 jittered lattice, the same density, species "
+                      f"mix and potential as the workload), FP64 energy+forces+virial of every atom: "
+                      f"{dt_all:.1f} s on {threads} BLAS threads, {dt_one:.1f} s on 1"}
 
 
 def main():
@@ -184,7 +291,7 @@ def main():
     ap.add_argument("--workload", default="bulk1m")
     ap.add_argument("--precisions", default="bf16,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cluster-radius", type=float, default=24.0)
+    ap.add_argument("--cpu-box", type=int, default=12, help="side of the periodic box the oracle is timed on")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device to device once before the steps (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -192,6 +299,8 @@ def main():
                     help="also time this many on-device MD steps (first precision; 0: skip)")
     ap.add_argument("--depth-steps", type=int, default=5,
                     help="also time the 13,824-atom box at K=6 and K=2 of one 6-layer weight set (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=10,
+                    help="also time this many evaluations of 512 independent small cells (0: skip)")
     ap.add_argument("--partitioned-steps", type=int, default=2,
                     help="also time this many evaluations of the 8M-atom box as 8 slab partitions (0: skip)")
     args = ap.parse_args()
@@ -227,17 +336,20 @@ def main():
 
     base = {}
     if not args.no_cpu_baseline:
-        log("cpu baseline (FP64 oracle on a cluster) ...")
-        base, exact = cpu_baseline(s, hp, blob, K, args.cluster_radius)
-        log(f"cpu baseline: {base['value']} atom-steps/s on {base['cores']} threads")
+        log("cpu baseline (FP64 oracle on a periodic box) ...")
+        base = cpu_baseline(hp, blob, K, args.cpu_box)
+        log(f"cpu baseline: {base['value']} atom-steps/s on {base['cores']} threads, "
+            f"{base['value_1core']} on 1")
     results = {}
     precs = [p for p in args.precisions.split(",") if p]
     for prec in precs:
-        o = model.evaluate(pos_sets[0], species, s.cell, s.pbc, K=K, precision=prec)
+        o = model.evaluate(pos_sets[0], species, s.cell, s.pbc, K=K, precision=prec, atom_energy=True)
         n_edges = o["n_edges"]
         cap = int(n_edges * 1.02) + 4096
         F0 = o["forces"].cpu().numpy()
         E0 = float(o["energy"].cpu()[0])
+        errors = errors_vs_fp64(args.workload, model, prec, F0, o["atom_energy"].cpu().numpy(), K, dev)
+        del o
         outs = [model.evaluate(p, species, s.cell, s.pbc, K=K, precision=prec, max_edges=cap)
                 for p in pos_sets]
         for k in range(args.warmup):
@@ -260,12 +372,9 @@ def main():
         log(f"{prec}: {ms:.3f} ms/step, {n_edges} edges")
         r = {"ms_per_step": round(ms, 4), "value": round(N / (ms * 1e-3), 1), "n_edges": n_edges,
              "energy": E0, "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tm.items()},
-             "roofline": roofline_entry(tm, hp, n_edges, prec, N)}
-        if base:
-            gi, Fx = exact
-            d = F0[gi] - Fx
-            r["force_err_vs_fp64"] = {"rms": float(np.sqrt(np.mean(d ** 2))), "max": float(np.abs(d).max()),
-                                      "ref_rms": float(np.sqrt(np.mean(Fx ** 2))), "atoms": int(gi.size)}
+             "roofline": roofline_entry(tm, hp, n_edges, prec, N),
+             "step_roofline": step_roofline(tm, args.steps, hp, n_edges, prec, N),
+             "errors_vs_fp64": errors}
         results[prec] = r
 
     head = precs[0]
@@ -297,30 +406,57 @@ def main():
     depth = None
     if args.depth_steps > 0:
         # message-passing depth pruning: the same 6-layer weight set evaluated
-        # to K = 6 and truncated to K = 2 (13,824-atom box, l_max = 2, C = 64)
+        # to K = 6 and truncated to K = 2 (13,824-atom box, l_max = 2, C = 64).
+        # K = 2 runs the specialised first- and last-layer kernels only, K = 6
+        # adds four middle layers on the generic kernels, so K6/K2 mixes depth
+        # with the kernel-class gap; the per-layer times and a run with the
+        # generic kernels for every layer (K2_generic) separate the two
         sd, hpd = W.mpdp_system(), W.HP_MPDP
-        modeld = M.Model(hpd, W.make_weights(hpd, W.WEIGHT_SEEDS["mpdp"]))
+        blobd = W.make_weights(hpd, W.WEIGHT_SEEDS["mpdp"])
+        modeld = M.Model(hpd, blobd)
+        os.environ["MPIP_FORCE_GENERIC"] = "1"
+        modelg = M.Model(hpd, blobd)
+        del os.environ["MPIP_FORCE_GENERIC"]
         pd = torch.tensor(sd.positions, dtype=torch.float64, device=dev)
         spd = torch.tensor(sd.species, dtype=torch.int32, device=dev)
         depth = {"metric": "ms per E+F evaluation of a 13,824-atom box, one 6-layer weight set run to K layers",
-                 "n_atoms": sd.n_atoms, "steps": args.depth_steps}
+                 "n_atoms": sd.n_atoms, "steps": args.depth_steps,
+                 "note": "K=2 uses the specialised first/last-layer kernels, K=6 adds 4 generic middle layers: "
+                         "K6_over_K2 includes that kernel-class gap; K6_over_K2_generic compares K=6 with K=2 "
+                         "run on the generic kernels; layers_ms splits each run by layer (edge kernels)"}
+
+        def timed(mdl, Kd, prec):
+            o = mdl.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec)
+            cap = int(o["n_edges"] * 1.02) + 4096
+            mdl.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec, max_edges=cap, out=o, check=False)
+            M.lib.mpip_timing_enable(mdl._h, 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.depth_steps):
+                mdl.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec, max_edges=cap, out=o, check=False)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.depth_steps * 1e3
+            tm = M.read_timing(mdl)
+            M.lib.mpip_timing_enable(mdl._h, 0)
+            layers = {}
+            for k, (tot, _) in tm.items():
+                if k.startswith("edge_"):
+                    t = int(k.rsplit("_t", 1)[1])
+                    layers[f"t{t}"] = round(layers.get(f"t{t}", 0.0) + tot / args.depth_steps, 3)
+            return round(ms, 3), layers
+
         for prec in precs:
             row = {}
-            for Kd in (6, 2):
-                o = modeld.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec)
-                cap = int(o["n_edges"] * 1.02) + 4096
-                modeld.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec, max_edges=cap, out=o, check=False)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(args.depth_steps):
-                    modeld.evaluate(pd, spd, sd.cell, sd.pbc, K=Kd, precision=prec, max_edges=cap, out=o,
-                                    check=False)
-                torch.cuda.synchronize()
-                row[f"K{Kd}_ms"] = round((time.perf_counter() - t0) / args.depth_steps * 1e3, 3)
+            row["K6_ms"], l6 = timed(modeld, 6, prec)
+            row["K2_ms"], l2 = timed(modeld, 2, prec)
+            row["K2_generic_ms"], l2g = timed(modelg, 2, prec)
             row["K6_over_K2"] = round(row["K6_ms"] / row["K2_ms"], 2)
+            row["K6_over_K2_generic"] = round(row["K6_ms"] / row["K2_generic_ms"], 2)
+            row["layers_ms"] = {"K6": l6, "K2": l2, "K2_generic": l2g}
             depth[prec] = row
-            log(f"depth pruning ({prec}): K=6 {row['K6_ms']} ms, K=2 {row['K2_ms']} ms")
-        del modeld, pd, spd
+            log(f"depth pruning ({prec}): K=6 {row['K6_ms']} ms, K=2 {row['K2_ms']} ms, "
+                f"K=2 generic {row['K2_generic_ms']} ms")
+        del modeld, modelg, pd, spd
     part = None
     if args.partitioned_steps > 0:
         # one-GPU partitioned mode: the whole 200^3 box in 8 slabs along x,
@@ -372,7 +508,54 @@ def main():
             nl_bfs = int(M.bfs_share(p8, sp8, s8.cell, n_parts, 0, Kh, hp8.r_cut)[0].shape[0])
             hg[f"K{Kh}"] = {"geometric": round((nl_geo - no) / no, 4), "graph": round((nl_bfs - no) / no, 4)}
         part["halo_growth_vs_K"] = hg
+        # one GPU's share of the 8M box (slab 0 of 8: 1M roots) with a halo of
+        # K r_cut, evaluated (trimmed) at K = 2 and K = 6 of the 6-layer weights
+        shares = {}
+        for Kh in (2, 6):
+            gp, gs, _, no = M.slab_share(p8, sp8, s8.cell, n_parts, 0, Kh * hp8.r_cut)
+            pbc_s = (False, True, True)
+            o = model8.evaluate(gp, gs, s8.cell, pbc_s, K=Kh, precision=head, n_owned=no)
+            cap = int(o["n_edges"] * 1.02) + 4096
+            reps = 3 if Kh == 2 else 1
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                model8.evaluate(gp, gs, s8.cell, pbc_s, K=Kh, precision=head, n_owned=no, max_edges=cap, out=o)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            shares[f"K{Kh}"] = {"ms": round(ms, 3), "rows": int(gp.shape[0]), "roots": no,
+                                "root_atom_steps_per_s": round(no / (ms * 1e-3), 1), "steps": reps}
+            log(f"share of the 8M box, K={Kh} ({head}): {ms:.1f} ms, {gp.shape[0]} rows")
+            del gp, gs, o
+        part["share_K2_vs_K6"] = shares
         del model8, p8, sp8, o8, og
+    batch = None
+    if args.batch_steps > 0:
+        # 512 independent periodic cells of 8-512 atoms (l_max = 2, C = 64,
+        # K = 2) in one pass of every kernel over the block-diagonal list
+        structs = W.batch_structures()
+        hpb = W.HP_BATCH
+        modelb = M.Model(hpb, W.make_weights(hpb, W.WEIGHT_SEEDS["batch512"]))
+        bt = M.Batch(structs, dev)
+        batch = {"metric": "atom-steps/s of 512 independent periodic cells (8-512 atoms, l_max=2, C=64, K=2) "
+                           "evaluated together", "n_structures": bt.B, "n_atoms": bt.n_atoms,
+                 "steps": args.batch_steps}
+        for prec in precs:
+            o = M.evaluate_batch(modelb, bt, K=2, precision=prec)
+            cap = int(o["n_edges"] * 1.02) + 4096
+            M.evaluate_batch(modelb, bt, K=2, precision=prec, max_edges=cap, check=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.batch_steps):
+                M.evaluate_batch(modelb, bt, K=2, precision=prec, max_edges=cap, check=False)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.batch_steps * 1e3
+            batch[prec] = {"ms_per_step": round(ms, 4), "value": round(bt.n_atoms / (ms * 1e-3), 1),
+                           "n_edges": o["n_edges"]}
+            log(f"batch512 ({prec}): {ms:.3f} ms per step")
+        if "bf16" in batch and "fp32" in batch:
+            batch["bf16_speedup_over_fp32"] = round(batch["fp32"]["ms_per_step"] / batch["bf16"]["ms_per_step"], 3)
+        del modelb, bt
     line = {"metric": METRIC, "value": results[head]["value"], "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": results[head]["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,
@@ -387,7 +570,8 @@ def main():
             "forms": results,
             "md": md,
             "depth_pruning": depth,
-            "partitioned": part}
+            "partitioned": part,
+            "batch512": batch}
     if "bf16" in results and "fp32" in results:
         line["bf16_speedup_over_fp32"] = round(results["fp32"]["ms_per_step"] / results["bf16"]["ms_per_step"], 3)
     print(json.dumps(line))

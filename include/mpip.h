@@ -55,8 +55,16 @@ typedef enum {
 
 typedef enum {
   MPIP_FP32 = 0,           /* all arithmetic in FP32 (FP32 MFMA for the dense contractions)       */
-  MPIP_BF16_MIXED = 1      /* radial MLP and channel mixing as BF16 MFMA with FP32 accumulation;
-                              tensor products, geometry in FP32; displacements and sums in FP64   */
+  MPIP_BF16_MIXED = 1      /* radial MLP and channel mixing as BF16 MFMA with FP32 accumulation.
+                              In the specialised first and last layers (64 or 128 channels) the
+                              tensor-product contractions also run on BF16 MFMA with BF16 operands
+                              and FP32 accumulation (first layer: Q = a2 (x) YC and its adjoint;
+                              last layer: X = ht . YC, dE/dYC and the sender-side pull), and the
+                              last layer's ht and per-edge messages are stored in BF16; generic
+                              (middle) layers form the tensor product on the VALU in FP32.
+                              Geometry (basis, harmonics) in FP32; r_e is the FP64 displacement
+                              rounded to FP32 (also in the virial); energy, force and virial
+                              sums in FP64                                                        */
 } mpip_precision;
 
 typedef struct {

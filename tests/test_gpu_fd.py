@@ -1,0 +1,85 @@
+"""Finite differences of the GPU energy against the GPU adjoint.
+
+MPIPEnergy's gradient (the hand-written adjoint behind torch.autograd) is
+compared with central differences of the energy that the same library
+computes, in the FP32 form, on the 128-atom box (generic kernels, C = 32,
+l_max = 1) and on a 216-atom box of the 1M-atom workload's potential
+(specialised first- and last-layer kernels, C = 128, l_max = 2).  Five-point
+stencils: along the force direction (a large, well-resolved slope, so the
+comparison is at FP32 resolution) and for single components of three atoms.
+The strain derivative checks the virial the same way: W = -dE/d(eps) for the
+homogeneous diagonal strain x -> (I + eps) x of positions and cell."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def M(torch):
+    import paper_2509_21694_amd as m
+    return m
+
+
+CASES = {"small_C32": (lambda: W.small_system(), W.HP_SMALL, W.WEIGHT_SEEDS["small"]),
+         "bulk216_C128": (lambda: W.bulk_system(6, 631, 632), W.HP_BULK, W.WEIGHT_SEEDS["bulk1m"])}
+
+
+def stencil5(f, h):
+    return (-f(2 * h) + 8 * f(h) - 8 * f(-h) + f(-2 * h)) / (12 * h)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_adjoint_against_finite_differences(torch, M, case):
+    mk, hp, seed = CASES[case]
+    s = mk()
+    model = M.Model(hp, W.make_weights(hp, seed))
+    dev = torch.device("cuda", 0)
+    pos = torch.tensor(s.positions, dtype=torch.float64, device=dev)
+    sp = torch.tensor(s.species, dtype=torch.int32, device=dev)
+    x = pos.clone().requires_grad_(True)
+    E, Wv = M.energy(x, model, sp, s.cell, s.pbc, K=2, precision="fp32")
+    E.backward()
+    grad = x.grad.detach().cpu().numpy()            # dE/dx = -F
+    x0 = s.positions.copy()
+
+    def energy_at(xn, cell=s.cell):
+        o = model.evaluate(torch.tensor(xn, dtype=torch.float64, device=dev), sp, cell, s.pbc, K=2,
+                           precision="fp32")
+        return float(o["energy"].cpu()[0])
+
+    # along the force direction: slope -|F|
+    v = -grad / np.linalg.norm(grad)
+    fd = stencil5(lambda t: energy_at(x0 + t * v), 1e-2)
+    an = float(np.sum(grad * v))
+    print(f"{case}: directional dE/dt FD {fd:.8e} adjoint {an:.8e} rel {abs(fd - an) / abs(an):.2e}")
+    assert abs(fd - an) <= 1e-3 * abs(an)
+    # single components of the atoms with the largest forces
+    for a in np.argsort(-np.linalg.norm(grad, axis=1))[:3]:
+        for k in range(3):
+            e = np.zeros_like(x0)
+            e[a, k] = 1.0
+            fdk = stencil5(lambda t: energy_at(x0 + t * e), 1e-2)
+            print(f"  atom {a} dim {k}: FD {fdk:.6e} adjoint {grad[a, k]:.6e}")
+            assert abs(fdk - grad[a, k]) <= 2e-2 * np.abs(grad[a]).max() + 2e-6
+    # virial: W = -dE/d(eps) for x -> (I + eps) x, cell -> cell (I + eps)^T
+    # (diagonal strains: the library takes orthorhombic cells)
+    Wg = Wv.detach().cpu().numpy().reshape(3, 3)
+    for (p, q) in ((0, 0), (1, 1), (2, 2)):
+        def e_strain(t):
+            D = np.eye(3)
+            D[p, q] += t
+            return energy_at(x0 @ D.T, s.cell @ D.T)
+        fdw = -stencil5(e_strain, 1e-3)
+        print(f"  virial[{p},{q}]: FD {fdw:.6e} adjoint {Wg[p, q]:.6e}")
+        assert abs(fdw - Wg[p, q]) <= 1e-3 * max(np.abs(Wg).max(), 1e-3)
