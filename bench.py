@@ -61,11 +61,11 @@ def workload(name):
 
 
 def phase_counts(hp, prec):
-    """Algorithmic work of the specialised first/last-layer edge kernels, per
-    directed edge and per atom, for the formulation they implement (live
-    paths only, nothing recomputed is counted): {phase: (mfma_flop/edge,
-    valu_flop/edge, bytes/edge, bytes/atom)}.  Bytes are each array read or
-    written once per launch (unique bytes, not per-edge gathers)."""
+    """Algorithmic work of the step's phases, per directed edge and per atom,
+    for the formulation they implement (live paths only, nothing recomputed
+    is counted): {phase: (mfma_flop/edge, valu_flop/edge, bytes/edge,
+    bytes/atom[, mfma_flop/atom])}.  Bytes are each array read or written
+    once per launch (unique bytes, not per-edge gathers)."""
     C, L, H, nb, S = hp.channels, hp.l_max, hp.radial_hidden, hp.n_basis, hp.n_species
     nlm, P = (L + 1) ** 2, L + 1
     fb = 2 if prec == "bf16" else 4            # storage of Q/P and h~ in the form
@@ -108,10 +108,10 @@ def phase_counts(hp, prec):
         KQ = 64 * S
         zq = 2.0 * KQ * (C * (1 + L) + (nlm - 1) * C)
         up = 2.0 * nlm * C * C
-        d["node_fused"] = (2 * (zq + up), 0.0, 0, 3 * nlm * KQ * 2 + 4 * C + 2 * nlm * C * 2)
+        d["node_fused"] = (0.0, 0.0, 0, 3 * nlm * KQ * 2 + 4 * C + 2 * nlm * C * 2, 2 * (zq + up))
         # last-layer node update and its adjoint: A and h_0 read, dE/dA written over A,
         # E_i written; z_0 = W_down^T A and dE/dA = W_down z-bar on MFMA
-        d["node_last"] = (2 * 2.0 * C * C, 0.0, 0, 3 * 4 * C + 8)
+        d["node_last"] = (0.0, 0.0, 0, 3 * 4 * C + 8, 2 * 2.0 * C * C)
     # neighbour list: positions and species read, the sorted copies, permutation
     # and row pointers written per atom; sender, shift, vector and reverse index
     # written per edge
@@ -125,9 +125,9 @@ def kernel_roofline(name, t, hp, prec, n_edges, n_atoms):
     counts = phase_counts(hp, prec)
     if name not in counts:
         return None
-    fm, fv, be, ba = counts[name]
+    fm, fv, be, ba, fma = (tuple(counts[name]) + (0.0,))[:5]
     peak_m = PEAK["mfma_bf16"] if prec == "bf16" else PEAK["mfma_fp32"]
-    work = {"mfma": fm * n_edges, "alu": fv * n_edges, "hbm": be * n_edges + ba * n_atoms}
+    work = {"mfma": fm * n_edges + fma * n_atoms, "alu": fv * n_edges, "hbm": be * n_edges + ba * n_atoms}
     peak = {"mfma": peak_m, "alu": PEAK["alu_fp32"], "hbm": PEAK["hbm"]}
     times = {k: work[k] / peak[k] for k in work}
     bound = max(times, key=times.get)
@@ -172,8 +172,8 @@ def step_roofline(phases, steps, hp, n_edges, prec, n_atoms):
         ms = ms_total / steps
         t_sum += ms
         if k in counts:
-            fm, fv, be, ba = counts[k]
-            roof = max(fm * n_edges / peak_m, fv * n_edges / PEAK["alu_fp32"],
+            fm, fv, be, ba, fma = (tuple(counts[k]) + (0.0,))[:5]
+            roof = max((fm * n_edges + fma * n_atoms) / peak_m, fv * n_edges / PEAK["alu_fp32"],
                        (be * n_edges + ba * n_atoms) / PEAK["hbm"]) * 1e3
         else:
             roof = 0.0

@@ -69,6 +69,10 @@ class MdParamsC(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python paper_2509_21694_amd/build.py`")
+    # PyTorch ships its own HIP runtime under the same soname: loading it
+    # first makes the library bind to that runtime, so the process holds one
+    # HIP runtime whose streams and memory both sides share
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, SZ, V = ctypes.POINTER, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
     lib.mpip_weights_count.argtypes = [P(HParamsC)]

@@ -103,11 +103,43 @@ __device__ __forceinline__ void sincos_0pi(float t, float* s, float* c) {
   *c = up ? -pc : pc;
 }
 
+// Per-kernel constants of the geometry (cutoff, basis normalisation,
+// envelope polynomial), formed once per wave from r_c and p and kept in
+// scalar registers.
+struct GeoK {
+  float irc;        // 1 / r_c
+  float pi_irc;     // pi / r_c
+  float pref;       // sqrt(2 / r_c)
+  float ea, eb, ec; // envelope 1 - ea x^p + eb x^(p+1) - ec x^(p+2)
+  float da, db, dc; // its derivative in d: (-da x^(p-1) + db x^p - dc x^(p+1))
+  int p;
+};
+
+__device__ __forceinline__ float sgpr_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+__device__ __forceinline__ GeoK geo_consts(float rc, int p) {
+  GeoK k;
+  const float irc = 1.0f / rc;
+  const float a = 0.5f * (p + 1) * (p + 2), b = (float)(p * (p + 2)), c = 0.5f * p * (p + 1);
+  k.irc = sgpr_f(irc);
+  k.pi_irc = sgpr_f(3.14159265358979f * irc);
+  k.pref = sgpr_f(sqrtf(2.0f * irc));
+  k.ea = sgpr_f(a); k.eb = sgpr_f(b); k.ec = sgpr_f(c);
+  k.da = sgpr_f(a * p * irc); k.db = sgpr_f(b * (p + 1) * irc); k.dc = sgpr_f(c * (p + 2) * irc);
+  k.p = __builtin_amdgcn_readfirstlane(p);
+  return k;
+}
+
 // Tail lanes of a tile (valid == false) evaluate a unit vector along x and
-// are zeroed at the end, so the code has no divergent branch.  The cutoff
-// enters through 1/r_c (one division per kernel, hoisted out of the loops);
-// the Bessel argument pi d / r_c lies in [0, pi] for every edge.
-__device__ __forceinline__ void edge_geometry(float4 v, bool valid, float rc, int p, Geo& g) {
+// are zeroed at the end, so the code has no divergent branch.  The Bessel
+// argument pi d / r_c lies in [0, pi] for every edge; sin(n t), cos(n t)
+// follow from the Chebyshev recurrence, and with A = sqrt(2/r_c) / d
+//   basis_n  = f A sin(n t)
+//   dbasis_n = f' A sin(n t) + f A (n pi / r_c cos(n t) - sin(n t) / d)
+//            = A (f' - f / d) sin(n t) + n (f A pi / r_c) cos(n t).
+__device__ __forceinline__ void edge_geometry(float4 v, bool valid, const GeoK& k, Geo& g) {
   const float vx = valid ? v.x : 1.f, vy = valid ? v.y : 0.f, vz = valid ? v.z : 0.f;
   // |v| and 1/|v| from the hardware reciprocal square root (about 1 ulp)
   const float d2 = vx * vx + vy * vy + vz * vz;
@@ -122,29 +154,29 @@ __device__ __forceinline__ void edge_geometry(float4 v, bool valid, float rc, in
   g.Y[4] = msk * s15 * x * y; g.Y[5] = msk * s15 * y * z; g.Y[6] = msk * 0.5f * s5 * (3.f * z * z - 1.f);
   g.Y[7] = msk * s15 * x * z; g.Y[8] = msk * 0.5f * s15 * (x * x - y * y);
   // polynomial envelope of order p (zero from r_c on)
-  const float irc = 1.0f / rc;
-  const float xr = d * irc;
-  const float a = 0.5f * (p + 1) * (p + 2), b = (float)(p * (p + 2)), c = 0.5f * p * (p + 1);
+  const float xr = d * k.irc;
   float xp1 = 1.f;  // x^(p-1)
-  for (int k = 0; k < p - 1; ++k) xp1 *= xr;
+  for (int q = 0; q < k.p - 1; ++q) xp1 *= xr;
   const float xp = xp1 * xr, xq = xp * xr, xs = xq * xr;
   const float in = (valid && xr < 1.f) ? 1.f : 0.f;
-  const float env = in * (1.f - a * xp + b * xq - c * xs);
-  const float denv = in * (-a * p * xp1 + b * (p + 1) * xp - c * (p + 2) * xq) * irc;
-  // Bessel basis via the Chebyshev recurrence for sin(n t), cos(n t)
-  const float pref = sqrtf(2.0f * irc);
-  const float th = fminf(3.14159265358979f * xr, 3.14159265358979f);
+  const float env = in * (1.f - k.ea * xp + k.eb * xq - k.ec * xs);
+  const float denv = in * (-k.da * xp1 + k.db * xp - k.dc * xq);
+  const float th = fminf(d * k.pi_irc, 3.14159265358979f);
   float s1, c1;
   sincos_0pi(th, &s1, &c1);
-  float sp = 0.f, cp = 1.f, sn = s1, cn = c1;
+  const float A = k.pref * inv;
+  const float E1 = env * A;
+  const float F1 = A * (denv - env * inv);
+  const float F2 = E1 * k.pi_irc;
+  const float tc = 2.f * c1;
+  float sp = 0.f, cp = 1.f, sn = s1, cn = c1, nF2 = F2;
 #pragma unroll
   for (int n = 1; n <= kNB; ++n) {
-    const float B = pref * sn * inv;
-    const float dB = pref * ((float)n * th * cn - sn) * inv * inv;
-    g.basis[n - 1] = env * B;
-    g.dbasis[n - 1] = denv * B + env * dB;
-    const float sx = 2.f * c1 * sn - sp, cx = 2.f * c1 * cn - cp;
+    g.basis[n - 1] = E1 * sn;
+    g.dbasis[n - 1] = fmaf(F1, sn, nF2 * cn);
+    const float sx = fmaf(tc, sn, -sp), cx = fmaf(tc, cn, -cp);
     sp = sn; cp = cn; sn = sx; cn = cx;
+    nF2 += F2;
   }
 }
 

@@ -788,7 +788,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   auto fast_layer = [&](int t) {
     const int kind = kind_of(t);
     if (!fast_cl) return false;
-    if (kind == KIND_FIRST) return S * nlm <= 64;
+    if (kind == KIND_FIRST) return S <= 4;   // species-factorised kernels: S <= 4
     return kind == KIND_LAST;
   };
   const int KQ = 64 * S;

@@ -54,6 +54,7 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
   __shared__ float syc[kTileE * NYC];
   __shared__ int sj[kTileE];
   if (edges_total(a) > a.capacity || a.status[ST_FLAGS] != 0) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const int lane = threadIdx.x;
   const int eg = lane / CW, cl = lane % CW;
   for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(64) void k_edge_fwd(EdgeArgs a) {
       const bool valid = e < e1;
       Geo geo;
       float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, a.rc, a.envelope_p, geo);
+      edge_geometry(v, valid, gk, geo);
       if (lane < kTileE) {
         sj[el] = valid ? (SPECIES_IN ? __float_as_int(v.w) : a.e_src[e]) : -1;
         // YC[p][m1][m3] = sum_m2 C_p[m1][m2][m3] Y[l2 m2]
@@ -173,6 +174,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
   __shared__ float seb[kTileE * kNB];
   __shared__ int sj[kTileE];
   if (edges_total(a) > a.capacity || a.status[ST_FLAGS] != 0) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const int lane = threadIdx.x;
   const int eg = lane / CW, cl = lane % CW;
   const int g = lane >> 4, el = lane & 15;
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(64) void k_edge_bwd(EdgeArgs a) {
       const bool valid = e < e1;
       Geo geo;
       float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, a.rc, a.envelope_p, geo);
+      edge_geometry(v, valid, gk, geo);
       const int jme = valid ? (SPECIES_IN ? __float_as_int(v.w) : a.e_src[e]) : -1;
       __syncthreads();
       if (lane < kTileE) {

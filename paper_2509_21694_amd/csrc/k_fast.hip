@@ -265,17 +265,28 @@ __device__ __forceinline__ void mlp_backward_ds(const f32x4* ab2, const DsPack& 
 // ============================================================ first layer
 
 // Workgroups of NW waves, each wave walking its own rows (row_walk); the
-// MLP weights sit in LDS in the BF16 form.  The per-tile harmonics table is
-// exchanged between the lanes of a wave through a wave-private LDS slice.
-template <int PREC, int L, int MQ, int NW>
+// MLP weights sit in LDS in the BF16 form.  The per-tile harmonics and
+// sender species are exchanged between the lanes of a wave through a
+// wave-private LDS slice.
+//
+// Rows of Q and P: the (species s, degree-order lm) pairs, numbered
+// q = lm S + s, so that Q_i[lm][s * 64 + k] = Q_i[q][k] (row q of 64 hidden
+// values, contiguous).  S <= 4.
+//
+// Forward: Q_i[q][k] = sum_e Ysel_e[q] a2_e[k], as D tiles (hidden 16 nt +
+// 4 g + r) x (q = 16 qt + lane % 16): the layer-2 activations in edges x
+// features layout are directly the A operand (rows hidden, k = edges), and
+// each lane stores 4 consecutive hidden values of one row q.
+template <int PREC, int L, int S, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 1))) void k_l1_fwd(FastArgs a) {
   typedef Op<PREC> O;
-  constexpr int NLM = (L + 1) * (L + 1);
+  constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, MROWS = S * NLM, MQ = (MROWS + 15) / 16;
   constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
   __shared__ typename O::T sM1[NM1], sM2[NM2];
   __shared__ float sY[NW][kTileE * NLM];
-  __shared__ int sS[NW][kTileE];
+  __shared__ __align__(16) int sS[NW][kTileE];
   if (fast_guard(a)) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NM1>(sM1, a.w1a);
@@ -285,21 +296,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* syc = sY[wv];
   int* ssp = sS[wv];
-  const int S = a.n_species, KQ = 64 * S, MROWS = S * NLM;
+  // the Q rows of this lane's columns: q = 16 qt + el = lm S + s
+  int qlm[MQ], qs[MQ];
+#pragma unroll
+  for (int qt = 0; qt < MQ; ++qt) {
+    const int q = 16 * qt + el;
+    qlm[qt] = q < MROWS ? q / S : 0;
+    qs[qt] = q < MROWS ? q - (q / S) * S : -2;   // -2 matches no sender (invalid edges carry -1)
+  }
   const RowWalk rw = row_walk<NW>(a.n);
   for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-    f32x4 q[MQ][4];
+    f32x4 q[4][MQ];
 #pragma unroll
-    for (int mt = 0; mt < MQ; ++mt)
+    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) q[mt][nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      for (int qt = 0; qt < MQ; ++qt) q[nt][qt] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int t0 = e0; t0 < e1; t0 += kTileE) {
       const int e = t0 + el;
       const bool valid = e < e1;
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, a.rc, a.envelope_p, geo);
+      edge_geometry(v, valid, gk, geo);
       if (g == 0) {
         float yc[NLM];
         yc_last<L>(cgd, geo.Y, yc);
@@ -339,67 +357,75 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         }
       }
       wave_lds_sync();
-      // Q^T[(s,lm), k] += sum_e Ysel[e, (s,lm)] a2[e, k]; a2 tile nt: edges 4g + r, hidden 16 nt + el
+      // Q[hidden][q] += sum_e a2[e][hidden] Ysel[e][q]: A = a2 tile nt (rows
+      // hidden 16 nt + el, k = edges 4 g + r), B = Ysel (k = edges 4 g + r, column q)
+      const int4 sp4 = *(const int4*)(ssp + 4 * g);
+      const int spr[4] = {sp4.x, sp4.y, sp4.z, sp4.w};
 #pragma unroll
-      for (int mt = 0; mt < MQ; ++mt) {
-        const int m = 16 * mt + el;
-        const int s = m / NLM, lm = m - s * NLM;
+      for (int qt = 0; qt < MQ; ++qt) {
         float ys[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int ee = 4 * g + r;
-          ys[r] = (m < MROWS && ssp[ee] == s) ? syc[ee * NLM + lm] : 0.f;
+          const float y = syc[(4 * g + r) * NLM + qlm[qt]];
+          ys[r] = (spr[r] == qs[qt]) ? y : 0.f;
         }
         if constexpr (PREC == 1) {
-          s16x4 av = {bfbits(ys[0]), bfbits(ys[1]), bfbits(ys[2]), bfbits(ys[3])};
+          const s16x4 bv = {bfbits(ys[0]), bfbits(ys[1]), bfbits(ys[2]), bfbits(ys[3])};
 #pragma unroll
           for (int nt = 0; nt < 4; ++nt) {
-            s16x4 bv = {bfbits(a2[nt][0]), bfbits(a2[nt][1]), bfbits(a2[nt][2]), bfbits(a2[nt][3])};
-            q[mt][nt] = mfma_bf16_k16(av, bv, q[mt][nt]);
+            const s16x4 av = {bfbits(a2[nt][0]), bfbits(a2[nt][1]), bfbits(a2[nt][2]), bfbits(a2[nt][3])};
+            q[nt][qt] = mfma_bf16_k16(av, bv, q[nt][qt]);
           }
         } else {
 #pragma unroll
           for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) q[mt][nt] = mfma_f32(ys[r], a2[nt][r], q[mt][nt]);
+            for (int r = 0; r < 4; ++r) q[nt][qt] = mfma_f32(a2[nt][r], ys[r], q[nt][qt]);
         }
       }
       wave_lds_sync();
     }
-    // Q_i[lm][s*64 + k]: D rows (s,lm) = 16 mt + 4 g + r, hidden k = 16 nt + el
+    // row q = 16 qt + el, hidden 16 nt + 4 g + r: four consecutive values per store
 #pragma unroll
-    for (int mt = 0; mt < MQ; ++mt)
+    for (int qt = 0; qt < MQ; ++qt) {
+      const int qq = 16 * qt + el;
+      if (qq < MROWS) {
+        const int64_t o = (int64_t)i * NLM * KQ + (int64_t)qq * 64 + 4 * g;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = 16 * mt + 4 * g + r;
-        if (m < MROWS) {
-          const int s = m / NLM, lm = m - s * NLM;
-          const int64_t o = ((int64_t)i * NLM + lm) * KQ + s * 64 + el;
+        for (int nt = 0; nt < 4; ++nt) {
           if constexpr (PREC == 1) {
-            __bf16* dst = (__bf16*)a.Q + o;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) dst[16 * nt] = (__bf16)q[mt][nt][r];
+            *(s16x4*)((__bf16*)a.Q + o + 16 * nt) = pk4_bf16(q[nt][qt]);
           } else {
-            float* dst = a.Q + o;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) dst[16 * nt] = q[mt][nt][r];
+            *(float4*)(a.Q + o + 16 * nt) = make_float4(q[nt][qt][0], q[nt][qt][1], q[nt][qt][2], q[nt][qt][3]);
           }
         }
       }
+    }
   }
 }
 
-template <int PREC, int L, int MQ, int NW>
+// Adjoint.  dE/da2_e[k] = sum_q P_i[q][k] Ysel_e[q] and dE/dYC_e[lm] =
+// sum_k P_i[(lm, s_e)][k] a2_e[k], both on MFMA with P_i as the A operand:
+//   pa (rows hidden 16 mt + lane % 16, k-slot (g, j) of chunk c = species
+//      4 (c / KCL) + g, lm = 8 (c % KCL) + j), against Ysel with the same
+//      slots, whose lm is known at compile time;
+//   pb (rows q = 16 mq + lane % 16, k = hidden in the operand permutation of
+//      the MLP), against the activations a2.
+// The row's P (BF16) is staged in a wave-private LDS slice, the next row's
+// loaded into registers while this row's tiles run.
+template <int PREC, int L, int S, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 2 : 1))) void k_l1_bwd(FastArgs a) {
   typedef Op<PREC> O;
-  constexpr int NLM = (L + 1) * (L + 1);
-  constexpr int KCQ = (PREC == 1) ? (MQ + 1) / 2 : 4 * MQ;   // k-chunks over the (s,lm) rows
+  constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, MROWS = S * NLM, MQ = (MROWS + 15) / 16;
+  constexpr int KCL = (PREC == 1) ? (NLM + 7) / 8 : NLM;   // chunks over lm per species group
+  constexpr int KCY = ((S + 3) / 4) * KCL;                  // chunks of the (s, lm) slots
   constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
   constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
   __shared__ typename O::T sM1[NM1], sM2[NM2], sB2[NB2], sB1[NB1];
   constexpr int SYB = 16 * MQ + 1;   // odd row stride: the 16 edge lanes hit distinct banks
   __shared__ float sYB[NW][kTileE * SYB];
   if (fast_guard(a)) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NM1>(sM1, a.w1a);
@@ -410,14 +436,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   }
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* syb = sYB[wv];
-  const int S = a.n_species, KQ = 64 * S, MROWS = S * NLM;
-  // BF16 form: the row's P (NLM x 64 S BF16) is staged in a wave-private LDS
-  // slice; the next row's P is loaded into registers while this row's tiles run
-  constexpr int PW = (PREC == 1) ? 16 * MQ * 64 : 8;      // BF16 elements, >= NLM * 64 S
-  constexpr int NPL = (PW / 8 + 63) / 64;                   // 16-byte pieces per lane
+  // BF16 form: P rows staged as [q][64] (q < 16 MQ, zero past MROWS) plus
+  // 4 zero rows, which the pa reads of species >= S may reach
+  constexpr int PW = (PREC == 1) ? 16 * MQ * 64 + 256 : 8;   // BF16 elements
+  constexpr int NPL = (PW / 8 + 63) / 64;                      // 16-byte pieces per lane
   __shared__ uint4 sPr[NW][PW / 8];
   const unsigned short* sPw = (const unsigned short*)sPr[wv];
-  const int pieces = NLM * KQ / 8;
+  constexpr int pieces = NLM * KQ / 8;
   const RowWalk rw = row_walk<NW>(a.n);
   uint4 praw[NPL];
   auto p_fetch = [&](int64_t row) {
@@ -446,51 +471,48 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
     p_stage();
     p_fetch(i + rw.step);
     const float* Pi = a.P + (int64_t)i * NLM * KQ;
-    auto Pval = [&](int m, int k) -> float {
-      if constexpr (PREC == 1) {
-        const int mm = m < MROWS ? m : 0;
-        const int s = mm / NLM, lm = mm - s * NLM;
-        const float v = __uint_as_float(((unsigned)sPw[lm * KQ + s * 64 + k]) << 16);
-        return m < MROWS ? v : 0.f;
-      } else {
-        if (m >= MROWS) return 0.f;
-        const int s = m / NLM, lm = m - s * NLM;
-        return Pi[lm * KQ + s * 64 + k];
-      }
-    };
-    // A operand of dE/da2^T = P^T Ysel^T: rows hidden 16 mt + el, k over (s,lm)
-    typename O::T pa[4][KCQ];
-    // A operand of dE/dYC^T = P a2^T: rows (s,lm) 16 mq + el, k over hidden (permuted)
+    typename O::T pa[4][KCY];
     typename O::T pb[MQ][O::KC64];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-      for (int kc = 0; kc < KCQ; ++kc) {
+      for (int c = 0; c < KCY; ++c) {
+        const int sg = c / KCL, lc = c % KCL;
         if constexpr (PREC == 1) {
+          // species 4 sg + g, lm = 8 lc + j, hidden 16 mt + el
+          const unsigned short* src = sPw + (4 * sg + g) * 64 + 16 * mt + el;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) pa[mt][kc][j] = (__bf16)Pval(32 * kc + 8 * g + j, 16 * mt + el);
+          for (int j = 0; j < 8; ++j) {
+            const int lm = 8 * lc + j;
+            pa[mt][c][j] = lm < NLM ? __builtin_bit_cast(__bf16, src[lm * KQ]) : (__bf16)0.f;
+          }
         } else {
-          pa[mt][kc] = Pval(4 * kc + g, 16 * mt + el);
+          const int sp_ = 4 * sg + g;
+          pa[mt][c] = sp_ < S ? Pi[lc * KQ + sp_ * 64 + 16 * mt + el] : 0.f;
         }
       }
 #pragma unroll
-    for (int mq = 0; mq < MQ; ++mq)
+    for (int mq = 0; mq < MQ; ++mq) {
+      const int qq = 16 * mq + el;
+      if constexpr (PREC == 1) {
+        const unsigned short* src = sPw + qq * 64 + 4 * g;
 #pragma unroll
-      for (int kc = 0; kc < O::KC64; ++kc) {
-        if constexpr (PREC == 1) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            pb[mq][kc][j] = (__bf16)Pval(16 * mq + el, 16 * (2 * kc + j / 4) + 4 * g + (j % 4));
-        } else {
-          pb[mq][kc] = Pval(16 * mq + el, 16 * (kc / 4) + 4 * g + (kc % 4));
+        for (int kc = 0; kc < O::KC64; ++kc) {
+          const uint2 lo = *(const uint2*)(src + 32 * kc), hi = *(const uint2*)(src + 32 * kc + 16);
+          pb[mq][kc] = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
         }
+      } else {
+#pragma unroll
+        for (int kc = 0; kc < O::KC64; ++kc)
+          pb[mq][kc] = qq < MROWS ? Pi[qq * 64 + 16 * (kc / 4) + 4 * g + (kc % 4)] : 0.f;
       }
+    }
     for (int t0 = e0; t0 < e1; t0 += kTileE) {
       const int e = t0 + el;
       const bool valid = e < e1;
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, a.rc, a.envelope_p, geo);
+      edge_geometry(v, valid, gk, geo);
       const int sp = valid ? __float_as_int(v.w) : -1;
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
@@ -501,38 +523,31 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
-      // Ysel^T operand for this lane's edge (column el): slot -> row m of (s, lm);
-      // the slot's row is a compile-time value per lane group, chosen by g
-      auto ysel_fixed = [&](int m) -> float {   // m known at compile time after unrolling
-        if (m >= MROWS) return 0.f;
-        const int s = m / NLM, lm = m - s * NLM;
-        return (s == sp) ? yc[lm] : 0.f;
-      };
-      typename O::T yb[KCQ];
+      // Ysel operand of this lane's edge (column el): slot (g, j) of chunk c
+      // is species 4 (c / KCL) + g, lm = 8 (c % KCL) + j (FP32: lm = c % KCL)
+      typename O::T yb[KCY];
 #pragma unroll
-      for (int kc = 0; kc < KCQ; ++kc) {
+      for (int c = 0; c < KCY; ++c) {
+        const int sg = c / KCL, lc = c % KCL;
+        const bool mine = (4 * sg + g) == sp;
         if constexpr (PREC == 1) {
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            float v = ysel_fixed(32 * kc + j);
-#pragma unroll
-            for (int gg = 1; gg < 4; ++gg) v = (g == gg) ? ysel_fixed(32 * kc + 8 * gg + j) : v;
-            yb[kc][j] = (__bf16)v;
+            const int lm = 8 * lc + j;
+            yb[c][j] = (__bf16)((lm < NLM && mine) ? yc[lm < NLM ? lm : 0] : 0.f);
           }
         } else {
-          float v = ysel_fixed(4 * kc);
-#pragma unroll
-          for (int gg = 1; gg < 4; ++gg) v = (g == gg) ? ysel_fixed(4 * kc + gg) : v;
-          yb[kc] = v;
+          yb[c] = mine ? yc[lc] : 0.f;
         }
       }
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kc = 0; kc < KCQ; ++kc) acc = O::mma(pa[mt][kc], yb[kc], acc);
+        for (int c = 0; c < KCY; ++c) acc = O::mma(pa[mt][c], yb[c], acc);
         ab2[mt] = acc;
       }
+      // dE/dYC^T rows q = 16 mq + 4 g + r of edge el, to LDS
 #pragma unroll
       for (int mq = 0; mq < MQ; ++mq) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -550,7 +565,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
         for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
 #pragma unroll
-        for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + sp * NLM + k];
+        for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + k * S + sp];
         yc_last_adj<L>(cgd, ycb, Yb);
         if (a.g2p) {
           // h_e = (this layer's dE/dr_e) - g2p[e], where g2p[e] is the last
@@ -660,6 +675,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   __shared__ typename O::T sM1[NM1], sM2[NM2];
   __shared__ typename O::T sW[NWT];
   if (fast_guard(a)) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3t);
@@ -695,7 +711,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       fetch(std::integral_constant<int, 0>{}, cb[0]);
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, a.rc, a.envelope_p, geo);
+      edge_geometry(v, valid, gk, geo);
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4];
@@ -771,6 +787,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
   __shared__ typename O::T sB2[NB2], sB1[NB1];
   if (fast_guard(a)) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3t);
@@ -814,7 +831,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       fetch(std::integral_constant<int, 0>{}, cb[0]);
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, a.rc, a.envelope_p, geo);
+      edge_geometry(v, valid, gk, geo);
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4], ab2[4];
@@ -918,6 +935,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   __shared__ typename O::T sW[NWT];
   __shared__ float sY[NW][kTileE * 17];   // odd row stride against bank conflicts
   if (fast_guard(a)) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NWT>(sW, a.w3f);
@@ -951,7 +969,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       }
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, a.rc, a.envelope_p, geo);
+      edge_geometry(v, valid, gk, geo);
       if (g == 0) {
         float yc[NLM];
         yc_last<L>(cgd, geo.Y, yc);
@@ -1063,6 +1081,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
   __shared__ unsigned sHT[NW][C * HT / 2];
   __shared__ float sY[NW][kTileE * 17];
   if (fast_guard(a)) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   stage_lds<bf16x8, (L + 1) * CN * 2 * 64>(sW, a.w3t);
   stage_lds<bf16x8, (L + 1) * 4 * KCC * 64>(sWB, a.w3b);
@@ -1117,7 +1136,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       const float* Aj = a.Abar + (int64_t)j * C + 8 * g;
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
-      edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, a.rc, a.envelope_p, geo);
+      edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
       if (g == 0) {
@@ -1282,6 +1301,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
   __shared__ bf16x8 sM1[4 * 64], sM2[4 * 2 * 64];
   __shared__ unsigned sHT[NW][C * HT / 2];
   if (fast_guard(a)) return;
+  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   stage_lds<bf16x8, (L + 1) * CN * 2 * 64>(sW, a.w3t);
   stage_lds<bf16x8, 4 * 64>(sM1, a.w1a);
@@ -1321,7 +1341,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
       const int rv = valid ? a.e_rev[e] : -1;
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
-      edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, a.rc, a.envelope_p, geo);
+      edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
       s16x4 yop[L + 1];
@@ -1441,14 +1461,14 @@ static int l2_grid(int64_t n, int nw, int per_xcd) {
 }
 
 template <int PREC, int L>
-static void l1_launch(bool fwd, int mq, const FastArgs& a, hipStream_t s) {
+static void l1_launch(bool fwd, int S, const FastArgs& a, hipStream_t s) {
   // 4 waves per workgroup; forward 4 waves per SIMD, adjoint 2
   constexpr int NW = 4;
   const int gf = l2_grid(a.n, NW, 128), gb = l2_grid(a.n, NW, PREC == 1 ? 64 : 128);
-#define MPIP_L1(MQ)                                                        \
-  if (fwd) k_l1_fwd<PREC, L, MQ, NW><<<gf, 64 * NW, 0, s>>>(a);              \
-  else k_l1_bwd<PREC, L, MQ, NW><<<gb, 64 * NW, 0, s>>>(a);
-  switch (mq) {
+#define MPIP_L1(SS)                                                        \
+  if (fwd) k_l1_fwd<PREC, L, SS, NW><<<gf, 64 * NW, 0, s>>>(a);              \
+  else k_l1_bwd<PREC, L, SS, NW><<<gb, 64 * NW, 0, s>>>(a);
+  switch (S) {
     case 1: MPIP_L1(1) break;
     case 2: MPIP_L1(2) break;
     case 3: MPIP_L1(3) break;
@@ -1457,13 +1477,12 @@ static void l1_launch(bool fwd, int mq, const FastArgs& a, hipStream_t s) {
 #undef MPIP_L1
 }
 
+// species-factorised first layer: n_species <= 4 (the engine checks)
 void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s) {
-  const int nlm = (L + 1) * (L + 1);
-  const int mq = (a.n_species * nlm + 15) / 16;
   if (prec == MPIP_BF16_MIXED) {
-    if (L == 1) l1_launch<1, 1>(fwd, mq, a, s); else l1_launch<1, 2>(fwd, mq, a, s);
+    if (L == 1) l1_launch<1, 1>(fwd, a.n_species, a, s); else l1_launch<1, 2>(fwd, a.n_species, a, s);
   } else {
-    if (L == 1) l1_launch<0, 1>(fwd, mq, a, s); else l1_launch<0, 2>(fwd, mq, a, s);
+    if (L == 1) l1_launch<0, 1>(fwd, a.n_species, a, s); else l1_launch<0, 2>(fwd, a.n_species, a, s);
   }
 }
 

@@ -80,6 +80,6 @@ def test_adjoint_against_finite_differences(torch, M, case):
             D = np.eye(3)
             D[p, q] += t
             return energy_at(x0 @ D.T, s.cell @ D.T)
-        fdw = -stencil5(e_strain, 1e-3)
+        fdw = -stencil5(e_strain, 1e-2)
         print(f"  virial[{p},{q}]: FD {fdw:.6e} adjoint {Wg[p, q]:.6e}")
         assert abs(fdw - Wg[p, q]) <= 1e-3 * max(np.abs(Wg).max(), 1e-3)
