@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpip.so")
-SOURCES = ["engine.cpp", "cg.cpp", "k_neighbor.hip", "k_edge.hip", "k_node.hip", "k_fast.hip", "k_node1.hip", "k_partition.hip", "k_batch.hip", "k_md.hip", "k_trim.hip"]
+SOURCES = ["engine.cpp", "cg.cpp", "k_neighbor.hip", "k_edge.hip", "k_node.hip", "k_fast.hip", "k_fast32.hip", "k_node1.hip", "k_partition.hip", "k_batch.hip", "k_md.hip", "k_trim.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of all device code

@@ -307,4 +307,86 @@ __device__ __forceinline__ void radial_out(const f32x4* a2, int lane, const void
 
 __device__ __forceinline__ int64_t edges_total(const EdgeArgs& a) { return (int64_t)a.row_ptr[a.n]; }
 
+// ---- FP32 radial MLP from row-major LDS copies (W1 [8][65], W2 [64][65],
+// rows the layer input), 16x16x4 MFMA: D tile row 4 g + r, column lane % 16;
+// A operand of lane (g, l16) = A[l16][g], B operand = B[g][l16]
+
+// hidden index of k-chunk q, lane group g (the D -> B operand order of the MLP)
+__device__ __forceinline__ int phi_f(int q, int g) { return 16 * (q / 4) + 4 * g + (q % 4); }
+
+// layers 1 and 2: p1, p2 (and a1 = silu(p1)) as D tiles (hidden 16 mt + 4 g + r) x (edge)
+__device__ __forceinline__ void mlp_fwd_rows(const Geo& geo, int lane, const float* sW1, const float* sW2, f32x4* p1,
+                                             f32x4* a1, f32x4* p2) {
+  const int g = lane >> 4, el = lane & 15;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc = mfma_f32(sW1[(4 * q + g) * 65 + 16 * mt + el], geo.basis[4 * q + g], acc);
+    p1[mt] = acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a1[mt][r] = silu(acc[r]);
+  }
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < 16; ++kc) acc = mfma_f32(sW2[phi_f(kc, g) * 65 + 16 * mt + el], a1[kc / 4][kc % 4], acc);
+    p2[mt] = acc;
+  }
+}
+
+// backward from ab2 = dE/da2 (features x edges): pb2 = ab2 silu'(p2) -> W2 ->
+// silu'(p1) -> W1 -> dE/de; lane el (< 16) receives dE/de of edge el in eb
+__device__ __forceinline__ void mlp_bwd_rows(const f32x4* ab2, const f32x4* p1, const f32x4* p2, int lane,
+                                             const float* sW1, const float* sW2, float* eb) {
+  const int g = lane >> 4, el = lane & 15;
+  f32x4 pb2[4], pb1[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pb2[mt][r] = ab2[mt][r] * dsilu(p2[mt][r]);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < 16; ++kc) acc = mfma_f32(sW2[(16 * mt + el) * 65 + phi_f(kc, g)], pb2[kc / 4][kc % 4], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
+  }
+  f32x4 eacc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < 16; ++kc)
+    eacc = mfma_f32(el < kNB ? sW1[(el < kNB ? el : 0) * 65 + phi_f(kc, g)] : 0.f, pb1[kc / 4][kc % 4], eacc);
+  const int src = el + 16;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    eb[r] = eacc[r];
+    eb[4 + r] = __shfl(eacc[r], src);
+  }
+}
+
+// stage n floats of a row-major weight copy into LDS (whole workgroup)
+template <int NF>
+__device__ __forceinline__ void stage_rows(float* dst, const float* src) {
+  for (int t = threadIdx.x; t < NF; t += blockDim.x) dst[t] = src[t];
+}
+
+
+// Rows of the calling wave.  Workgroups are dispatched to the 8 XCDs in
+// round-robin order, so workgroup b runs on XCD b % 8: each XCD takes a
+// contiguous eighth of the spatially sorted rows and its waves walk that
+// range side by side, so the sender rows they gather stay within one L2.
+// The grid is a multiple of 8 workgroups.
+struct RowWalk {
+  int64_t i, end, step;
+};
+template <int NW>
+__device__ __forceinline__ RowWalk row_walk(int64_t n) {
+  const int b = blockIdx.x, x = b & 7, lb = b >> 3, BX = gridDim.x >> 3;
+  const int64_t r0 = n * x / 8, r1 = n * (x + 1) / 8;
+  return {r0 + (int64_t)lb * NW + (threadIdx.x >> 6), r1, (int64_t)BX * NW};
+}
+
+
 }  // namespace mpip

@@ -403,9 +403,37 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
         if ((st = pack(C / 16, C / 32, [&](int mt, int kc, int lane, int j) {
                return Wd[(size_t)(32 * kc + 8 * (lane >> 4) + j) * nzd + 16 * mt + (lane & 15)];
              }, &d.nk_dt)) != MPIP_OK) goto done;
+        // dE/dA = W_down zbar with the message normalisation 1/n_avg folded in:
+        // the fused last-layer adjoint reads dA / n_avg
+        const double inv_n = hp->inv_avg_neighbors;
         if ((st = pack(C / 16, C / 32, [&](int mt, int kc, int lane, int j) {
-               return Wd[(size_t)(16 * mt + (lane & 15)) * nzd + phi_bf(kc, lane >> 4, j)];
+               return (float)(Wd[(size_t)(16 * mt + (lane & 15)) * nzd + phi_bf(kc, lane >> 4, j)] * inv_n);
              }, &d.nk_d)) != MPIP_OK) goto done;
+      }
+      // FP32 form, specialised first and sender-side last layer: row-major
+      // copies with odd row strides
+      d.w1r = d.w2r = d.w3r = nullptr;
+      if (!bf && (C == 64 || C == 128)) {
+        std::vector<float> v1((size_t)8 * 65, 0.f), v2((size_t)64 * 65, 0.f);
+        for (int n_ = 0; n_ < nb; ++n_)
+          for (int h = 0; h < H; ++h) v1[(size_t)n_ * 65 + h] = W1(n_, h);
+        for (int a = 0; a < H; ++a)
+          for (int b2 = 0; b2 < H; ++b2) v2[(size_t)a * 65 + b2] = W2(a, b2);
+        const void* p1;
+        if ((st = upload(m, v1, &p1)) != MPIP_OK) goto done;
+        d.w1r = (const float*)p1;
+        if ((st = upload(m, v2, &p1)) != MPIP_OK) goto done;
+        d.w2r = (const float*)p1;
+        if (t >= 2) {   // W3 of the live paths when the layer is the last one
+          const std::vector<int>& lv = live[1];
+          const int ws = (int)lv.size() * C + 1;
+          std::vector<float> v3((size_t)H * ws, 0.f);
+          for (int h = 0; h < H; ++h)
+            for (int pi = 0; pi < (int)lv.size(); ++pi)
+              for (int c = 0; c < C; ++c) v3[(size_t)h * ws + pi * C + c] = W3(h, lv[pi] * C + c);
+          if ((st = upload(m, v3, &p1)) != MPIP_OK) goto done;
+          d.w3r = (const float*)p1;
+        }
       }
       // ---- operand layouts of the specialised first / last layer kernels
       // layer-2 B operand, edges x features: col h2 = 16 nt + lane%16, k-slot -> h1
@@ -550,7 +578,9 @@ size_t take(size_t& cur, size_t bytes) {
   return o;
 }
 
-Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
+// prec: the message buffer of the sender-side last layer holds BF16 or FP32
+// values (the default sizes it for FP32, the larger)
+Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K, int prec = MPIP_FP32) {
   Plan p;
   size_t cur = 0;
   p.max_bins = (int)std::min<int64_t>(std::max<int64_t>(4096, 2 * N), 1 << 26);
@@ -594,7 +624,8 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K) {
     }
     if ((C == 64 || C == 128) && S * nlm <= 64 && K >= 2)
       p.o_qp = take(cur, sizeof(float) * N * nlm * 64 * S);
-    if ((C == 64 || C == 128) && K >= 2) p.o_msg = take(cur, sizeof(uint16_t) * cap * C);
+    if ((C == 64 || C == 128) && K >= 2)
+      p.o_msg = take(cur, (prec == MPIP_BF16_MIXED ? sizeof(uint16_t) : sizeof(float)) * cap * C);
     if (K >= 3) p.o_part = take(cur, sizeof(float) * kPartStride * cap);
     p.o_atom_e = take(cur, sizeof(double) * N);
     p.nblocks_out = (int)((N + 255) / 256);
@@ -669,7 +700,7 @@ mpip_status mpip_workspace_size(const mpip_model* m, const mpip_system* sys, mpi
   if (K < 1 || K > m->hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
   if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
   if (sys->n_atoms < 1) return fail(MPIP_EINVAL, "n_atoms must be >= 1");
-  *bytes = make_plan(sys->n_atoms, max_edges, &m->hp, K).total;
+  *bytes = make_plan(sys->n_atoms, max_edges, &m->hp, K, prec).total;
   return MPIP_OK;
 }
 
@@ -805,6 +836,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   auto set_fast = [&](const LayerDev& d, int role) {
     fa.w1a = d.w1a; fa.w2a = d.w2a; fa.w2b = d.w2b; fa.w1b = d.w1b; fa.w2f = d.w2f;
     fa.w3f = d.w3fp[role]; fa.w3t = d.w3t[role]; fa.w3b = d.w3bp[role]; fa.cg = d.cg[role];
+    fa.w1r = d.w1r; fa.w2r = d.w2r; fa.w3r = d.w3r;
   };
   const int ht_bf16 = prec == MPIP_BF16_MIXED ? 1 : 0;
   // two-layer evaluation with specialised first and last layers (BF16 form):
@@ -813,9 +845,12 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   fa.htbar_bf16 = node1 ? 1 : 0;
   // the last layer's node update fused with its adjoint (needs the messages of the BF16 form in A)
   const bool nodeK = node1 && fa.msg && LD[K - 1].nk_dt != nullptr;
-  // two specialised layers in the BF16 form: the last layer's edge gradients go
-  // to the (then dead) message buffer and the first layer's adjoint combines them
-  if (node1 && fa.msg) fa.g2p = (float4*)fa.msg;
+  // FP32 form: the last layer runs sender side (messages, their sum, one fused adjoint)
+  const bool send32 = !ht_bf16 && fa.msg && fast_layer(K) && kind_of(K) == KIND_LAST && LD[K - 1].w3r != nullptr;
+  // two specialised layers in the sender-side form: the last layer's edge
+  // gradients go to the (then dead) message buffer and the first layer's
+  // adjoint combines them
+  if ((node1 && fa.msg) || (send32 && K == 2 && fast_layer(1))) fa.g2p = (float4*)fa.msg;
   NodeKArgs nk;
   nk.n = N; nk.nlm = nlm; nk.A = A; nk.h = h; nk.w_read = m->w_read; nk.e0 = m->e0;
   nk.spec_s = b.spec_s; nk.owned_s = b.owned_s; nk.atom_e = atom_e;
@@ -863,6 +898,15 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
           T.begin("edge_sum_t" + std::to_string(t), s);
           fa.n = R(K);
           launch_l2(prec, C, L, 5, fa, s);
+        } else if (send32) {
+          fa.n = R(K - 1);
+          fa.row_end = root_end;
+          launch_l2_32(C, L, 0, fa, s);
+          fa.row_end = nullptr;
+          T.end(s);
+          T.begin("edge_sum_t" + std::to_string(t), s);
+          fa.n = R(K);
+          launch_l2_32(C, L, 1, fa, s);
         } else {
           fa.n = R(K);
           launch_l2(prec, C, L, 0, fa, s);
@@ -926,7 +970,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   T.begin("outputs", s);
   if (!fa.g2p) launch_zero(g, sizeof(float4) * (size_t)max_edges, s);
   // the FP32 form's edge-parallel adjoint needs each edge's receiver
-  if (fast_layer(K) && kind_of(K) == KIND_LAST && !ht_bf16) edge_receivers(b, N, max_edges, s);
+  if (fast_layer(K) && kind_of(K) == KIND_LAST && !ht_bf16 && !send32) edge_receivers(b, N, max_edges, s);
   // trimmed: the adjoint's pull adds into hbar rows up to R(K - 1), the
   // layer-K seed (gate adjoint) writes rows < R(K) only
   if (rows && !node1 && K >= 2) zero_rows(hbar, R(K), (int64_t)nlm * C);
@@ -985,13 +1029,17 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         launch_l1(prec, L, false, fa, s);
       } else {
         fa.ht = ht; fa.Abar = A;
-        if (ht_bf16) {
+        if (ht_bf16 || send32) {
+          // the BF16 adjoint reads dA / n_avg, which the fused last-layer node
+          // kernel writes; after the generic node adjoint, scale here
+          if (ht_bf16 && !nodeK) launch_scale(A, (float)hp.inv_avg_neighbors, R(K) * (int64_t)C, s);
           fa.n = R(K - 1);   // sender-side
           fa.row_end = root_end;
           // the walked prefix gets its gradient slots written; the rest of
           // those rows (receivers with dA = 0) must read as zero
           if (root_end && fa.g2p) zero_row_tails(fa.g2p, b.row_ptr, root_end, R(K - 1), N, max_edges, s);
-          launch_l2(prec, C, L, 3, fa, s);
+          if (ht_bf16) launch_l2(prec, C, L, 3, fa, s);
+          else launch_l2_32(C, L, 2, fa, s);
           fa.row_end = nullptr;
         } else {
           fa.n = R(K);       // edge-parallel over the roots' edges
@@ -1055,7 +1103,7 @@ static mpip_status evaluate_impl(mpip_model* m, const mpip_system* sys, mpip_pre
   if (!ws) return fail(MPIP_EINVAL, "null workspace");
   if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
   const int64_t N = sys->n_atoms;
-  Plan p = make_plan(N, max_edges, &hp, K);
+  Plan p = make_plan(N, max_edges, &hp, K, prec);
   if (ws_bytes < p.total) return fail(MPIP_ECAPACITY, "workspace too small");
   int cur = 0;
   HIPCHK(hipGetDevice(&cur));
@@ -1111,7 +1159,7 @@ mpip_status mpip_evaluate_noalloc(mpip_model* m, const mpip_system* sys, mpip_pr
   if (!sys || sys->n_atoms < 1) return fail(MPIP_EINVAL, "null system or n_atoms < 1");
   if (K < 1 || K > m->hp.n_layers) return fail(MPIP_EINVAL, "K must be in 1..n_layers");
   if (max_edges < 0 || max_edges > ((int64_t)1 << 31) - 1) return fail(MPIP_EINVAL, "max_edges out of range");
-  const size_t need = make_plan(sys->n_atoms, max_edges, &m->hp, K).total;
+  const size_t need = make_plan(sys->n_atoms, max_edges, &m->hp, K, prec).total;
   if (need > kNoAllocScratchBytes)
     return fail(MPIP_ECAPACITY, "mpip_evaluate_noalloc: this system needs " + std::to_string(need) +
                                     " bytes of workspace; the static scratch holds " +
@@ -1364,7 +1412,7 @@ PartLayout part_layout(const mpip_model* m, int64_t N, double L, double halo, in
   q.o_w = take(cur, sizeof(double) * 9);
   q.o_f = take(cur, sizeof(double) * 3 * max_local);
   q.o_ae = take(cur, sizeof(double) * max_local);
-  q.eval_bytes = make_plan(max_local, max_edges, &m->hp, K).total;
+  q.eval_bytes = make_plan(max_local, max_edges, &m->hp, K).total;   // sized for either precision
   q.o_eval = take(cur, q.eval_bytes);
   q.total = cur + 256;
   return q;
@@ -1498,7 +1546,7 @@ mpip_status mpip_batch_workspace_size(const mpip_model* m, int64_t n_atoms, int3
   if (!m || !bytes) return fail(MPIP_EINVAL, "null argument");
   if (n_atoms < 1 || B < 1 || K < 1 || K > m->hp.n_layers || max_edges < 0) return fail(MPIP_EINVAL, "bad sizes");
   if (prec != MPIP_FP32 && prec != MPIP_BF16_MIXED) return fail(MPIP_EINVAL, "bad precision");
-  *bytes = batch_bytes(make_plan(n_atoms, max_edges, &m->hp, K), n_atoms, B);
+  *bytes = batch_bytes(make_plan(n_atoms, max_edges, &m->hp, K, prec), n_atoms, B);
   return MPIP_OK;
 }
 
@@ -1535,7 +1583,7 @@ mpip_status mpip_evaluate_batch(mpip_model* m, int32_t B, const int64_t* atom_pt
   }
   const int64_t N = atom_ptr[B];
   if (N > ((int64_t)1 << 30)) return fail(MPIP_EINVAL, "too many atoms");
-  Plan p = make_plan(N, max_edges, &hp, K);
+  Plan p = make_plan(N, max_edges, &hp, K, prec);
   if (ws_bytes < batch_bytes(p, N, B)) return fail(MPIP_ECAPACITY, "workspace too small");
   int cur = 0;
   HIPCHK(hipGetDevice(&cur));

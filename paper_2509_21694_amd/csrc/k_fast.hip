@@ -159,21 +159,6 @@ __device__ __forceinline__ float row16_sum(float v) {
 }
 
 
-// Rows of the calling wave.  Workgroups are dispatched to the 8 XCDs in
-// round-robin order, so workgroup b runs on XCD b % 8: each XCD takes a
-// contiguous eighth of the spatially sorted rows and its waves walk that
-// range side by side, so the sender rows they gather stay within one L2.
-// The grid is a multiple of 8 workgroups.
-struct RowWalk {
-  int64_t i, end, step;
-};
-template <int NW>
-__device__ __forceinline__ RowWalk row_walk(int64_t n) {
-  const int b = blockIdx.x, x = b & 7, lb = b >> 3, BX = gridDim.x >> 3;
-  const int64_t r0 = n * x / 8, r1 = n * (x + 1) / 8;
-  return {r0 + (int64_t)lb * NW + (threadIdx.x >> 6), r1, (int64_t)BX * NW};
-}
-
 template <typename T, int NT>
 __device__ __forceinline__ void stage_lds(T* dst, const void* src) {
   const T* s = (const T*)src;
@@ -283,6 +268,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, MROWS = S * NLM, MQ = (MROWS + 15) / 16;
   constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
   __shared__ typename O::T sM1[NM1], sM2[NM2];
+  // FP32 form: W1, W2 as row-major copies (one copy serves both orientations)
+  __shared__ float sR1[PREC == 0 ? 8 * 65 : 1], sR2[PREC == 0 ? 64 * 65 : 1];
   __shared__ float sY[NW][kTileE * NLM];
   __shared__ __align__(16) int sS[NW][kTileE];
   if (fast_guard(a)) return;
@@ -291,8 +278,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   if constexpr (PREC == 1) {
     stage_lds<typename O::T, NM1>(sM1, a.w1a);
     stage_lds<typename O::T, NM2>(sM2, a.w2f);
-    __syncthreads();
+  } else {
+    stage_rows<8 * 65>(sR1, a.w1r);
+    stage_rows<64 * 65>(sR2, a.w2r);
   }
+  __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* syc = sY[wv];
   int* ssp = sS[wv];
@@ -336,8 +326,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
             acc = O::mma(sM1[mt * 64 + lane], basis_op_bf16(geo.basis, g), acc);
           } else {
 #pragma unroll
-            for (int qq = 0; qq < 2; ++qq)
-              acc = O::mma(O::ldt(a.w1a, mt * 2 + qq, lane), geo.basis[4 * qq + g], acc);
+            for (int qq = 0; qq < 2; ++qq) acc = O::mma(sR1[(4 * qq + g) * 65 + 16 * mt + el], geo.basis[4 * qq + g], acc);
           }
 #pragma unroll
           for (int r = 0; r < 4; ++r) a1[mt][r] = silu(acc[r]);
@@ -349,7 +338,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
           for (int kc = 0; kc < O::KC64; ++kc) {
             typename O::T w;
             if constexpr (PREC == 1) w = sM2[(nt * O::KC64 + kc) * 64 + lane];
-            else w = O::ldt(a.w2f, nt * O::KC64 + kc, lane);
+            else w = sR2[phi_f(kc, g) * 65 + 16 * nt + el];   // B = W2 [h1][h2 = 16 nt + el]
             acc = O::mma(O::from_tiles(a1, kc), w, acc);
           }
 #pragma unroll
@@ -422,6 +411,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
   constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
   __shared__ typename O::T sM1[NM1], sM2[NM2], sB2[NB2], sB1[NB1];
+  // FP32 form: W1, W2 as row-major copies (one copy serves forward and adjoint)
+  __shared__ float sR1[PREC == 0 ? 8 * 65 : 1], sR2[PREC == 0 ? 64 * 65 : 1];
   constexpr int SYB = 16 * MQ + 1;   // odd row stride: the 16 edge lanes hit distinct banks
   __shared__ float sYB[NW][kTileE * SYB];
   if (fast_guard(a)) return;
@@ -432,8 +423,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
     stage_lds<typename O::T, NM2>(sM2, a.w2a);
     stage_lds<typename O::T, NB2>(sB2, a.w2b);
     stage_lds<typename O::T, NB1>(sB1, a.w1b);
-    __syncthreads();
+  } else {
+    stage_rows<8 * 65>(sR1, a.w1r);
+    stage_rows<64 * 65>(sR2, a.w2r);
   }
+  __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* syb = sYB[wv];
   // BF16 form: P rows staged as [q][64] (q < 16 MQ, zero past MROWS) plus
@@ -517,8 +511,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
       f32x4 p1[4], p2[4], a2[4], ab2[4];
-      if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
-      else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
+      if constexpr (PREC == 1) {
+        mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
+      } else {
+        f32x4 a1[4];
+        mlp_fwd_rows(geo, lane, sR1, sR2, p1, a1, p2);
+      }
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -558,7 +556,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       }
       float eb[kNB];
       if constexpr (PREC == 1) mlp_backward_reg<PREC>(ab2, p1, p2, lane, sB2, sB1, eb);
-      else mlp_backward_reg<PREC>(ab2, p1, p2, lane, (const typename O::T*)a.w2b, (const typename O::T*)a.w1b, eb);
+      else mlp_bwd_rows(ab2, p1, p2, lane, sR1, sR2, eb);
       wave_lds_sync();
       if (lane < kTileE && valid) {
         float ycb[NLM], Yb[kMaxNlm];
@@ -1174,7 +1172,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       }
       wave_lds_sync();
       // pull operands: A[lm = el][k-slot 4g + j] = YC_{e'}[lm] of edge 4g + j
-      // (1/n_avg is already in the products with dA_j)
+      // (1/n_avg is already in dA_j: the last-layer node kernel writes dA / n_avg)
       s16x4 ya[L + 1];
       {
         float yt[4];
@@ -1198,8 +1196,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       static_for<NK>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
         __builtin_amdgcn_sched_barrier(0);
-        const float ai[8] = {a.inv_n * an0.x, a.inv_n * an0.y, a.inv_n * an0.z, a.inv_n * an0.w,
-                             a.inv_n * an1.x, a.inv_n * an1.y, a.inv_n * an1.z, a.inv_n * an1.w};
+        const float ai[8] = {an0.x, an0.y, an0.z, an0.w, an1.x, an1.y, an1.z, an1.w};
         const bf16x8 hr = hn;
         const s16x4 hx[2] = {hx_op(2 * k), hx_op(2 * k + 1)};
         if constexpr (k + 1 < NK) {

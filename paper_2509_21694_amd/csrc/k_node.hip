@@ -386,4 +386,16 @@ void launch_fill32(void* p, uint32_t value, size_t bytes, hipStream_t s) {
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) { launch_fill32(p, 0u, bytes, s); }
 
+__global__ void k_scale(float* p, int64_t n, float f) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] *= f;
+}
+
+void launch_scale(float* p, float f, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_scale<<<(unsigned)blocks, 256, 0, s>>>(p, n, f);
+}
+
 }  // namespace mpip

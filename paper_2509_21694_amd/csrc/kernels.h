@@ -123,7 +123,11 @@ struct LayerDev {
   const void* n1_up[3];    // next layer's W_up_l: rows channel, k = channel in order
   const void* n1_vw[3];    // V_l W_down_l: rows (s, k) as (S*16)(r/4) + 4 mt + r%4, k = z feature permuted per C block
   const void* nk_dt;       // last layer, W_down's scalar block transposed: rows z feature, k = channel in order
-  const void* nk_d;        // last layer, W_down's scalar block: rows channel, k = z feature permuted
+  const void* nk_d;        // last layer, W_down's scalar block (/ n_avg): rows channel, k = z feature permuted
+  // FP32 form, sender-side last layer (k_fast32.hip): row-major copies with odd row strides
+  const float* w1r;        // W1 [n_basis 8][65]
+  const float* w2r;        // W2 [64][65] (rows the layer input)
+  const float* w3r;        // W3 of the last layer's live paths [64][P C + 1]
 };
 
 struct Node1Args {
@@ -193,6 +197,9 @@ struct FastArgs {
   const void* w3f;       // permuted (w3fp)
   const void* w3t;
   const void* w3b;       // permuted (w3bp)
+  const float* w1r;      // FP32 row-major copies (k_fast32.hip)
+  const float* w2r;
+  const float* w3r;
   const float* cg;
   float* Q;              // first layer forward: [N][nlm][S*64]
   const float* P;        // first layer adjoint: [N][nlm][S*64]
@@ -223,6 +230,9 @@ void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s);
 // 3 both adjoints fused over the reverse edges, 4 forward as sender-side
 // messages, 5 their segmented sum into A (3, 4 and 5: BF16 form only)
 void launch_l2(int prec, int C, int L, int which, const FastArgs& a, hipStream_t s);
+// last layer of the FP32 form, sender side (C = 64 or 128): which = 0 messages
+// (FP32, into msg), 1 their sum into A, 2 the fused adjoint
+void launch_l2_32(int C, int L, int which, const FastArgs& a, hipStream_t s);
 
 struct EdgeArgs {
   int64_t n;               // atoms
@@ -355,6 +365,8 @@ void add_energy_virial_launch(const double* e, const double* w, double* E, doubl
 void scatter_scalars_launch(const double* src, const int32_t* index, int64_t n, int64_t n_dst, double* dst,
                             hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+// p[0 .. n-1] *= f
+void launch_scale(float* p, float f, int64_t n, hipStream_t s);
 // fill `bytes` (a multiple of 4) with a 32-bit pattern
 void launch_fill32(void* p, uint32_t value, size_t bytes, hipStream_t s);
 
