@@ -76,31 +76,23 @@ def phase_counts(hp, prec):
         "edge_fwd_t1": (2 * (mlp12 + H * nlm), 0.0, ev, 8 + nlm * 64 * S * fb),
         # MLP adjoint through layers 2, 1; dE/da2 = P^T Ysel; dE/dYC = P a2
         "edge_bwd_t1": (2 * (mlp12 + 2 * H * nlm), 0.0, ev + grw, 8 + nlm * 64 * S * fb),
-        # full MLP; s_l = <h~_j,l , YC_l> (nlm FMA/channel) and A += R s (P FMA/channel)
-        "edge_fwd_t2": (2 * (mlp12 + mlp3), 2.0 * C * (nlm + P), ev + src, 8 + nlm * C * fb + C * 4),
-        # MLP adjoint (W3, W2, W1); s (nlm FMA), dYC (nlm FMA), dR and R dA (2P mul) per channel
-        "edge_bwd_t2": (2 * (mlp12 + mlp3), C * (4.0 * nlm + 2 * P), ev + src + grw, 8 + nlm * C * fb + C * 4),
-        # h~bar_i = sum_e YC^T (R dA_j): nlm MAC per channel on MFMA; R dA_j: P mul per channel
-        "edge_pull_t2": (2.0 * nlm * C, 1.0 * P * C, ev + src, 8 + C * 4 + nlm * C * 4),
-    }
-    if prec == "bf16":
+        # last layer, sender side (both forms): messages with the full MLP,
+        # X_l = <h~_j,l , YC_l> on MFMA (nlm MAC per channel), m = sum_l R_l X_l
+        # on the VALU (P FMA per channel); h~_j read once per atom, e_vec, e_rev
+        # read per edge.  The per-edge messages this form writes (and the sum
+        # reads back) are not algorithmic bytes of the layer: they count in the
+        # measured traffic only
+        "edge_fwd_t2": (2 * (mlp12 + mlp3) + 2.0 * nlm * C, 2.0 * P * C, ev + src, 8 + nlm * C * fb),
+        # A_i = sum over the row of the messages: C adds per edge; A_i (C FP32) written per atom
+        "edge_sum_t2": (0.0, 1.0 * C, 0, 8 + 4 * C),
         # one fused adjoint over the reverse edges: the MLP adjoint, and
         # s_l = <h~_i,l , YC_l>, dYC and the pull (nlm MAC per channel each) on
         # MFMA; dR and R dA_j (P mul per channel each) on the VALU; e_rev read
-        # per edge; h~_i read and h~bar_i written (BF16) once per atom
-        d["edge_bwd_t2"] = (2 * (mlp12 + mlp3) + 6.0 * nlm * C, 2.0 * P * C, ev + 2 * src + grw,
-                            8 + nlm * C * fb + C * 4 + nlm * C * fb)
-        del d["edge_pull_t2"]
-        # forward as sender-side messages: full MLP, X_l = <h~_j,l , YC_l> on
-        # MFMA (nlm MAC per channel), m = sum_l R_l X_l on the VALU (P FMA per
-        # channel); h~_j read once per atom, e_vec, e_rev read per edge.  The
-        # per-edge messages this form writes (and the sum reads back) are
-        # not algorithmic bytes of the layer: they count in the measured
-        # traffic only
-        d["edge_fwd_t2"] = (2 * (mlp12 + mlp3) + 2.0 * nlm * C, 2.0 * P * C, ev + src,
-                            8 + nlm * C * fb)
-        # A_i = sum over the row of the messages: C adds per edge; A_i (C FP32) written per atom
-        d["edge_sum_t2"] = (0.0, 1.0 * C, 0, 8 + 4 * C)
+        # per edge; h~_i read and h~bar_i written once per atom
+        "edge_bwd_t2": (2 * (mlp12 + mlp3) + 6.0 * nlm * C, 2.0 * P * C, ev + 2 * src + grw,
+                        8 + nlm * C * fb + C * 4 + nlm * C * fb),
+    }
+    if prec == "bf16":
         # fused node kernels between the two layers, forward and adjoint
         # (one phase): z = Q (VW) and h~ = h W_up forward, h-bar = h~-bar W_up^T
         # and P = z-bar (VW)^T backward; Q read twice, P written, h_0 (FP32) and

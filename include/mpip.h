@@ -350,7 +350,7 @@ mpip_status mpip_md_run(mpip_model* model, const mpip_system* sys, double* posit
  * adds their durations to per-phase totals and returns the totals since the
  * last enable.  Phase names: "neighbors", "trim", "node_gemm", "gates", "outputs",
  * "node_fused", "node_last", "edge_fwd_t<k>", "edge_sum_t<k>",
- * "edge_bwd_t<k>", "edge_pull_t<k>" (k = layer).  Host-side only; the model
+ * "edge_bwd_t<k>" (k = layer).  Host-side only; the model
  * must not be evaluated concurrently on two streams while enabled. */
 #define MPIP_MAX_PHASES 48
 typedef struct {

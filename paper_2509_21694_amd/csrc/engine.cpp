@@ -846,6 +846,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   // the last layer's node update fused with its adjoint (needs the messages of the BF16 form in A)
   const bool nodeK = node1 && fa.msg && LD[K - 1].nk_dt != nullptr;
   // FP32 form: the last layer runs sender side (messages, their sum, one fused adjoint)
+  // (the message buffer and W3 copy exist whenever the last layer is specialised)
   const bool send32 = !ht_bf16 && fa.msg && fast_layer(K) && kind_of(K) == KIND_LAST && LD[K - 1].w3r != nullptr;
   // two specialised layers in the sender-side form: the last layer's edge
   // gradients go to the (then dead) message buffer and the first layer's
@@ -898,7 +899,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
           T.begin("edge_sum_t" + std::to_string(t), s);
           fa.n = R(K);
           launch_l2(prec, C, L, 5, fa, s);
-        } else if (send32) {
+        } else {   // FP32 form (send32)
           fa.n = R(K - 1);
           fa.row_end = root_end;
           launch_l2_32(C, L, 0, fa, s);
@@ -907,9 +908,6 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
           T.begin("edge_sum_t" + std::to_string(t), s);
           fa.n = R(K);
           launch_l2_32(C, L, 1, fa, s);
-        } else {
-          fa.n = R(K);
-          launch_l2(prec, C, L, 0, fa, s);
         }
       }
     } else {
@@ -969,8 +967,6 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   // ---------------- adjoint ----------------
   T.begin("outputs", s);
   if (!fa.g2p) launch_zero(g, sizeof(float4) * (size_t)max_edges, s);
-  // the FP32 form's edge-parallel adjoint needs each edge's receiver
-  if (fast_layer(K) && kind_of(K) == KIND_LAST && !ht_bf16 && !send32) edge_receivers(b, N, max_edges, s);
   // trimmed: the adjoint's pull adds into hbar rows up to R(K - 1), the
   // layer-K seed (gate adjoint) writes rows < R(K) only
   if (rows && !node1 && K >= 2) zero_rows(hbar, R(K), (int64_t)nlm * C);
@@ -1029,26 +1025,17 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
         launch_l1(prec, L, false, fa, s);
       } else {
         fa.ht = ht; fa.Abar = A;
-        if (ht_bf16 || send32) {
-          // the BF16 adjoint reads dA / n_avg, which the fused last-layer node
-          // kernel writes; after the generic node adjoint, scale here
-          if (ht_bf16 && !nodeK) launch_scale(A, (float)hp.inv_avg_neighbors, R(K) * (int64_t)C, s);
-          fa.n = R(K - 1);   // sender-side
-          fa.row_end = root_end;
-          // the walked prefix gets its gradient slots written; the rest of
-          // those rows (receivers with dA = 0) must read as zero
-          if (root_end && fa.g2p) zero_row_tails(fa.g2p, b.row_ptr, root_end, R(K - 1), N, max_edges, s);
-          if (ht_bf16) launch_l2(prec, C, L, 3, fa, s);
-          else launch_l2_32(C, L, 2, fa, s);
-          fa.row_end = nullptr;
-        } else {
-          fa.n = R(K);       // edge-parallel over the roots' edges
-          launch_l2(prec, C, L, 1, fa, s);
-          T.end(s);
-          T.begin("edge_pull_t" + std::to_string(t), s);
-          fa.n = R(K - 1);   // pull onto the senders
-          launch_l2(prec, C, L, 2, fa, s);
-        }
+        // the BF16 adjoint reads dA / n_avg, which the fused last-layer node
+        // kernel writes; after the generic node adjoint, scale here
+        if (ht_bf16 && !nodeK) launch_scale(A, (float)hp.inv_avg_neighbors, R(K) * (int64_t)C, s);
+        fa.n = R(K - 1);   // sender-side
+        fa.row_end = root_end;
+        // the walked prefix gets its gradient slots written; the rest of
+        // those rows (receivers with dA = 0) must read as zero
+        if (root_end && fa.g2p) zero_row_tails(fa.g2p, b.row_ptr, root_end, R(K - 1), N, max_edges, s);
+        if (ht_bf16) launch_l2(prec, C, L, 3, fa, s);
+        else launch_l2_32(C, L, 2, fa, s);
+        fa.row_end = nullptr;
       }
     } else {
       ea.w1a = d.w1a; ea.w2a = d.w2a; ea.w2b = d.w2b; ea.w1b = d.w1b;

@@ -584,471 +584,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 
 // ============================================================ last layer
 
-template <int PREC> struct HT;
-template <> struct HT<1> {  // bf16 features
-  typedef unsigned short T;
-  // N consecutive values starting at an address aligned to 2*N bytes (N = 4 or 8)
-  template <int N>
-  __device__ static void loadN(const T* p, float* out) {
-    if constexpr (N == 8) {
-      const uint4 w = *(const uint4*)p;
-      const unsigned u[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        out[2 * k] = __uint_as_float(u[k] << 16);
-        out[2 * k + 1] = __uint_as_float(u[k] & 0xffff0000u);
-      }
-    } else {
-      const uint2 w = *(const uint2*)p;
-      out[0] = __uint_as_float(w.x << 16);
-      out[1] = __uint_as_float(w.x & 0xffff0000u);
-      out[2] = __uint_as_float(w.y << 16);
-      out[3] = __uint_as_float(w.y & 0xffff0000u);
-    }
-  }
-};
-template <> struct HT<0> {
-  typedef float T;
-  template <int N>
-  __device__ static void loadN(const T* p, float* out) {
-#pragma unroll
-    for (int k = 0; k < N; k += 4) {
-      const float4 w = *(const float4*)(p + k);
-      out[k] = w.x; out[k + 1] = w.y; out[k + 2] = w.z; out[k + 3] = w.w;
-    }
-  }
-};
-
-// one gathered 8-channel piece of a sender row, kept packed until use
-template <int PREC> struct HRaw;
-template <> struct HRaw<1> {
-  uint4 v;
-  __device__ void load(const unsigned short* p) { v = *(const uint4*)p; }
-  __device__ void get(float* o) const {
-    const unsigned u[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      o[2 * k] = __uint_as_float(u[k] << 16);
-      o[2 * k + 1] = __uint_as_float(u[k] & 0xffff0000u);
-    }
-  }
-};
-template <> struct HRaw<0> {
-  float4 a, b;
-  __device__ void load(const float* p) {
-    a = *(const float4*)p;
-    b = *(const float4*)(p + 4);
-  }
-  __device__ void get(float* o) const {
-    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
-    o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
-  }
-};
-
-// what one 8-channel chunk (path l, channels 32k + 8g ..) reads, fetched
-// one chunk ahead of its use
-template <int PREC, int L>
-struct Chunk {
-  HRaw<PREC> h[2 * L + 1];             // h~_j[l, m, chunk]
-  typename Op<PREC>::T w[2][Op<PREC>::KC64];   // W3 operands of the chunk's two M-tiles (BF16 form)
-  typename Op<PREC>::T wb[4];          // MLP-adjoint operands (adjoint a, BF16 form)
-  float4 a0, a1;                       // dA_i of the chunk's channels (adjoint a)
-};
-
-// The last layer keeps W3 in LDS in the BF16 form (one copy per workgroup,
-// staged once by a persistent grid); the FP32 form reads it from global
-// memory.  Lanes own (channel block g of C/4 channels, edge el); channels go
-// 8 at a time (a "chunk") so only one chunk of R, h~_j and dR is live, and
-// the next chunk's gathers are in flight while the current one computes.
-// Tail lanes of a tile read row 0 with zero harmonics and zero radial
-// weights, so they add exact zeros.
-template <int PREC, int C, int L, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 1))) void k_l2_fwd(FastArgs a) {
-  typedef Op<PREC> O;
-  typedef typename HT<PREC>::T HTy;
-  constexpr int NLM = (L + 1) * (L + 1);
-  constexpr int CB = C / 4, NK = CB / 8, CN = C / 16, NCH = (L + 1) * NK;
-  constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
-  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
-  __shared__ typename O::T sM1[NM1], sM2[NM2];
-  __shared__ typename O::T sW[NWT];
-  if (fast_guard(a)) return;
-  const GeoK gk = geo_consts(a.rc, a.envelope_p);
-  const CgDiag<L> cgd = cg_diag<L>(a.cg);
-  if constexpr (PREC == 1) {
-    stage_lds<typename O::T, NWT>(sW, a.w3t);
-    stage_lds<typename O::T, NM1>(sM1, a.w1a);
-    stage_lds<typename O::T, NM2>(sM2, a.w2a);
-    __syncthreads();
-  }
-  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
-  const HTy* ht = (const HTy*)a.ht;
-  const RowWalk rw = row_walk<NW>(a.n);
-  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-    float acc[CB];
-#pragma unroll
-    for (int q = 0; q < CB; ++q) acc[q] = 0.f;
-    for (int t0 = e0; t0 < e1; t0 += kTileE) {
-      const int e = t0 + el;
-      const bool valid = e < e1;
-      const int j = valid ? a.e_src[e] : 0;
-      const HTy* hj = ht + (int64_t)j * NLM * C + 8 * g;
-      Chunk<PREC, L> cb[2];
-      auto fetch = [&](auto cc, Chunk<PREC, L>& b) {
-        constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
-#pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) b.h[m].load(hj + (l * l + m) * C + 32 * k);
-        if constexpr (PREC == 1) {
-#pragma unroll
-          for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-            for (int kc = 0; kc < O::KC64; ++kc) b.w[hh][kc] = sW[((l * CN + 2 * k + hh) * O::KC64 + kc) * 64 + lane];
-        }
-      };
-      fetch(std::integral_constant<int, 0>{}, cb[0]);
-      Geo geo;
-      const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, gk, geo);
-      float yc[NLM];
-      yc_last<L>(cgd, geo.Y, yc);
-      f32x4 p1[4], p2[4], a2[4];
-      if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
-      else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
-      typename O::T bop[O::KC64];
-#pragma unroll
-      for (int kc = 0; kc < O::KC64; ++kc) bop[kc] = O::from_tiles(a2, kc);
-      static_for<NCH>([&](auto cc) {
-        constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (c + 1 < NCH) fetch(std::integral_constant<int, c + 1>{}, cb[(c + 1) & 1]);
-        const Chunk<PREC, L>& cur = cb[c & 1];
-        float R8[8];
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-          f32x4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int kc = 0; kc < O::KC64; ++kc) {
-            typename O::T wv;
-            if constexpr (PREC == 1) wv = cur.w[hh][kc];
-            else wv = O::ldt(a.w3t, (l * CN + 2 * k + hh) * O::KC64 + kc, lane);
-            d = O::mma(wv, bop[kc], d);
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) R8[4 * hh + r] = d[r];
-        }
-        float h[2 * l + 1][8];
-#pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) cur.h[m].get(h[m]);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          float s = 0.f;
-#pragma unroll
-          for (int m = 0; m < 2 * l + 1; ++m) s += h[m][q] * yc[l * l + m];
-          acc[8 * k + q] += R8[q] * s;
-        }
-      });
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int q = 0; q < CB; ++q) acc[q] = row16_sum(acc[q]);
-    if (el == 0) {
-      // chunk k of lane group g holds channels 32k + 8g .. + 8
-#pragma unroll
-      for (int q = 0; q < CB; q += 4) {
-        float* dst = a.A + (int64_t)i * C + 32 * (q / 8) + 8 * g + q % 8;
-        *(float4*)dst = make_float4(a.inv_n * acc[q], a.inv_n * acc[q + 1], a.inv_n * acc[q + 2], a.inv_n * acc[q + 3]);
-      }
-    }
-  }
-}
-
-// adjoint a: per edge dR, dE/dY and the MLP adjoint, in the layout and chunk
-// order of the forward kernel (W3 and its adjoint operands in LDS in the BF16 form)
-template <int PREC, int C, int L, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 2 : 1))) void k_l2_bwd_a(FastArgs a) {
-  typedef Op<PREC> O;
-  typedef typename HT<PREC>::T HTy;
-  constexpr int NLM = (L + 1) * (L + 1);
-  constexpr int CB = C / 4, NK = CB / 8, CN = C / 16, NCH = (L + 1) * NK;
-  constexpr int KCC = O::kch(C);             // k-chunks over channels (MLP adjoint)
-  constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
-  constexpr int NWB = (PREC == 1) ? (L + 1) * 4 * KCC * 64 : 1;
-  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
-  __shared__ typename O::T sM1[NM1], sM2[NM2];
-  __shared__ typename O::T sW[NWT];
-  __shared__ typename O::T sWB[NWB];
-  constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
-  __shared__ typename O::T sB2[NB2], sB1[NB1];
-  if (fast_guard(a)) return;
-  const GeoK gk = geo_consts(a.rc, a.envelope_p);
-  const CgDiag<L> cgd = cg_diag<L>(a.cg);
-  if constexpr (PREC == 1) {
-    stage_lds<typename O::T, NWT>(sW, a.w3t);
-    stage_lds<typename O::T, NWB>(sWB, a.w3b);
-    stage_lds<typename O::T, NM1>(sM1, a.w1a);
-    stage_lds<typename O::T, NM2>(sM2, a.w2a);
-    stage_lds<typename O::T, NB2>(sB2, a.w2b);
-    stage_lds<typename O::T, NB1>(sB1, a.w1b);
-    __syncthreads();
-  }
-  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15;
-  const HTy* ht = (const HTy*)a.ht;
-  // edge-parallel: tiles of 16 consecutive edges regardless of rows (no
-  // per-row padding); each lane reads dA of its own edge's receiver
-  const int64_t E = a.row_ptr[a.n];
-  const RowWalk tw = row_walk<NW>((E + kTileE - 1) / kTileE);
-  for (int64_t t = tw.i; t < tw.end; t += tw.step) {
-    {
-      const int e = (int)(t * kTileE) + el;
-      const bool valid = e < E;
-      const int j = valid ? a.e_src[e] : 0;
-      const int i = valid ? a.e_dst[e] : 0;
-      const float* Abi = a.Abar + (int64_t)i * C + 8 * g;
-      const HTy* hj = ht + (int64_t)j * NLM * C + 8 * g;
-      Chunk<PREC, L> cb[2];
-      auto fetch = [&](auto cc, Chunk<PREC, L>& b) {
-        constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
-#pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) b.h[m].load(hj + (l * l + m) * C + 32 * k);
-        b.a0 = *(const float4*)(Abi + 32 * k);
-        b.a1 = *(const float4*)(Abi + 32 * k + 4);
-        if constexpr (PREC == 1) {
-#pragma unroll
-          for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-            for (int kc = 0; kc < O::KC64; ++kc) b.w[hh][kc] = sW[((l * CN + 2 * k + hh) * O::KC64 + kc) * 64 + lane];
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) b.wb[mt] = sWB[((l * 4 + mt) * KCC + k) * 64 + lane];
-        }
-      };
-      fetch(std::integral_constant<int, 0>{}, cb[0]);
-      Geo geo;
-      const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, gk, geo);
-      float yc[NLM];
-      yc_last<L>(cgd, geo.Y, yc);
-      f32x4 p1[4], p2[4], a2[4], ab2[4];
-      if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
-      else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) { a2[mt][r] = silu(p2[mt][r]); ab2[mt][r] = 0.f; }
-      typename O::T bop[O::KC64];
-#pragma unroll
-      for (int kc = 0; kc < O::KC64; ++kc) bop[kc] = O::from_tiles(a2, kc);
-      float ycb[NLM];
-#pragma unroll
-      for (int k = 0; k < NLM; ++k) ycb[k] = 0.f;
-      static_for<NCH>([&](auto cc) {
-        constexpr int c = decltype(cc)::value, l = c / NK, k = c % NK;
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (c + 1 < NCH) fetch(std::integral_constant<int, c + 1>{}, cb[(c + 1) & 1]);
-        const Chunk<PREC, L>& cur = cb[c & 1];
-        float R8[8];
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-          f32x4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int kc = 0; kc < O::KC64; ++kc) {
-            typename O::T wv;
-            if constexpr (PREC == 1) wv = cur.w[hh][kc];
-            else wv = O::ldt(a.w3t, (l * CN + 2 * k + hh) * O::KC64 + kc, lane);
-            d = O::mma(wv, bop[kc], d);
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) R8[4 * hh + r] = d[r];
-        }
-        const float Ai[8] = {cur.a0.x, cur.a0.y, cur.a0.z, cur.a0.w, cur.a1.x, cur.a1.y, cur.a1.z, cur.a1.w};
-        float h[2 * l + 1][8];
-#pragma unroll
-        for (int m = 0; m < 2 * l + 1; ++m) cur.h[m].get(h[m]);
-        float rb[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const float ai = a.inv_n * Ai[q];
-          float s = 0.f;
-#pragma unroll
-          for (int m = 0; m < 2 * l + 1; ++m) s += h[m][q] * yc[l * l + m];
-          rb[q] = ai * s;
-          const float w = R8[q] * ai;
-#pragma unroll
-          for (int m = 0; m < 2 * l + 1; ++m) ycb[l * l + m] += w * h[m][q];
-        }
-        // MLP adjoint through layer 3: ab2^T += W3_l (hidden x C) rbar^T over this chunk's channels
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-          if constexpr (PREC == 1) {
-            typename O::T bv;
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) bv[jj] = (__bf16)rb[jj];
-            ab2[mt] = O::mma(cur.wb[mt], bv, ab2[mt]);
-          } else {
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-              ab2[mt] = O::mma(O::ldt(a.w3b, (l * 4 + mt) * KCC + 8 * k + q, lane), rb[q], ab2[mt]);
-          }
-        }
-      });
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int k = 0; k < NLM; ++k) {
-        float w = ycb[k];
-        w += __shfl_xor(w, 16);
-        w += __shfl_xor(w, 32);
-        ycb[k] = w;
-      }
-      float eb[kNB];
-      if constexpr (PREC == 1) mlp_backward_reg<PREC>(ab2, p1, p2, lane, sB2, sB1, eb);
-      else mlp_backward_reg<PREC>(ab2, p1, p2, lane, (const typename O::T*)a.w2b, (const typename O::T*)a.w1b, eb);
-      if (lane < kTileE && valid) {
-        float Yb[kMaxNlm];
-#pragma unroll
-        for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
-        yc_last_adj<L>(cgd, ycb, Yb);
-        add_edge_grad(a.g, e, geo, eb, Yb);
-      }
-    }
-  }
-}
-
-// adjoint b: the sender-side feature adjoint pulled through the reverse edge,
-//   htbar_i[lm, c] = sum_e (-1)^l YC_e[lm] R_e[l, c] dA_{j_e}[c] / n_avg,
-// as an MFMA over the 16 edges of a tile: D[lm][c] += YC^T[lm][e] U_l[e][c]
-// with U_l = R_l * dA_j in the edges x channels layout of R (lane (g, n):
-// edges 4g + r, channel (C/16) n + nt), which is directly the B operand.
-template <int PREC, int C, int L, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 1))) void k_l2_bwd_b(FastArgs a) {
-  typedef Op<PREC> O;
-  constexpr int NLM = (L + 1) * (L + 1);
-  constexpr int CN = C / 16;
-  constexpr int NWT = (PREC == 1) ? (L + 1) * CN * O::KC64 * 64 : 1;
-  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
-  __shared__ typename O::T sM1[NM1], sM2[NM2];
-  __shared__ typename O::T sW[NWT];
-  __shared__ float sY[NW][kTileE * 17];   // odd row stride against bank conflicts
-  if (fast_guard(a)) return;
-  const GeoK gk = geo_consts(a.rc, a.envelope_p);
-  const CgDiag<L> cgd = cg_diag<L>(a.cg);
-  if constexpr (PREC == 1) {
-    stage_lds<typename O::T, NWT>(sW, a.w3f);
-    stage_lds<typename O::T, NM1>(sM1, a.w1a);
-    stage_lds<typename O::T, NM2>(sM2, a.w2a);
-    __syncthreads();
-  }
-  const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
-  float* syc = sY[wv];
-  const RowWalk rw = row_walk<NW>(a.n);
-  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-    f32x4 hb[CN];
-#pragma unroll
-    for (int t = 0; t < CN; ++t) hb[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int t0 = e0; t0 < e1; t0 += kTileE) {
-      const int e = t0 + el;
-      const bool valid = e < e1;
-      const int j = valid ? a.e_src[e] : 0;
-      // dA of the senders of this lane's edges 4g + r, channels CN*el .. + CN
-      float Aj[4][CN];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int jr = __shfl(j, 4 * g + r);
-        const float* src = a.Abar + (int64_t)jr * C + CN * el;
-#pragma unroll
-        for (int t = 0; t < CN; t += 4) {
-          const float4 w = *(const float4*)(src + t);
-          Aj[r][t] = w.x; Aj[r][t + 1] = w.y; Aj[r][t + 2] = w.z; Aj[r][t + 3] = w.w;
-        }
-      }
-      Geo geo;
-      const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, gk, geo);
-      if (g == 0) {
-        float yc[NLM];
-        yc_last<L>(cgd, geo.Y, yc);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          float val = 0.f;
-          if (k < NLM) val = (k >= 1 && k < 4) ? -yc[k] : yc[k];
-          syc[el * 17 + k] = val;
-        }
-      }
-      f32x4 p1[4], p2[4], a2[4];
-      if constexpr (PREC == 1) mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
-      else mlp_forward<PREC>(geo, lane, a.w1a, a.w2a, p1, p2);
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
-      typename O::T aop[O::KC64];
-#pragma unroll
-      for (int kc = 0; kc < O::KC64; ++kc) aop[kc] = O::from_tiles(a2, kc);
-      wave_lds_sync();
-      // YC^T rows lm = el, edges 4g + r (zero for tail edges: their harmonics are zero)
-      float yt[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) yt[r] = a.inv_n * syc[(4 * g + r) * 17 + el];
-      wave_lds_sync();
-      static_for<L + 1>([&](auto lc) {
-        constexpr int l = decltype(lc)::value;
-        const bool mine = el >= l * l && el < (l + 1) * (l + 1);
-        float ya[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) ya[r] = mine ? yt[r] : 0.f;
-#pragma unroll
-        for (int nt = 0; nt < CN; ++nt) {
-          f32x4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int kc = 0; kc < O::KC64; ++kc) {
-            typename O::T wv2;
-            if constexpr (PREC == 1) wv2 = sW[((l * CN + nt) * O::KC64 + kc) * 64 + lane];
-            else wv2 = O::ldt(a.w3f, (l * CN + nt) * O::KC64 + kc, lane);
-            d = O::mma(aop[kc], wv2, d);
-          }
-          float u[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) u[r] = d[r] * Aj[r][nt];
-          if constexpr (PREC == 1) {
-            const s16x4 av = {bfbits(ya[0]), bfbits(ya[1]), bfbits(ya[2]), bfbits(ya[3])};
-            const s16x4 bv = {bfbits(u[0]), bfbits(u[1]), bfbits(u[2]), bfbits(u[3])};
-            hb[nt] = mfma_bf16_k16(av, bv, hb[nt]);
-          } else {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) hb[nt] = mfma_f32(ya[r], u[r], hb[nt]);
-          }
-        }
-      });
-    }
-    // D rows lm = 4g + r, column el = channels CN*el + nt
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int lm = 4 * g + r;
-      if (lm < NLM) {
-        const int64_t o = ((int64_t)i * NLM + lm) * C + CN * el;
-        if (PREC == 1 && a.htbar_bf16) {
-          __bf16* dst = (__bf16*)a.htbar + o;
-#pragma unroll
-          for (int t = 0; t < CN; t += 4) {
-            typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
-            const bf16x4 v = {(__bf16)hb[t][r], (__bf16)hb[t + 1][r], (__bf16)hb[t + 2][r], (__bf16)hb[t + 3][r]};
-            *(bf16x4*)(dst + t) = v;
-          }
-        } else {
-          float* dst = a.htbar + o;
-#pragma unroll
-          for (int t = 0; t < CN; t += 4)
-            *(float4*)(dst + t) = make_float4(hb[t][r], hb[t + 1][r], hb[t + 2][r], hb[t + 3][r]);
-        }
-      }
-    }
-  }
-}
-
 // Fused adjoint of the last layer (BF16 form).  Rows i are walked as in the
 // pull; every edge e = (i <- j) stands for its reverse e' = (j <- i), whose
 // sender is the row's own atom (same length, unit vector -u):
@@ -1483,36 +1018,22 @@ void launch_l1(int prec, int L, bool fwd, const FastArgs& a, hipStream_t s) {
   }
 }
 
-template <int PREC, int C, int L>
+// BF16 form, sender side: which = 3 the fused adjoint (one workgroup of 8
+// waves per CU: W3 in both packings and the MLP weights fill the LDS), 4 the
+// messages (16 waves, 4 per SIMD sharing the LDS weights), 5 their sum
+template <int C, int L>
 static void l2_launch(int which, const FastArgs& a, hipStream_t s) {
-  // BF16 form: W3 and the MLP weights staged in LDS (forward and pull:
-  // (L+1) C 128 B + 12 KB; adjoint a: twice the W3 part + 22 KB).  Forward
-  // and pull run 3 waves per SIMD as 2 workgroups of 6 waves per CU; adjoint
-  // a runs 2 waves per SIMD (one workgroup of 8 waves for 128 channels, two
-  // of 4 for 64).  FP32 form: weights from memory.
-  constexpr int NWF = PREC == 1 ? 6 : 4, NWA = (PREC == 1 && C == 128) ? 8 : 4;
-  const int pf = PREC == 1 ? 64 : 128, pa = PREC == 1 ? (NWA == 8 ? 32 : 64) : 128;
-  if (which == 0) k_l2_fwd<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
-  else if (which == 1) k_l2_bwd_a<PREC, C, L, NWA><<<l2_grid(a.n, NWA, pa), 64 * NWA, 0, s>>>(a);
-  else if (which == 2) k_l2_bwd_b<PREC, C, L, NWF><<<l2_grid(a.n, NWF, pf), 64 * NWF, 0, s>>>(a);
-  else if constexpr (PREC == 1) {
-    if (which == 3) k_l2_adj<C, L, 8><<<l2_grid(a.n, 8, 32), 64 * 8, 0, s>>>(a);
-    else if (which == 4) k_l2_msg<C, L, 16><<<l2_grid(a.n, 16, C == 128 ? 32 : 64), 64 * 16, 0, s>>>(a);
-    else k_l2_msum<C><<<(unsigned)((a.n + 3) / 4), 256, 0, s>>>(a);
-  }
-}
-
-template <int PREC>
-static void l2_prec(int C, int L, int which, const FastArgs& a, hipStream_t s) {
-  if (C == 64 && L == 1) l2_launch<PREC, 64, 1>(which, a, s);
-  else if (C == 64 && L == 2) l2_launch<PREC, 64, 2>(which, a, s);
-  else if (C == 128 && L == 1) l2_launch<PREC, 128, 1>(which, a, s);
-  else l2_launch<PREC, 128, 2>(which, a, s);
+  if (which == 3) k_l2_adj<C, L, 8><<<l2_grid(a.n, 8, 32), 64 * 8, 0, s>>>(a);
+  else if (which == 4) k_l2_msg<C, L, 16><<<l2_grid(a.n, 16, C == 128 ? 32 : 64), 64 * 16, 0, s>>>(a);
+  else k_l2_msum<C><<<(unsigned)((a.n + 3) / 4), 256, 0, s>>>(a);
 }
 
 void launch_l2(int prec, int C, int L, int which, const FastArgs& a, hipStream_t s) {
-  if (prec == MPIP_BF16_MIXED) l2_prec<1>(C, L, which, a, s);
-  else l2_prec<0>(C, L, which, a, s);
+  (void)prec;   // BF16 form only (the FP32 form: launch_l2_32)
+  if (C == 64 && L == 1) l2_launch<64, 1>(which, a, s);
+  else if (C == 64 && L == 2) l2_launch<64, 2>(which, a, s);
+  else if (C == 128 && L == 1) l2_launch<128, 1>(which, a, s);
+  else l2_launch<128, 2>(which, a, s);
 }
 
 }  // namespace mpip

@@ -843,18 +843,6 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
                                                        capacity, b.e_rev);
 }
 
-// receiver of every edge, one wave per row
-__global__ __launch_bounds__(256) void k_edge_dst(int64_t n, const int32_t* __restrict__ row_ptr, int64_t capacity,
-                                                  int32_t* __restrict__ e_dst) {
-  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n || row_ptr[n] > capacity) return;
-  for (int e = row_ptr[i] + (threadIdx.x & 63); e < row_ptr[i + 1]; e += 64) e_dst[e] = (int32_t)i;
-}
-
-void edge_receivers(const NbrBuffers& b, int64_t n, int64_t capacity, hipStream_t s) {
-  k_edge_dst<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, b.row_ptr, capacity, b.e_dst);
-}
-
 void export_neighbors(const NbrBuffers& b, int64_t n, int64_t capacity, int32_t* oi, int32_t* oj, int32_t* os,
                       hipStream_t s) {
   const int ga = (int)((n + 255) / 256);

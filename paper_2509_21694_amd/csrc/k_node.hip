@@ -96,12 +96,14 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a, int64_t row_tiles)
       sb[idx] = *(const bf16x8*)(W + (int64_t)n * a.ldw + 32 * kc + 8 * (l >> 4));
     }
   } else {
+    // FP32: k-slot g of chunk kc is k = 16 (kc / 4) + 4 g + kc % 4, so one
+    // float4 of X per lane feeds four consecutive chunks
     float* sb = (float*)smem;
     const float* W = (const float*)a.wt;
     for (int idx = threadIdx.x; idx < NT * KCH * 64; idx += 256) {
       const int l = idx & 63, kc = (idx >> 6) % KCH, nt = (idx >> 6) / KCH;
       const int n = n0 + 16 * nt + (l & 15);
-      sb[idx] = W[(int64_t)n * a.ldw + 4 * kc + (l >> 4)];
+      sb[idx] = W[(int64_t)n * a.ldw + 16 * (kc / 4) + 4 * (l >> 4) + (kc % 4)];
     }
   }
   __syncthreads();
@@ -134,10 +136,17 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a, int64_t row_tiles)
       }
     } else {
       const float* sb = (const float*)smem;
-      for (int kc = 0; kc < KCH; ++kc) {
-        const float av = rv ? xrow[4 * kc + g] : 0.f;
+      const int KQ = KCH / 4;   // K / 16
+      const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 xv = rv ? *(const float4*)(xrow + 4 * g) : zero;
+      for (int q = 0; q < KQ; ++q) {
+        const float4 cur = xv;
+        if (q + 1 < KQ) xv = rv ? *(const float4*)(xrow + 16 * (q + 1) + 4 * g) : zero;
+        const float c4[4] = {cur.x, cur.y, cur.z, cur.w};
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = mfma_f32(av, sb[(t * KCH + kc) * 64 + lane], acc[t]);
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] = mfma_f32(c4[j], sb[(t * KCH + 4 * q + j) * 64 + lane], acc[t]);
       }
     }
 #pragma unroll
@@ -160,6 +169,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a, int64_t row_tiles)
 
 template <int PREC>
 static bool gemm_lds_try(int nt, const GemmArgs& g, hipStream_t s) {
+  if (PREC == 0 && g.K % 16 != 0) return false;   // the FP32 loads take K in 16s
   const int KCH = (PREC == 1) ? g.K / 32 : g.K / 4;
   const size_t per = (size_t)KCH * 64 * (PREC == 1 ? 16 : 4);
   if ((g.Nout / 16) % nt != 0 || per * nt > 64 * 1024) return false;

@@ -41,7 +41,7 @@ struct NbrBuffers {
   uint32_t* e_shift;     // [cap] S packed as three int8
   float4* e_vec;         // [cap] r_e (FP32 of the FP64 difference), species of sender in .w bits
   int32_t* e_rev;        // [cap]
-  int32_t* e_dst;        // [cap] receiver (sorted index) of each edge, for edge-parallel passes
+  int32_t* e_dst;        // [cap] scratch of the receptive-field trimming
 };
 
 // neighbour-list reuse within a skin: sorted positions refreshed from the
@@ -79,7 +79,6 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
                      hipStream_t s);
 void export_neighbors(const NbrBuffers& b, int64_t n, int64_t capacity, int32_t* oi, int32_t* oj, int32_t* os,
                       hipStream_t s);
-void edge_receivers(const NbrBuffers& b, int64_t n, int64_t capacity, hipStream_t s);
 
 // ------------------------------------------------------------------ layers
 

@@ -54,12 +54,14 @@ def per_kernel(path, counter):
 
 
 def mean_of(d, pat):
-    """Mean over the dispatches of the kernel matching pat."""
+    """Mean over the large dispatches (at least half the largest) of the
+    kernel matching pat: the run also evaluates smaller systems."""
     hits = [v for k, v in d.items() if re.search(pat, k.replace(" ", ""))]
     if not hits:
         return None
     v = max(hits, key=len)
-    return sum(v) / len(v)
+    big = [x for x in v if x >= 0.5 * max(v)]
+    return sum(big) / len(big)
 
 
 def largest_of(d, pat):
