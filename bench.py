@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--precisions", default="bf16,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-box", type=int, default=12, help="side of the periodic box the oracle is timed on")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the error statement against stored oracle values (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device to device once before the steps (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -340,7 +342,8 @@ def main():
         cap = int(n_edges * 1.02) + 4096
         F0 = o["forces"].cpu().numpy()
         E0 = float(o["energy"].cpu()[0])
-        errors = errors_vs_fp64(args.workload, model, prec, F0, o["atom_energy"].cpu().numpy(), K, dev)
+        errors = None if args.no_errors else errors_vs_fp64(args.workload, model, prec, F0,
+                                                             o["atom_energy"].cpu().numpy(), K, dev)
         del o
         outs = [model.evaluate(p, species, s.cell, s.pbc, K=K, precision=prec, max_edges=cap)
                 for p in pos_sets]

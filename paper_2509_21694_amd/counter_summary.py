@@ -14,6 +14,8 @@ are per SIMD (1024) or per CU (256) over that time:
   wait        = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES
 
 usage: python -m paper_2509_21694_amd.counter_summary "command text" CSV [CSV ...]
+       python -m paper_2509_21694_amd.counter_summary --trace "title" "command text" KERNEL_TRACE_CSV
+(the second form: per-kernel dispatch times from a --kernel-trace run)
 """
 from __future__ import annotations
 
@@ -45,8 +47,7 @@ def collect(paths):
                     if re.search(pat, name):
                         disp[row["Dispatch_Id"]][row["Counter_Name"]] = float(row["Counter_Value"])
                         kname[row["Dispatch_Id"]] = k
-                        meta[k] = (row.get("VGPR_Count") or row.get("Arch_VGPR_Count"),
-                                   row.get("Accum_VGPR_Count"), row.get("Scratch_Size"), row.get("LDS_Block_Size"))
+                        meta[k] = (row.get("Scratch_Size"), row.get("LDS_Block_Size"))
                         break
         top = collections.defaultdict(float)
         for d, cv in disp.items():
@@ -64,9 +65,11 @@ def main():
     print("# Per-kernel counters, bulk1m (1,000,000 atoms, K = 2, l_max = 2, C = 128)\n")
     print("Commands (run from the repository root on one MI355X, `cd /tmp` first for rocprofv3):\n")
     print("```\n" + cmd + "\n```\n")
-    print("Definitions: " + __doc__.split("are per SIMD")[1].split("usage:")[0].strip().replace("\n", " ") + "\n")
+    defs = __doc__.split("over that time:")[1].split("usage:")[0].strip().splitlines()
+    print("Utilisation per SIMD (1024) or per CU (256) over the dispatch's GRBM_GUI_ACTIVE / 8 cycles:\n")
+    print("\n".join("- " + d.strip() for d in defs) + "\n")
     cols = ["kernel", "time ms", "MFMA busy", "VALU busy", "co-issue", "waves/SIMD", "wait/wave", "LDS conflict",
-            "VALU instr/wave", "MFMA instr/wave", "trans/VALU", "VGPR", "AGPR", "scratch B", "LDS B"]
+            "VALU instr/wave", "MFMA instr/wave", "trans/VALU", "scratch B/lane", "LDS B/workgroup"]
     print("| " + " | ".join(cols) + " |")
     print("|" + "---|" * len(cols))
     for k in KERNELS:
@@ -88,11 +91,33 @@ def main():
                f"{v['SQ_INSTS_VALU'] / waves:.4g}" if waves and "SQ_INSTS_VALU" in v else "-",
                f"{v['SQ_INSTS_MFMA'] / waves:.4g}" if waves and "SQ_INSTS_MFMA" in v else "-",
                f"{v['SQ_INSTS_VALU_TRANS_F32'] / v['SQ_INSTS_VALU']:.3f}" if "SQ_INSTS_VALU_TRANS_F32" in v and "SQ_INSTS_VALU" in v else "-"]
-        m = meta.get(k, ("-",) * 4)
+        m = meta.get(k, ("-",) * 2)
         row += [str(x) for x in m]
         print("| " + " | ".join(row) + " |")
     print("\n(time: GRBM_GUI_ACTIVE / 8 at 2.4 GHz; counters of one pass per group, averaged over the large dispatches)")
 
 
+def trace_main():
+    title, cmd, path = sys.argv[2], sys.argv[3], sys.argv[4]
+    t = collections.defaultdict(list)
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            t[row["Kernel_Name"]].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-3)
+    total = sum(sum(v) for v in t.values())
+    print(f"# Kernel time per dispatch, {title}\n")
+    print("Command (run from the repository root on one MI355X):\n")
+    print("```\n" + cmd + "\n```\n")
+    print(f"Total kernel time {total * 1e-3:.2f} ms over all dispatches.\n")
+    print("| Kernel | Calls | Total ms | Avg us | Min us | Max us | % |")
+    print("|---|---|---|---|---|---|---|")
+    for name, v in sorted(t.items(), key=lambda kv: -sum(kv[1])):
+        nm = name if len(name) <= 90 else name[:87] + "..."
+        print(f"| `{nm}` | {len(v)} | {sum(v) * 1e-3:.3f} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
+              f"{100.0 * sum(v) / total:.2f} |")
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--trace":
+        trace_main()
+    else:
+        main()
