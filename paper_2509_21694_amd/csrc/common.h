@@ -45,6 +45,25 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// NT tiles of 64 x 16 bytes, contiguous at src, copied into LDS at dst by
+// the whole workgroup with direct global -> LDS loads (each wave copies whole
+// tiles: lane k of a load lands at byte 16 k of the tile).  No data passes
+// through registers and every load of the copy is in flight at once; call
+// lds_dma_sync() before the tiles are read.
+template <int NT, typename T>
+__device__ __forceinline__ void lds_dma_tiles(T* dst, const T* src) {
+  static_assert(sizeof(T) == 16, "16-byte elements");
+  const int lane = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
+  for (int t = (int)(threadIdx.x >> 6); t < NT; t += nw)
+    __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)t * 64 + lane),
+                                     (__attribute__((address_space(3))) void*)(dst + t * 64), 16, 0, 0);
+}
+// this wave's direct loads landed, then a workgroup barrier
+__device__ __forceinline__ void lds_dma_sync() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
 // LDS written by some lanes of a wave and read by others of the same wave
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -93,10 +93,11 @@ struct PairStore {
   }
 };
 
-// whole-block copy of NT operand tiles (64 lanes x 16 B each) into LDS
+// whole-block copy of NT operand tiles (64 lanes x 16 B each) into LDS,
+// complete after lds_dma_sync()
 template <int NT>
 __device__ __forceinline__ void stage_tiles(bf16x8* dst, const bf16x8* src) {
-  for (int t = threadIdx.x; t < NT * 64; t += blockDim.x) dst[t] = src[t];
+  lds_dma_tiles<NT>(dst, src);
 }
 
 // D tiles mt = 0..MT-1 of W x B with W's A-operand tiles in LDS at
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(4
   // scalars: h_0 = emb + SiLU(z_0[0:C])
   stage_tiles<NVT>(sV, VT0);
   stage_tiles<NU>(sU, (const bf16x8*)a.upt[0]);
-  __syncthreads();
+  lds_dma_sync();
   if (act) {
     bf16x8 q0[KCQ];
     qload(0, q0);
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(4
   for (int l = 1; l <= L; ++l) {
     __syncthreads();
     stage_tiles<NVT>(sV, VT0 + (size_t)l * NVT * 64);
-    __syncthreads();
+    lds_dma_sync();
     f32x4 gt[MTC];
     if (act) {
       bf16x8 q0[KCQ];
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(4
     __syncthreads();
     stage_tiles<NVT>(sV, (const bf16x8*)a.vwt[l]);
     stage_tiles<NU>(sU, (const bf16x8*)a.upt[l]);
-    __syncthreads();
+    lds_dma_sync();
     if (act) {
       for (int m = 0; m < 2 * l + 1; ++m) {
         const int lm = l * l + m;
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(2
   // scalars: zbar_0[0:C] = hbar_0 * SiLU'(z_0[0:C]), hbar_0 = w_read (root atoms) + W_up_0 h~bar_0
   stage_tiles<NU>(sU, (const bf16x8*)a.up[0]);
   stage_tiles<NVT>(sV, VT0);
-  __syncthreads();
+  lds_dma_sync();
   if (act) {
     f32x4 hb[MTC];
     hbar_row(0, hb);
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(2
   for (int l = 1; l <= L; ++l) {
     __syncthreads();
     stage_tiles<NVT>(sV, VT0 + (size_t)l * NVT * 64);
-    __syncthreads();
+    lds_dma_sync();
     f32x4 s[MTC], dg[MTC];
     if (act) {
       bf16x8 q0[KCQ];
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(2
     stage_tiles<NU>(sU, (const bf16x8*)a.up[l]);
     stage_tiles<NVT>(sV, (const bf16x8*)a.vwt[l]);
     stage_tiles<D::NVW>(sP, (const bf16x8*)a.vw[l]);
-    __syncthreads();
+    lds_dma_sync();
     if (act) {
       for (int m = 0; m < 2 * l + 1; ++m) {
         const int lm = l * l + m;
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(2
   for (int hf = 0; hf < 2; ++hf) {
     __syncthreads();
     stage_tiles<D::NP0>(sW, (const bf16x8*)a.vw[0] + (size_t)hf * D::NP0 * 64);
-    __syncthreads();
+    lds_dma_sync();
     if (act)
       lds_rows<MTP / 2, NZC>(sW, NZC, 0, z0b, lane, [&](int mt, f32x4 d) {
         if (av) ps.put(hf * (MTP / 2) + mt, d, dst);
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(4
   __shared__ bf16x8 sDt[MT * KC * 64], sD[MT * KC * 64];
   stage_tiles<MT * KC>(sDt, (const bf16x8*)a.dt);
   stage_tiles<MT * KC>(sD, (const bf16x8*)a.d);
-  __syncthreads();
+  lds_dma_sync();
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
   const int64_t a0 = ((int64_t)blockIdx.x * kN1Waves + (threadIdx.x >> 6)) * 16;
   if (a0 >= a.n) return;
