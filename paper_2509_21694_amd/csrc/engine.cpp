@@ -628,7 +628,7 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K, int prec =
       p.o_msg = take(cur, (prec == MPIP_BF16_MIXED ? sizeof(uint16_t) : sizeof(float)) * cap * C);
     if (K >= 3) p.o_part = take(cur, sizeof(float) * kPartStride * cap);
     p.o_atom_e = take(cur, sizeof(double) * N);
-    p.nblocks_out = (int)((N + 255) / 256);
+    p.nblocks_out = (int)((N + kOutRowsPerBlock - 1) / kOutRowsPerBlock);
     p.o_partials = take(cur, sizeof(double) * 10 * p.nblocks_out);
   }
   p.total = cur + 256;

@@ -47,6 +47,14 @@ __device__ __forceinline__ f32x4 mfma_bf16_k16(s16x4 a, s16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// Transposing LDS read of 16-bit data.  In each group of 16 lanes, lane m
+// names 4 consecutive elements, which the group's 16 addresses take as row
+// m / 4, columns 4 (m % 4) .. 4 (m % 4) + 3 of a 4 x 16 matrix T; lane i of
+// the group receives column i, (T[0][i], T[1][i], T[2][i], T[3][i]).
+__device__ __forceinline__ s16x4 lds_read_tr16(const void* p) {
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4*)p);
+}
+
 __device__ __forceinline__ bool fast_guard(const FastArgs& a) {
   return (int64_t)a.row_ptr[a.n] > a.capacity || a.status[ST_FLAGS] != 0;
 }
@@ -597,9 +605,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 // edges); X is a 16x16x16 MFMA of the row's features (transposed through a
 // wave-private LDS slice, one row per row) with YC masked to degree l; the
 // products with dA_j feed the MLP adjoint (B operand) and dE/dYC (an MFMA
-// against the row's features); for the pull they are transposed to edges x
-// channels by an MFMA with a 0/1 selection matrix (column n of half tt is
-// channel 32k + 2n + tt) and summed with YC^T over the tile's edges.
+// against the row's features); for the pull, R dA is written to a wave-private
+// LDS tile (edges x 32 channels), read back transposed (lds_read_tr16: lane
+// (g, n) receives channel 16 tt + n of edges 4g .. 4g + 3, the B operand of a
+// 16x16x16 MFMA over edges) and summed with YC^T over the tile's edges.
 template <int C, int L, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_l2_adj(FastArgs a) {
   typedef Op<1> O;
@@ -612,7 +621,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
   __shared__ bf16x8 sWB[(L + 1) * 4 * KCC * 64];
   __shared__ bf16x8 sM1[4 * 64], sM2[4 * 2 * 64], sB2[4 * 2 * 64], sB1[2 * 64];
   __shared__ unsigned sHT[NW][C * HT / 2];
-  __shared__ float sY[NW][kTileE * 17];
+  __shared__ __align__(16) float sY[NW][kTileE * 20];
   if (fast_guard(a)) return;
   const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
@@ -626,13 +635,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   unsigned* sh = sHT[wv];
   float* syc = sY[wv];
+  // the pull's transposition tile (edges x 32 channels, BF16, rows padded to
+  // 80 bytes against bank conflicts) reuses the YC slice, which is free once
+  // the pull operands ya are formed
+  constexpr int TRS = 40;
+  unsigned short* str = (unsigned short*)syc;
+  static_assert(kTileE * 20 * 4 >= kTileE * TRS * 2, "transposition tile fits the YC slice");
   const unsigned short* ht = (const unsigned short*)a.ht;
-  // 0/1 selection operands of the transposition
-  bf16x8 sel[2];
-#pragma unroll
-  for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) sel[tt][j] = (__bf16)((8 * g + j == 2 * el + tt) ? 1.f : 0.f);
   const RowWalk rw = row_walk<NW>(a.n);
   for (int64_t i = rw.i; i < rw.end; i += rw.step) {
     const int e0 = a.row_ptr[i], e1 = a.row_end ? a.row_end[i] : a.row_ptr[i + 1];
@@ -667,6 +676,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       const bool valid = e < e1;
       const int j = valid ? a.e_src[e] : 0;
       const float* Aj = a.Abar + (int64_t)j * C + 8 * g;
+      wave_lds_sync();   // the previous tile's transposition reads are done
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
       edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
@@ -762,11 +772,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
           for (int mt = 0; mt < 4; ++mt) ab2[mt] = O::mma(sWB[((l * 4 + mt) * KCC + k) * 64 + lane], rb, ab2[mt]);
           // dE/dYC: D[lm][edge] += ht_i[lm][chunk] (R dA)[chunk][edge]
           dy[l] = O::mma(hr, ra, dy[l]);
-          // pull: transpose (R dA) to edges x channels, then sum over the tile's edges
+          // pull: (R dA) through the LDS tile to edges x channels, summed over
+          // the tile's edges.  The LDS executes a wave's accesses in order and
+          // the write and the reads may alias, so they stay in program order
+          // without a wave barrier, which would also hold back the weight reads.
+          *(bf16x8*)(str + el * TRS + 8 * g) = ra;
 #pragma unroll
           for (int tt = 0; tt < 2; ++tt) {
-            const f32x4 tr = O::mma(ra, sel[tt], (f32x4){0.f, 0.f, 0.f, 0.f});
-            hb[k][tt] = mfma_bf16_k16(ya[l], pk4_bf16(tr), hb[k][tt]);
+            const s16x4 tr = lds_read_tr16(str + (4 * g + el / 4) * TRS + 16 * tt + 4 * (el % 4));
+            hb[k][tt] = mfma_bf16_k16(ya[l], tr, hb[k][tt]);
           }
         });
       });
@@ -794,22 +808,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         }
       }
     }
-    // htbar_i: D rows lm = 4g + r, column el of half tt = channel 32k + 2 el + tt
+    // htbar_i: D rows lm = 4g + r, column el of half tt = channel 32k + 16 tt + el
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int lm = 4 * g + r;
       if (lm < NLM) {
-        const int64_t o = ((int64_t)i * NLM + lm) * C + 2 * el;
+        const int64_t o = ((int64_t)i * NLM + lm) * C + el;
 #pragma unroll
-        for (int k = 0; k < NK; ++k) {
-          if (a.htbar_bf16) {
-            const unsigned w = (unsigned)(unsigned short)bfbits(hb[k][0][r]) |
-                               ((unsigned)(unsigned short)bfbits(hb[k][1][r]) << 16);
-            *(unsigned*)((unsigned short*)a.htbar + o + 32 * k) = w;
-          } else {
-            *(float2*)(a.htbar + o + 32 * k) = make_float2(hb[k][0][r], hb[k][1][r]);
+        for (int k = 0; k < NK; ++k)
+#pragma unroll
+          for (int tt = 0; tt < 2; ++tt) {
+            if (a.htbar_bf16) ((short*)a.htbar)[o + 32 * k + 16 * tt] = bfbits(hb[k][tt][r]);
+            else a.htbar[o + 32 * k + 16 * tt] = hb[k][tt][r];
           }
-        }
       }
     }
     wave_lds_sync();

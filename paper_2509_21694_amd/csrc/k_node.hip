@@ -294,34 +294,50 @@ void launch_gate_bwd(const NodeArgs& a, int last, int init_hbar, hipStream_t s) 
 // order, with G_e = g[e] (dE/dr_e, or the h_e of FastArgs::g2p, which gives
 // the same sums); per block: sum of root energies and of r_e (x) G_e, fixed
 // order.
-// A wave takes 64 rows, 4 at a time with 16 lanes over each row's edges and
-// a 16-lane butterfly per row; each lane keeps its virial partial sums.
+// A wave takes 16 rows, 4 at a time with 16 lanes over each row's edges
+// (three edges per lane in flight, so a row of up to 48 edges costs one
+// round of dependent loads) and a 16-lane butterfly per row; each lane keeps
+// its virial partial sums, reduced over the wave by shuffles and over the
+// block's 4 waves in LDS, always in the same order.
 __global__ __launch_bounds__(256) void k_forces(OutArgs a) {
-  __shared__ double sh[10][256];
+  __shared__ double sh[4][10];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, el = lane & 15;
   double loc[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) loc[k] = 0.0;
   const bool run = (a.status[ST_FLAGS] == 0) && ((int64_t)a.row_ptr[a.n] <= a.capacity);
   if (run) {
-    const int64_t r0 = (int64_t)blockIdx.x * 256 + w * 64;
-    for (int64_t ib = r0; ib < r0 + 64; ib += 4) {
+    const int64_t r0 = (int64_t)blockIdx.x * kOutRowsPerBlock + w * 16;
+#pragma unroll 1
+    for (int64_t ib = r0; ib < r0 + 16; ib += 4) {
       const int64_t i = ib + q;
       double F[3] = {0.0, 0.0, 0.0};
       if (i < a.n) {
-        for (int e = a.row_ptr[i] + el; e < a.row_ptr[i + 1]; e += 16) {
-          const int rv = a.e_rev[e];
-          const float4 ge = a.g[e];
-          const float4 gr = rv >= 0 ? a.g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
-          const float4 r = a.e_vec[e];
-          F[0] += (double)ge.x - (double)gr.x;
-          F[1] += (double)ge.y - (double)gr.y;
-          F[2] += (double)ge.z - (double)gr.z;
-          const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
+        const int e1 = a.row_ptr[i + 1];
+        for (int e = a.row_ptr[i] + el; e < e1; e += 48) {
+          int rv[3];
+          float4 ge[3], gr[3], r[3];
 #pragma unroll
-          for (int p = 0; p < 3; ++p)
+          for (int u = 0; u < 3; ++u) {
+            const int eu = e + 16 * u;
+            const bool ok = eu < e1;
+            rv[u] = ok ? a.e_rev[eu] : -1;
+            ge[u] = ok ? a.g[eu] : make_float4(0.f, 0.f, 0.f, 0.f);
+            r[u] = ok ? a.e_vec[eu] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) loc[1 + 3 * p + c] += rr[p] * gg[c];
+          for (int u = 0; u < 3; ++u) gr[u] = rv[u] >= 0 ? a.g[rv[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            F[0] += (double)ge[u].x - (double)gr[u].x;
+            F[1] += (double)ge[u].y - (double)gr[u].y;
+            F[2] += (double)ge[u].z - (double)gr[u].z;
+            const double rr[3] = {r[u].x, r[u].y, r[u].z}, gg[3] = {ge[u].x, ge[u].y, ge[u].z};
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) loc[1 + 3 * p + c] += rr[p] * gg[c];
+          }
         }
       }
 #pragma unroll
@@ -339,15 +355,16 @@ __global__ __launch_bounds__(256) void k_forces(OutArgs a) {
     }
   }
 #pragma unroll
-  for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = loc[k];
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off)
+  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-      for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x < 10) a.partials[(int64_t)blockIdx.x * 10 + threadIdx.x] = sh[threadIdx.x][0];
+    for (int k = 0; k < 10; ++k) loc[k] += __shfl_xor(loc[k], off);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) sh[w][k] = loc[k];
+  __syncthreads();
+  if (threadIdx.x < 10)
+    a.partials[(int64_t)blockIdx.x * 10 + threadIdx.x] =
+        ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
 }
 
 __global__ void k_final(OutArgs a) {

@@ -295,10 +295,11 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(2
     if (act) {
       for (int m = 0; m < 2 * l + 1; ++m) {
         const int lm = l * l + m;
-        f32x4 hb[MTC];
-        hbar_row(lm, hb);
+        // both rows' loads issued before the first product, so their latencies overlap
         bf16x8 ql[KCQ];
         qload(lm, ql);
+        f32x4 hb[MTC];
+        hbar_row(lm, hb);
         // z_lm consumed tile by tile: dgate += hbar z, zbar_lm = hbar sigmoid(gate) (in hb)
         lds_rows<MTC, KCQ>(sV, KCQ, 0, ql, lane, [&](int mt, f32x4 d) {
 #pragma unroll

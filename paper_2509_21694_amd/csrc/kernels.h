@@ -296,6 +296,9 @@ void launch_gate_fwd(const NodeArgs& a, int first, int last, hipStream_t s);
 void launch_readout(const NodeArgs& a, hipStream_t s);
 void launch_gate_bwd(const NodeArgs& a, int last, int init_hbar, hipStream_t s);
 
+// rows per workgroup of the force / virial output pass
+constexpr int kOutRowsPerBlock = 64;
+
 struct OutArgs {
   int64_t n;
   const int32_t* row_ptr;
@@ -307,7 +310,7 @@ struct OutArgs {
   const double* atom_e;
   int64_t capacity;
   const int64_t* status;
-  double* partials;       // [nblocks][10]
+  double* partials;       // [nblocks][10], nblocks = ceil(n / kOutRowsPerBlock)
   int nblocks;
   double* forces;         // out [N][3] input order
   double* atom_energy;    // out [N] or null
