@@ -32,6 +32,8 @@ struct GridParams {
   int nbins;
   int mbits[3];        // bits per dimension of the bins' space-filling-curve rank
   int nrank;           // size of the rank space, 2^(mbits[0]+mbits[1]+mbits[2])
+  float pf_rc2;        // r_c^2 in FP32, and the half-width of the band around it (and above 0) in
+  float pf_margin;     // which the FP32 prefilter defers to the FP64 predicate; < 0: prefilter off
 };
 
 // ---- MFMA wrappers (16x16 output tile, 64 lanes) --------------------------

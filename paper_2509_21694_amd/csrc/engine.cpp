@@ -562,7 +562,8 @@ struct LayerOffsets {
 struct Plan {
   size_t total = 0;
   size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_rcount, o_rstart, o_scan, o_info, o_perm, o_iperm, o_pos,
-      o_info_s, o_spec, o_owned, o_cnt, o_row, o_blk, o_cmask, o_esrc, o_eshift, o_evec, o_erev, o_edst, o_g;
+      o_info_s, o_spec, o_owned, o_cnt, o_row, o_blk, o_cmask, o_esrc, o_eshift, o_evec, o_erev, o_edst, o_g,
+      o_ypos;
   size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
   size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
   size_t o_msg = 0; // last-layer messages of the BF16 form, [max_edges][C] bf16
@@ -598,6 +599,7 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K, int prec =
   p.o_iperm = take(cur, sizeof(int32_t) * N);
   p.o_pos = take(cur, sizeof(double) * 3 * N);
   p.o_info_s = take(cur, sizeof(int4) * N);
+  p.o_ypos = take(cur, sizeof(float4) * N);
   p.o_spec = take(cur, sizeof(int32_t) * N);
   p.o_owned = take(cur, N);
   p.o_cnt = take(cur, sizeof(int32_t) * N);
@@ -675,6 +677,7 @@ NbrBuffers nbr_buffers(char* ws, const Plan& p) {
   b.inv_perm = (int32_t*)(ws + p.o_iperm);
   b.pos_s = (double*)(ws + p.o_pos);
   b.info_s = (int4*)(ws + p.o_info_s);
+  b.ypos_s = (float4*)(ws + p.o_ypos);
   b.spec_s = (int32_t*)(ws + p.o_spec);
   b.owned_s = (uint8_t*)(ws + p.o_owned);
   b.cnt = (int32_t*)(ws + p.o_cnt);

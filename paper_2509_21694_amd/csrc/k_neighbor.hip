@@ -191,6 +191,36 @@ __global__ void k_grid(const double* __restrict__ part, int nparts, CellInfo ci,
     tot += bits;
   }
   g.nrank = 1 << tot;
+  // FP32 prefilter of the stencil search (orthorhombic cells): with the
+  // wrapped positions y (|y| <= Y per component) and per-block shifts s
+  // (|s| <= S) rounded to FP32 (unit roundoff u), each component of the FP32
+  // difference is within du = u (2Y + 2S + 2|d|) of the exact one, so for
+  // |d| <= sqrt(2) r_c the FP32 |d|^2 is within E = du (2 sqrt(6) r_c + 3 du)
+  // + 7 u r_c^2 of the exact (and of the FP64) value.  Outside a band of
+  // half-width 2E around r_c^2, and above 2E, the FP32 decision is the FP64
+  // one; the band (and near-coincident pairs) take the FP64 predicate.
+  {
+    bool ortho = true;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        if (a != b && ci.cell[3 * a + b] != 0.0) ortho = false;
+    double Y = 0.0, S = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      if (ci.pbc[d]) {
+        Y = fmax(Y, fabs(ci.cell[4 * d]) * (1.0 + 1e-6));
+        S = fmax(S, fabs(ci.cell[4 * d]));
+      } else {
+        Y = fmax(Y, fmax(fabs(mn[d]), fabs(mx[d])));
+      }
+    }
+    const double u = 1.0 / 8388608.0;   // 2^-23, twice FP32's unit roundoff
+    const double rc = ci.rc;
+    const double du = u * (2.0 * Y + 2.0 * S + 2.0 * 1.4142135623730951 * rc);
+    const double E = du * (2.0 * 2.449489742783178 * rc + 3.0 * du) + 7.0 * u * rc * rc + 1e-12 * rc * rc;
+    const bool finite = isfinite(Y) && Y < 1e7;
+    g.pf_rc2 = (float)(rc * rc);
+    g.pf_margin = (ortho && finite && 2.0 * E < 0.25 * rc * rc) ? (float)(2.0 * E * 1.01) : -1.0f;
+  }
   *gp = g;
   (void)status;
 }
@@ -284,16 +314,29 @@ __global__ void k_bin_sort(const GridParams* __restrict__ gp, const int32_t* __r
 
 __global__ void k_gather_sorted(const int32_t* __restrict__ perm, int64_t n, const double* __restrict__ pos,
                                 const int32_t* __restrict__ spec, const int4* __restrict__ info,
-                                int64_t n_owned, int n_species, double* __restrict__ pos_s, int4* __restrict__ info_s,
+                                int64_t n_owned, int n_species, CellInfo ci, double* __restrict__ pos_s,
+                                int4* __restrict__ info_s, float4* __restrict__ ypos_s,
                                 int32_t* __restrict__ spec_s, int32_t* __restrict__ inv_perm,
                                 uint8_t* __restrict__ owned_s) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= n) return;
   int o = perm[k];
-  pos_s[3 * k + 0] = pos[3 * (int64_t)o + 0];
-  pos_s[3 * k + 1] = pos[3 * (int64_t)o + 1];
-  pos_s[3 * k + 2] = pos[3 * (int64_t)o + 2];
-  info_s[k] = info[o];
+  const double x[3] = {pos[3 * (int64_t)o + 0], pos[3 * (int64_t)o + 1], pos[3 * (int64_t)o + 2]};
+  pos_s[3 * k + 0] = x[0];
+  pos_s[3 * k + 1] = x[1];
+  pos_s[3 * k + 2] = x[2];
+  const int4 io = info[o];
+  info_s[k] = io;
+  // y = x - sum_d image_d cell_d (the image counts are 0 in open dimensions)
+  const int im[3] = {io.x, io.y, io.z};
+  float y[3];
+  for (int c = 0; c < 3; ++c) {
+    double v = x[c];
+    for (int d = 0; d < 3; ++d)
+      if (im[d] != 0) v -= (double)im[d] * ci.cell[3 * d + c];
+    y[c] = (float)v;
+  }
+  ypos_s[k] = make_float4(y[0], y[1], y[2], 0.f);
   int sp = spec[o];  // out-of-range species are flagged by k_bounds; clamp so reads stay in bounds
   spec_s[k] = sp < 0 ? 0 : (sp >= n_species ? n_species - 1 : sp);
   inv_perm[o] = (int32_t)k;
@@ -410,6 +453,9 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
 // predicate, and the passing ones are compacted with a ballot so each row
 // is written contiguously.  Edge order (stencil block, then bin order) and
 // the per-block offsets blk are those of k_nbr.
+// sShift code of the stencil's central block (Sp = 0)
+constexpr int kCenterShift = 1 | (1 << 2) | (1 << 4);
+
 // position of the r-th (from 0) set bit of x; x has more than r set bits
 __device__ __forceinline__ int nth_set_bit(unsigned long long x, int r) {
   int pos = 0;
@@ -430,7 +476,8 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long x, int r) {
 
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restrict__ pos_s,
-                                               const int4* __restrict__ info_s, const int32_t* __restrict__ spec_s,
+                                               const int4* __restrict__ info_s, const float4* __restrict__ ypos_s,
+                                               const int32_t* __restrict__ spec_s,
                                                CellInfo ci, const GridParams* __restrict__ gp,
                                                const int32_t* __restrict__ bin_start,
                                                const int32_t* __restrict__ bin_count, int32_t* __restrict__ blk,
@@ -439,6 +486,7 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
                                                uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec,
                                                uint64_t* __restrict__ cmask, int64_t* __restrict__ status) {
   __shared__ int sPre[4][28], sStart[4][27], sShift[4][27], sCnt[4][27];
+  __shared__ float4 sSf[4][27];   // the blocks' shifts Sp . cell, rounded to FP32 (prefilter)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = blockIdx.x * 4 + wv;
   const GridParams g = *gp;
@@ -474,6 +522,16 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
     }
     sStart[wv][lane] = bs;
     sShift[wv][lane] = (Sp[0] + 1) | ((Sp[1] + 1) << 2) | ((Sp[2] + 1) << 4);
+    float sf[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      double v = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (Sp[d] != 0) v += (double)Sp[d] * ci.cell[3 * d + cc];
+      sf[cc] = (float)v;
+    }
+    sSf[wv][lane] = make_float4(sf[0], sf[1], sf[2], 0.f);
     sCnt[wv][lane] = 0;
   }
   // exclusive prefix of the bin sizes over lanes 0..26
@@ -489,6 +547,8 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
   wave_lds_sync();
   const double xi[3] = {pos_s[3 * i], pos_s[3 * i + 1], pos_s[3 * i + 2]};
   const double rc2 = ci.rc * ci.rc;
+  const bool pf_on = g.pf_margin >= 0.f;
+  const float4 yi = ypos_s[i];
   const int64_t out = FILL ? row_ptr[i] : 0;
   int count = 0, coincident = 0;
   // candidate f: stencil block k (last with pre[k] <= f; empty bins share the
@@ -566,15 +626,29 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
         if (k + step < 27 && sPre[wv][k + step] <= f) k += step;
       j = sStart[wv][k] + (f - sPre[wv][k]);
       const int sc = sShift[wv][k];
-      const int Sp[3] = {(sc & 3) - 1, ((sc >> 2) & 3) - 1, ((sc >> 4) & 3) - 1};
-      const int4 oj = info_s[j];
-      S[0] = ci.pbc[0] ? Sp[0] - oj.x + me.x : 0;
-      S[1] = ci.pbc[1] ? Sp[1] - oj.y + me.y : 0;
-      S[2] = ci.pbc[2] ? Sp[2] - oj.z + me.z : 0;
-      if (!(j == i && S[0] == 0 && S[1] == 0 && S[2] == 0)) {
-        const double xj[3] = {pos_s[3 * (int64_t)j], pos_s[3 * (int64_t)j + 1], pos_s[3 * (int64_t)j + 2]};
-        pass = pair_test(xi, xj, ci, S[0], S[1], S[2], rc2, dx);
-        if (pass && dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+      // counting pass: the FP32 prefilter decides outside its band
+      int decided = 0;   // 1 pass, -1 fail, 0 FP64 predicate
+      if (!FILL && pf_on) {
+        const float4 yj = ypos_s[j], sf = sSf[wv][k];
+        const float d0 = (yj.x - yi.x) + sf.x, d1 = (yj.y - yi.y) + sf.y, d2 = (yj.z - yi.z) + sf.z;
+        const float q = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+        if (j == i && sc == kCenterShift) decided = -1;   // the atom itself (S = 0)
+        else if (q > g.pf_rc2 + g.pf_margin) decided = -1;
+        else if (q < g.pf_rc2 - g.pf_margin && q > g.pf_margin) decided = 1;
+      }
+      if (decided != 0) {
+        pass = decided > 0;
+      } else {
+        const int Sp[3] = {(sc & 3) - 1, ((sc >> 2) & 3) - 1, ((sc >> 4) & 3) - 1};
+        const int4 oj = info_s[j];
+        S[0] = ci.pbc[0] ? Sp[0] - oj.x + me.x : 0;
+        S[1] = ci.pbc[1] ? Sp[1] - oj.y + me.y : 0;
+        S[2] = ci.pbc[2] ? Sp[2] - oj.z + me.z : 0;
+        if (!(j == i && S[0] == 0 && S[1] == 0 && S[2] == 0)) {
+          const double xj[3] = {pos_s[3 * (int64_t)j], pos_s[3 * (int64_t)j + 1], pos_s[3 * (int64_t)j + 2]};
+          pass = pair_test(xi, xj, ci, S[0], S[1], S[2], rc2, dx);
+          if (pass && dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+        }
       }
     }
     const unsigned long long m = __ballot(pass);
@@ -824,17 +898,17 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   k_bin_start<<<gb, 256, 0, s>>>(b.grid, b.rank_start, b.bin_start);
   k_bin_fill<<<ga, nblk, 0, s>>>(b.info, n, b.bin_start, b.bin_cursor, b.perm);
   k_bin_sort<<<gb, 256, 0, s>>>(b.grid, b.bin_start, b.bin_count, b.perm);
-  k_gather_sorted<<<ga, nblk, 0, s>>>(b.perm, n, sys.positions, sys.species, b.info, sys.n_owned, ci.n_species, b.pos_s,
-                                      b.info_s, b.spec_s, b.inv_perm, b.owned_s);
+  k_gather_sorted<<<ga, nblk, 0, s>>>(b.perm, n, sys.positions, sys.species, b.info, sys.n_owned, ci.n_species, ci,
+                                      b.pos_s, b.info_s, b.ypos_s, b.spec_s, b.inv_perm, b.owned_s);
   // one of each pair does the work: k_nbr_w when all dimensions use the 27-bin stencil, else k_nbr
   const unsigned gw = (unsigned)((n + 3) / 4);
-  k_nbr_w<false><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt,
+  k_nbr_w<false><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.ypos_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt,
                                     nullptr, capacity, nullptr, nullptr, nullptr, b.cmask, b.status);
   k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt, nullptr,
                                    capacity, nullptr, nullptr, nullptr, b.status);
   exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
   k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
-  k_nbr_w<true><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr,
+  k_nbr_w<true><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.ypos_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr,
                                    b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.cmask, b.status);
   k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);

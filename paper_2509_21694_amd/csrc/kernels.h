@@ -30,6 +30,7 @@ struct NbrBuffers {
   int32_t* perm;         // [N] sorted position -> input index
   int32_t* inv_perm;     // [N]
   double* pos_s;         // [N,3] raw positions, sorted order
+  float4* ypos_s;        // [N] the positions minus their cell images, rounded to FP32 (prefilter)
   int4* info_s;          // [N]
   int32_t* spec_s;       // [N]
   uint8_t* owned_s;      // [N]
