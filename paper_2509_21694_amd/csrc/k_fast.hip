@@ -421,8 +421,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   __shared__ typename O::T sM1[NM1], sM2[NM2], sB2[NB2], sB1[NB1];
   // FP32 form: W1, W2 as row-major copies (one copy serves forward and adjoint)
   __shared__ float sR1[PREC == 0 ? 8 * 65 : 1], sR2[PREC == 0 ? 64 * 65 : 1];
-  constexpr int SYB = 16 * MQ + 1;   // odd row stride: the 16 edge lanes hit distinct banks
+  // dE/dYC rows of the tile: row el (edge), q = 16 mq + 4 g + r stored at
+  // 16 g + 4 mq + r (sy_pos), row stride 65: a D-tile store's 64 lanes meet
+  // each bank twice, the fewest for 64 words
+  static_assert(MQ <= 4, "dE/dYC row layout");
+  constexpr int SYB = 65;
   __shared__ float sYB[NW][kTileE * SYB];
+  auto sy_pos = [](int q) { return 16 * ((q & 15) >> 2) + 4 * (q >> 4) + (q & 3); };
   if (fast_guard(a)) return;
   const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
@@ -439,9 +444,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* syb = sYB[wv];
   // BF16 form: P rows staged as [q][64] (q < 16 MQ, zero past MROWS) plus
-  // 4 zero rows, which the pa reads of species >= S may reach
-  constexpr int PW = (PREC == 1) ? 16 * MQ * 64 + 256 : 8;   // BF16 elements
-  constexpr int NPL = (PW / 8 + 63) / 64;                      // 16-byte pieces per lane
+  // 4 zero rows, which the pa reads of species >= S may reach; rows padded to
+  // PRS = 80 elements (40 words), so the pb reads (16 rows x 4 lane groups of
+  // 8 bytes) meet each bank 4 times and the pa reads (4 rows x 16 lanes) once
+  constexpr int PRS = 80, PROWS = 16 * MQ + 4;
+  constexpr int PW = (PREC == 1) ? PROWS * PRS : 8;         // BF16 elements
+  constexpr int NPL = (PROWS * 8 + 63) / 64;                   // 16-byte pieces per lane (8 a row)
   __shared__ uint4 sPr[NW][PW / 8];
   const unsigned short* sPw = (const unsigned short*)sPr[wv];
   constexpr int pieces = NLM * KQ / 8;
@@ -462,7 +470,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
       for (int q = 0; q < NPL; ++q) {
         const int pc = q * 64 + lane;
-        if (pc < PW / 8) sPr[wv][pc] = praw[q];
+        if (pc < PROWS * 8) sPr[wv][(pc >> 3) * (PRS / 8) + (pc & 7)] = praw[q];
       }
       wave_lds_sync();
     }
@@ -482,11 +490,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         const int sg = c / KCL, lc = c % KCL;
         if constexpr (PREC == 1) {
           // species 4 sg + g, lm = 8 lc + j, hidden 16 mt + el
-          const unsigned short* src = sPw + (4 * sg + g) * 64 + 16 * mt + el;
+          const unsigned short* src = sPw + (4 * sg + g) * PRS + 16 * mt + el;
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             const int lm = 8 * lc + j;
-            pa[mt][c][j] = lm < NLM ? __builtin_bit_cast(__bf16, src[lm * KQ]) : (__bf16)0.f;
+            pa[mt][c][j] = lm < NLM ? __builtin_bit_cast(__bf16, src[lm * S * PRS]) : (__bf16)0.f;
           }
         } else {
           const int sp_ = 4 * sg + g;
@@ -497,7 +505,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
     for (int mq = 0; mq < MQ; ++mq) {
       const int qq = 16 * mq + el;
       if constexpr (PREC == 1) {
-        const unsigned short* src = sPw + qq * 64 + 4 * g;
+        const unsigned short* src = sPw + qq * PRS + 4 * g;
 #pragma unroll
         for (int kc = 0; kc < O::KC64; ++kc) {
           const uint2 lo = *(const uint2*)(src + 32 * kc), hi = *(const uint2*)(src + 32 * kc + 16);
@@ -560,7 +568,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
         for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(pb[mq][kc], O::from_tiles(a2, kc), acc);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) syb[el * SYB + 16 * mq + 4 * g + r] = acc[r];
+        for (int r = 0; r < 4; ++r) syb[el * SYB + 16 * g + 4 * mq + r] = acc[r];
       }
       float eb[kNB];
       if constexpr (PREC == 1) mlp_backward_reg<PREC>(ab2, p1, p2, lane, sB2, sB1, eb);
@@ -571,7 +579,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
         for (int k = 0; k < kMaxNlm; ++k) Yb[k] = 0.f;
 #pragma unroll
-        for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + k * S + sp];
+        for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + sy_pos(k * S + sp)];
         yc_last_adj<L>(cgd, ycb, Yb);
         if (a.g2p) {
           // h_e = (this layer's dE/dr_e) - g2p[e], where g2p[e] is the last
