@@ -388,5 +388,27 @@ __device__ __forceinline__ RowWalk row_walk(int64_t n) {
   return {r0 + (int64_t)lb * NW + (threadIdx.x >> 6), r1, (int64_t)BX * NW};
 }
 
+// Edge ranges of a wave's current row and of its next row along a RowWalk
+// (the next row's bounds are read a row ahead), so that a tile loop can
+// request the first tile of the next row while it works on its last one.
+// row_end: the walked prefix of each row (receptive-field trimming), or null.
+struct RowAhead {
+  int64_t i, end, step;
+  int e0, e1, n0, n1;
+  __device__ __forceinline__ RowAhead(const RowWalk& rw, const int32_t* row_ptr, const int32_t* row_end)
+      : i(rw.i), end(rw.end), step(rw.step), e0(0), e1(0), n0(0), n1(0) {
+    if (i < end) { e0 = row_ptr[i]; e1 = row_end ? row_end[i] : row_ptr[i + 1]; }
+    if (i + step < end) { n0 = row_ptr[i + step]; n1 = row_end ? row_end[i + step] : row_ptr[i + step + 1]; }
+  }
+  __device__ __forceinline__ bool has_row() const { return i < end; }
+  __device__ __forceinline__ bool has_next() const { return i + step < end; }
+  __device__ __forceinline__ void advance(const int32_t* row_ptr, const int32_t* row_end) {
+    i += step;
+    e0 = n0;
+    e1 = n1;
+    if (i + step < end) { n0 = row_ptr[i + step]; n1 = row_end ? row_end[i + step] : row_ptr[i + step + 1]; }
+  }
+};
+
 
 }  // namespace mpip

@@ -476,8 +476,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
     }
   };
   p_fetch(rw.i);
-  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+  // each tile's edge vectors are requested during the tile before it
+  RowAhead ra(rw, a.row_ptr, nullptr);
+  float4 pv = make_float4(1.f, 0.f, 0.f, 0.f);
+  auto fetch = [&](int e, int end) { pv = e < end ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f); };
+  if (ra.has_row()) fetch(ra.e0 + el, ra.e1);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step, ra.advance(a.row_ptr, nullptr)) {
+    const int e0 = ra.e0, e1 = ra.e1;
+    if (e0 >= e1 && ra.has_next()) fetch(ra.n0 + el, ra.n1);
     p_stage();
     p_fetch(i + rw.step);
     const float* Pi = a.P + (int64_t)i * NLM * KQ;
@@ -521,7 +527,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       const int e = t0 + el;
       const bool valid = e < e1;
       Geo geo;
-      const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
+      const float4 v = pv;
+      if (t0 + kTileE < e1) fetch(t0 + kTileE + el, e1);
+      else if (ra.has_next()) fetch(ra.n0 + el, ra.n1);
+      // the last layer's reverse-edge gradient of this edge, requested early
+      const float4 gq = (a.g2p && lane < kTileE && valid) ? a.g2p[e] : make_float4(0.f, 0.f, 0.f, 0.f);
       edge_geometry(v, valid, gk, geo);
       const int sp = valid ? __float_as_int(v.w) : -1;
       float yc[NLM];
@@ -587,8 +597,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
           // and the virial is -sum_e r_e (x) h_e (r_rev(e) = -r_e), so the
           // outputs gather one array through the reverse edges instead of two
           const float4 d = edge_grad(geo, eb, Yb);
-          const float4 q = a.g2p[e];
-          a.g[e] = make_float4(d.x - q.x, d.y - q.y, d.z - q.z, 0.f);
+          a.g[e] = make_float4(d.x - gq.x, d.y - gq.y, d.z - gq.z, 0.f);
         } else {
           add_edge_grad(a.g, e, geo, eb, Yb);
         }
@@ -651,8 +660,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
   static_assert(kTileE * 20 * 4 >= kTileE * TRS * 2, "transposition tile fits the YC slice");
   const unsigned short* ht = (const unsigned short*)a.ht;
   const RowWalk rw = row_walk<NW>(a.n);
-  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_end ? a.row_end[i] : a.row_ptr[i + 1];
+  // each tile's senders and edge vectors are requested during the tile before it
+  RowAhead rah(rw, a.row_ptr, a.row_end);
+  float4 pv = make_float4(-1.f, 0.f, 0.f, 0.f);
+  int pj = 0;
+  auto fetch = [&](int e, int end) {
+    const bool ok = e < end;
+    pj = ok ? a.e_src[e] : 0;
+    pv = ok ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
+  };
+  if (rah.has_row()) fetch(rah.e0 + el, rah.e1);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step, rah.advance(a.row_ptr, a.row_end)) {
+    const int e0 = rah.e0, e1 = rah.e1;
+    if (e0 >= e1 && rah.has_next()) fetch(rah.n0 + el, rah.n1);
     const unsigned short* hi = ht + (int64_t)i * NLM * C;
     // the row's features, transposed: sh[c][lm] (degrees NLM .. HT-1 zero)
 #pragma unroll
@@ -682,11 +702,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     for (int t0 = e0; t0 < e1; t0 += kTileE) {
       const int e = t0 + el;
       const bool valid = e < e1;
-      const int j = valid ? a.e_src[e] : 0;
+      const int j = pj;
+      const float4 v = pv;
+      if (t0 + kTileE < e1) fetch(t0 + kTileE + el, e1);
+      else if (rah.has_next()) fetch(rah.n0 + el, rah.n1);
       const float* Aj = a.Abar + (int64_t)j * C + 8 * g;
+      // dA_j of the first channel chunk, requested before the geometry
+      float4 an0 = *(const float4*)Aj, an1 = *(const float4*)(Aj + 4);
       wave_lds_sync();   // the previous tile's transposition reads are done
       Geo geo;
-      const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
       edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
@@ -744,7 +768,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       f32x4 dy[L + 1];
 #pragma unroll
       for (int l = 0; l <= L; ++l) dy[l] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      float4 an0 = *(const float4*)Aj, an1 = *(const float4*)(Aj + 4);
       bf16x8 hn = *(const bf16x8*)(hi + (int64_t)(el < NLM ? el : 0) * C + 8 * g);
       static_for<NK>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
@@ -863,8 +886,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
   const unsigned short* ht = (const unsigned short*)a.ht;
   unsigned short* M = (unsigned short*)a.msg;
   const RowWalk rw = row_walk<NW>(a.n);
-  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_end ? a.row_end[i] : a.row_ptr[i + 1];
+  // each tile's reverse edges and edge vectors are requested during the tile before it
+  RowAhead rah(rw, a.row_ptr, a.row_end);
+  float4 pv = make_float4(-1.f, 0.f, 0.f, 0.f);
+  int prv = -1;
+  auto fetch = [&](int e, int end) {
+    const bool ok = e < end;
+    prv = ok ? a.e_rev[e] : -1;
+    pv = ok ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
+  };
+  if (rah.has_row()) fetch(rah.e0 + el, rah.e1);
+  for (int64_t i = rw.i; i < rw.end; i += rw.step, rah.advance(a.row_ptr, a.row_end)) {
+    const int e0 = rah.e0, e1 = rah.e1;
+    if (e0 >= e1 && rah.has_next()) fetch(rah.n0 + el, rah.n1);
     const unsigned short* hi = ht + (int64_t)i * NLM * C;
     // the row's features, transposed: sh[c][lm] (degrees NLM .. HT-1 zero)
 #pragma unroll
@@ -889,9 +923,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
     for (int t0 = e0; t0 < e1; t0 += kTileE) {
       const int e = t0 + el;
       const bool valid = e < e1;
-      const int rv = valid ? a.e_rev[e] : -1;
+      const int rv = prv;
+      const float4 v = pv;
+      if (t0 + kTileE < e1) fetch(t0 + kTileE + el, e1);
+      else if (rah.has_next()) fetch(rah.n0 + el, rah.n1);
       Geo geo;
-      const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
       edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
