@@ -626,6 +626,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 // LDS tile (edges x 32 channels), read back transposed (lds_read_tr16: lane
 // (g, n) receives channel 16 tt + n of edges 4g .. 4g + 3, the B operand of a
 // 16x16x16 MFMA over edges) and summed with YC^T over the tile's edges.
+#ifndef MPIP_ADJ_WPF
+#define MPIP_ADJ_WPF 2
+#endif
+constexpr int kAdjWPF = MPIP_ADJ_WPF;   // W3 tiles in flight in the fused adjoint's chunk loop
 template <int C, int L, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_l2_adj(FastArgs a) {
   typedef Op<1> O;
@@ -769,6 +773,24 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
       for (int l = 0; l <= L; ++l) dy[l] = (f32x4){0.f, 0.f, 0.f, 0.f};
       bf16x8 hn = *(const bf16x8*)(hi + (int64_t)(el < NLM ? el : 0) * C + 8 * g);
+      // W3 operand tiles in the order the chunk loop uses them (per chunk k
+      // and degree l: the four R tiles (hh, kc), then the four MLP-adjoint
+      // tiles mt), read from LDS WPF steps ahead of their MFMA through a ring
+      // of registers, so the LDS latency is not paid by each MFMA
+      constexpr int WPL = 8, WPK = (L + 1) * WPL, NWS = NK * WPK;
+      auto wtile = [&](auto sc) -> bf16x8 {
+        constexpr int st = decltype(sc)::value, k = st / WPK, l = (st % WPK) / WPL, w = st % WPL;
+        if constexpr (w < 4) return sW[((l * CN + 2 * k + (w >> 1)) * 2 + (w & 1)) * 64 + lane];
+        else return sWB[((l * 4 + (w - 4)) * KCC + k) * 64 + lane];
+      };
+      bf16x8 wring[kAdjWPF];
+      static_for<kAdjWPF>([&](auto pc) { wring[decltype(pc)::value] = wtile(pc); });
+      auto wtake = [&](auto sc) -> bf16x8 {
+        constexpr int st = decltype(sc)::value;
+        const bf16x8 w = wring[st % kAdjWPF];
+        if constexpr (st + kAdjWPF < NWS) wring[st % kAdjWPF] = wtile(std::integral_constant<int, st + kAdjWPF>{});
+        return w;
+      };
       static_for<NK>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
         __builtin_amdgcn_sched_barrier(0);
@@ -781,17 +803,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
           hn = *(const bf16x8*)(hi + (int64_t)(el < NLM ? el : 0) * C + 32 * (k + 1) + 8 * g);
         }
         static_for<L + 1>([&](auto lc) {
-          constexpr int l = decltype(lc)::value;
+          constexpr int l = decltype(lc)::value, s0 = k * WPK + l * WPL;
           float R8[8], X8[8];
-#pragma unroll
-          for (int hh = 0; hh < 2; ++hh) {
+          static_for<2>([&](auto hc) {
+            constexpr int hh = decltype(hc)::value;
             f32x4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < 2; ++kc) d = O::mma(sW[((l * CN + 2 * k + hh) * 2 + kc) * 64 + lane], bop[kc], d);
+            d = O::mma(wtake(std::integral_constant<int, s0 + 2 * hh>{}), bop[0], d);
+            d = O::mma(wtake(std::integral_constant<int, s0 + 2 * hh + 1>{}), bop[1], d);
             const f32x4 x = mfma_bf16_k16(hx[hh], yop[l], (f32x4){0.f, 0.f, 0.f, 0.f});
 #pragma unroll
             for (int r = 0; r < 4; ++r) { R8[4 * hh + r] = d[r]; X8[4 * hh + r] = x[r]; }
-          }
+          });
           bf16x8 rb, ra;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
@@ -799,8 +821,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
             ra[q] = (__bf16)(ai[q] * R8[q]);
           }
           // MLP adjoint through layer 3
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt) ab2[mt] = O::mma(sWB[((l * 4 + mt) * KCC + k) * 64 + lane], rb, ab2[mt]);
+          static_for<4>([&](auto mc) {
+            constexpr int mt = decltype(mc)::value;
+            ab2[mt] = O::mma(wtake(std::integral_constant<int, s0 + 4 + mt>{}), rb, ab2[mt]);
+          });
           // dE/dYC: D[lm][edge] += ht_i[lm][chunk] (R dA)[chunk][edge]
           dy[l] = O::mma(hr, ra, dy[l]);
           // pull: (R dA) through the LDS tile to edges x channels, summed over
