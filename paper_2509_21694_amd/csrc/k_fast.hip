@@ -476,10 +476,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
     }
   };
   p_fetch(rw.i);
-  // each tile's edge vectors are requested during the tile before it
+  // BF16 form: each tile's edge vectors are requested during the tile before
+  // it (the FP32 form, short of registers, loads them at the tile's start)
   RowAhead ra(rw, a.row_ptr, nullptr);
   float4 pv = make_float4(1.f, 0.f, 0.f, 0.f);
-  auto fetch = [&](int e, int end) { pv = e < end ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f); };
+  auto fetch = [&](int e, int end) {
+    if constexpr (PREC == 1) pv = e < end ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
+  };
   if (ra.has_row()) fetch(ra.e0 + el, ra.e1);
   for (int64_t i = rw.i; i < rw.end; i += rw.step, ra.advance(a.row_ptr, nullptr)) {
     const int e0 = ra.e0, e1 = ra.e1;
@@ -527,11 +530,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       const int e = t0 + el;
       const bool valid = e < e1;
       Geo geo;
-      const float4 v = pv;
-      if (t0 + kTileE < e1) fetch(t0 + kTileE + el, e1);
-      else if (ra.has_next()) fetch(ra.n0 + el, ra.n1);
-      // the last layer's reverse-edge gradient of this edge, requested early
-      const float4 gq = (a.g2p && lane < kTileE && valid) ? a.g2p[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 v;
+      if constexpr (PREC == 1) {
+        v = pv;
+        if (t0 + kTileE < e1) fetch(t0 + kTileE + el, e1);
+        else if (ra.has_next()) fetch(ra.n0 + el, ra.n1);
+      } else {
+        v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
+      }
+      // BF16 form: the last layer's reverse-edge gradient of this edge, requested early
+      float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (PREC == 1) gq = (a.g2p && lane < kTileE && valid) ? a.g2p[e] : gq;
       edge_geometry(v, valid, gk, geo);
       const int sp = valid ? __float_as_int(v.w) : -1;
       float yc[NLM];
@@ -597,6 +606,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
           // and the virial is -sum_e r_e (x) h_e (r_rev(e) = -r_e), so the
           // outputs gather one array through the reverse edges instead of two
           const float4 d = edge_grad(geo, eb, Yb);
+          if constexpr (PREC == 0) gq = a.g2p[e];
           a.g[e] = make_float4(d.x - gq.x, d.y - gq.y, d.z - gq.z, 0.f);
         } else {
           add_edge_grad(a.g, e, geo, eb, Yb);

@@ -239,6 +239,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(1))) vo
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* sh = sH[wv];
   float* syc = sY[wv];
+  for (int k = lane; k < 16 * SY; k += 64) syc[k] = 0.f;   // columns NLM .. SY-1 stay zero
   const float* ht = (const float*)a.ht;
   const float inv_n = a.inv_n;
   // degree of the pull's A-operand row lm = lane % 16
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(1))) vo
       float ya[L + 1][4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float y = el < NLM ? syc[(4 * q + g) * SY + (el < NLM ? el : 0)] : 0.f;
+        const float y = syc[(4 * q + g) * SY + el];   // columns NLM .. 15 are zero
 #pragma unroll
         for (int l = 0; l <= L; ++l) ya[l][q] = lml == l ? y : 0.f;
       }
@@ -308,12 +309,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(1))) vo
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
               ab2[mt] = mfma_f32(sW3[(16 * mt + el) * WS + l * C + 16 * t + 4 * g + r], dR[r], ab2[mt]);
-          // dE/dYC_l[lm][e] += sum_c h~[lm][c] RA[c][e]
+          // dE/dYC_l[lm][e] += sum_c h~[lm][c] RA[c][e]; rows lm >= NLM of the
+          // staged features are zero, so lanes el >= NLM read row NLMP - 1
+          const float4 hv4 = *(const float4*)(sh + (el < D::NLMP ? el : D::NLMP - 1) * C + 16 * t + 4 * g);
+          const float hv[4] = {hv4.x, hv4.y, hv4.z, hv4.w};
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float hv = el < NLM ? sh[(el < NLM ? el : 0) * C + 16 * t + 4 * g + r] : 0.f;
-            dy[l] = mfma_f32(hv, RA[r], dy[l]);
-          }
+          for (int r = 0; r < 4; ++r) dy[l] = mfma_f32(hv[r], RA[r], dy[l]);
           // pull: RA (channels x edges) to edges x channels through LDS, then
           // h~bar[lm][c] += sum_e YC[lm][e] RA[c][e]
           float* tt = sT[wv][par];
