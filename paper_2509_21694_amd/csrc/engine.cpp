@@ -1567,7 +1567,10 @@ mpip_status mpip_evaluate_batch(mpip_model* m, int32_t B, const int64_t* atom_pt
       c.pbc[d] = pbc[3 * b + d] ? 1 : 0;
       c.L[d] = c.cell[4 * d];
       if (c.pbc[d] && !(c.L[d] > 0.0)) return fail(MPIP_ECELL, "periodic cell length must be positive");
-      c.img[d] = c.pbc[d] ? (int)std::ceil(hp.r_cut / c.L[d]) + 1 : 0;
+      // positions are taken to their image in [0, L) before the search, so a
+      // pair within r_cut has |S_d| < r_cut / L + 1; the slack covers the
+      // rounding of the wrap
+      c.img[d] = c.pbc[d] ? (int)std::ceil(hp.r_cut / c.L[d] + 1e-6) : 0;
       if (c.img[d] > 60) return fail(MPIP_ECELL, "cell too thin for the cutoff");
     }
   }

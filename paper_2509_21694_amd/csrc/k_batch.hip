@@ -1,9 +1,11 @@
 // Batched evaluation of many small independent structures in one pass: the
 // structures' atoms are concatenated and the neighbour list is built per
 // structure, so the CSR is block diagonal and every per-layer kernel runs
-// once over all rows of all structures.  Small periodic cells (thinner than
-// three cutoff bins) are searched over all images |S_k| <= img_k; the
-// membership test is the same FP64 expression as for single structures.
+// once over all rows of all structures.  Each receiver scans its
+// structure's atoms and, per sender, only the periodic images that can lie
+// within the cutoff (|S_k| <= img_k); the membership test is the same FP64
+// expression as for single structures.  A row lists its edges by sender,
+// then image.
 #include "kernels.h"
 
 namespace mpip {
@@ -71,16 +73,39 @@ __global__ void k_batch_nbr(int64_t n, const double* __restrict__ pos, const int
   const double rc2 = rc * rc;
   int count = 0, coincident = 0;
   const int64_t out = FILL ? row_ptr[i] : 0;
-  for (int oz = -c.img[2]; oz <= c.img[2]; ++oz)
-    for (int oy = -c.img[1]; oy <= c.img[1]; ++oy)
-      for (int ox = -c.img[0]; ox <= c.img[0]; ++ox)
-        for (int64_t j = j0; j < j1; ++j) {
-          const int4 oj = info[j];
+  // wrapped coordinates of the receiver, for the image ranges only (the
+  // membership test below is the FP64 expression of the full search)
+  const int mi[3] = {me.x, me.y, me.z};
+  double yi[3], invL[3];
+  for (int d = 0; d < 3; ++d) {
+    yi[d] = c.pbc[d] ? xi[d] - (double)mi[d] * c.L[d] : 0.0;
+    invL[d] = c.pbc[d] ? 1.0 / c.L[d] : 0.0;
+  }
+  // per sender: along each periodic axis only the images o with
+  // |y_j - y_i + o L| < r_c can hold a pair (one or two of -img..img),
+  // widened by a slack far above the rounding of the wrapped coordinates
+  for (int64_t j = j0; j < j1; ++j) {
+    const int4 oj = info[j];
+    const double xj[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
+    const int ojn[3] = {oj.x, oj.y, oj.z};
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      if (c.pbc[d]) {
+        const double dy = (xj[d] - (double)ojn[d] * c.L[d]) - yi[d];
+        lo[d] = max(-c.img[d], (int)ceil((-rc - dy) * invL[d] - 1e-6));
+        hi[d] = min(c.img[d], (int)floor((rc - dy) * invL[d] + 1e-6));
+      } else {
+        lo[d] = 0;
+        hi[d] = 0;
+      }
+    }
+    for (int oz = lo[2]; oz <= hi[2]; ++oz)
+      for (int oy = lo[1]; oy <= hi[1]; ++oy)
+        for (int ox = lo[0]; ox <= hi[0]; ++ox) {
           const int S0 = c.pbc[0] ? ox - oj.x + me.x : 0;
           const int S1 = c.pbc[1] ? oy - oj.y + me.y : 0;
           const int S2 = c.pbc[2] ? oz - oj.z + me.z : 0;
           if (j == i && S0 == 0 && S1 == 0 && S2 == 0) continue;
-          const double xj[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
           double dx[3];
           if (batch_pair(xi, xj, c, S0, S1, S2, rc2, dx)) {
             if (dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
@@ -93,6 +118,7 @@ __global__ void k_batch_nbr(int64_t n, const double* __restrict__ pos, const int
             ++count;
           }
         }
+  }
   if (!FILL) cnt[i] = count;
   if (coincident) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_COINCIDENT);
 }

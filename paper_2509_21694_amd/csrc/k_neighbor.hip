@@ -157,7 +157,7 @@ __global__ void k_grid(const double* __restrict__ part, int nparts, CellInfo ci,
         g.nb[d] = nb; g.stencil[d] = 1; g.inv_bin[d] = (double)nb / L;
       } else {
         g.nb[d] = 1; g.stencil[d] = 0; g.inv_bin[d] = 0.0;
-        g.img[d] = (int)ceil(ci.rc / L) + 1;
+        g.img[d] = (int)ceil(ci.rc / L + 1e-6);   // wrapped positions: |S| < r_c / L + 1
       }
     } else {
       double ext = (mx[d] >= mn[d]) ? (mx[d] - mn[d]) : 0.0;
@@ -175,7 +175,7 @@ __global__ void k_grid(const double* __restrict__ part, int nparts, CellInfo ci,
     for (int k = 1; k < 3; ++k) if (g.nb[k] > g.nb[d]) d = k;
     int nb = g.nb[d] / 2;
     if (ci.pbc[d] && nb < 3) {
-      g.nb[d] = 1; g.stencil[d] = 0; g.inv_bin[d] = 0.0; g.img[d] = (int)ceil(ci.rc / ci.L[d]) + 1;
+      g.nb[d] = 1; g.stencil[d] = 0; g.inv_bin[d] = 0.0; g.img[d] = (int)ceil(ci.rc / ci.L[d] + 1e-6);
     } else {
       if (nb < 1) nb = 1;
       g.nb[d] = nb;
@@ -384,21 +384,25 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
   const int ni[3] = {me.x, me.y, me.z};
   double xi[3] = {pos_s[3 * i], pos_s[3 * i + 1], pos_s[3 * i + 2]};
   const double rc2 = ci.rc * ci.rc;
+  // stencil dimensions: the bins -1..1 around the atom's; dimensions
+  // thinner than three bins (periodic, one bin): per sender, only the
+  // images o with |y_j - y_i + o L| < r_c (y the wrapped coordinates), which
+  // are one or two of -img..img, widened by a slack far above the rounding
   int lo[3], hi[3];
+  double yi[3];
   for (int d = 0; d < 3; ++d) {
-    if (g.stencil[d]) { lo[d] = -1; hi[d] = 1; }
-    else { lo[d] = -g.img[d]; hi[d] = g.img[d]; }
+    lo[d] = g.stencil[d] ? -1 : 0;
+    hi[d] = g.stencil[d] ? 1 : 0;
+    yi[d] = g.stencil[d] ? 0.0 : xi[d] - (double)ni[d] * ci.L[d];
   }
   int count = 0;
   int64_t out = FILL ? row_ptr[i] : 0;
   int coincident = 0;
-  const bool stencil3 = g.stencil[0] && g.stencil[1] && g.stencil[2];
+  const bool stencil3 = false;   // the all-stencil case runs in k_nbr_w
   for (int oz = lo[2]; oz <= hi[2]; ++oz)
     for (int oy = lo[1]; oy <= hi[1]; ++oy)
       for (int ox = lo[0]; ox <= hi[0]; ++ox) {
         int o[3] = {ox, oy, oz};
-        // with a 27-bin stencil, the row's edges come in blocks by stencil offset
-        if (FILL && stencil3) blk[28 * i + ((oz + 1) * 3 + (oy + 1)) * 3 + (ox + 1)] = count;
         int c[3], Sp[3];
         bool skip = false;
         for (int d = 0; d < 3; ++d) {
@@ -413,7 +417,7 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
             c[d] = cc;
           } else {
             c[d] = 0;
-            Sp[d] = o[d];
+            Sp[d] = 0;
           }
         }
         if (skip) continue;
@@ -421,24 +425,39 @@ __global__ void k_nbr(int64_t n, const double* __restrict__ pos_s, const int4* _
         int s = bin_start[bin], e = s + bin_count[bin];
         for (int j = s; j < e; ++j) {
           int4 oj = info_s[j];
-          int S[3];
-          S[0] = ci.pbc[0] ? Sp[0] - oj.x + ni[0] : 0;
-          S[1] = ci.pbc[1] ? Sp[1] - oj.y + ni[1] : 0;
-          S[2] = ci.pbc[2] ? Sp[2] - oj.z + ni[2] : 0;
-          if (j == i && S[0] == 0 && S[1] == 0 && S[2] == 0) continue;
           double xj[3] = {pos_s[3 * (int64_t)j], pos_s[3 * (int64_t)j + 1], pos_s[3 * (int64_t)j + 2]};
-          double dx[3];
-          if (pair_test(xi, xj, ci, S[0], S[1], S[2], rc2, dx)) {
-            if (dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
-            if (FILL) {
-              int64_t eidx = out + count;
-              e_src[eidx] = j;
-              e_shift[eidx] = (uint32_t)(S[0] & 0xff) | ((uint32_t)(S[1] & 0xff) << 8) |
-                              ((uint32_t)(S[2] & 0xff) << 16);
-              e_vec[eidx] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], __int_as_float(spec_s[j]));
+          const int nj[3] = {oj.x, oj.y, oj.z};
+          int ilo[3], ihi[3];
+          for (int d = 0; d < 3; ++d) {
+            if (g.stencil[d]) {
+              ilo[d] = ihi[d] = 0;
+            } else {
+              const double dy = (xj[d] - (double)nj[d] * ci.L[d]) - yi[d], invL = 1.0 / ci.L[d];
+              ilo[d] = max(-g.img[d], (int)ceil((-ci.rc - dy) * invL - 1e-6));
+              ihi[d] = min(g.img[d], (int)floor((ci.rc - dy) * invL + 1e-6));
             }
-            ++count;
           }
+          for (int pz = ilo[2]; pz <= ihi[2]; ++pz)
+            for (int py = ilo[1]; py <= ihi[1]; ++py)
+              for (int px = ilo[0]; px <= ihi[0]; ++px) {
+                int S[3];
+                S[0] = ci.pbc[0] ? Sp[0] + px - oj.x + ni[0] : 0;
+                S[1] = ci.pbc[1] ? Sp[1] + py - oj.y + ni[1] : 0;
+                S[2] = ci.pbc[2] ? Sp[2] + pz - oj.z + ni[2] : 0;
+                if (j == i && S[0] == 0 && S[1] == 0 && S[2] == 0) continue;
+                double dx[3];
+                if (pair_test(xi, xj, ci, S[0], S[1], S[2], rc2, dx)) {
+                  if (dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+                  if (FILL) {
+                    int64_t eidx = out + count;
+                    e_src[eidx] = j;
+                    e_shift[eidx] = (uint32_t)(S[0] & 0xff) | ((uint32_t)(S[1] & 0xff) << 8) |
+                                    ((uint32_t)(S[2] & 0xff) << 16);
+                    e_vec[eidx] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], __int_as_float(spec_s[j]));
+                  }
+                  ++count;
+                }
+              }
         }
       }
   if (!FILL) cnt[i] = count;
