@@ -132,23 +132,6 @@ __global__ void k_batch_capacity(const int32_t* __restrict__ row_ptr, int64_t n,
   }
 }
 
-// reverse edge of (i, j, S) is (j, i, -S) in row j (same as k_nbr_rev)
-__global__ void k_batch_rev(int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ e_src,
-                            const uint32_t* __restrict__ e_shift, int64_t capacity, int32_t* __restrict__ e_rev) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n || row_ptr[n] > capacity) return;
-  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-    const int j = e_src[e];
-    const uint32_t sh = e_shift[e];
-    const int S0 = (int8_t)(sh & 0xff), S1 = (int8_t)((sh >> 8) & 0xff), S2 = (int8_t)((sh >> 16) & 0xff);
-    const uint32_t want = (uint32_t)((-S0) & 0xff) | ((uint32_t)((-S1) & 0xff) << 8) | ((uint32_t)((-S2) & 0xff) << 16);
-    int r = -1;
-    for (int f = row_ptr[j]; f < row_ptr[j + 1]; ++f)
-      if (e_src[f] == (int)i && e_shift[f] == want) { r = f; break; }
-    e_rev[e] = r;
-  }
-}
-
 void build_neighbors_batch(const NbrBuffers& b, const BatchBuffers& bb, int B, const double* pos,
                            const int32_t* spec, int64_t n, int n_species, double rc, int64_t capacity, hipStream_t s) {
   const int ga = (int)((n + 255) / 256);
@@ -161,56 +144,68 @@ void build_neighbors_batch(const NbrBuffers& b, const BatchBuffers& bb, int B, c
   k_batch_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
   k_batch_nbr<true><<<ga, 256, 0, s>>>(n, pos, b.info_s, b.spec_s, bb.sidx, bb.ptr, bb.cells, rc, nullptr,
                                        b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.status);
-  k_batch_rev<<<ga, 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, capacity, b.e_rev);
+  reverse_edges(b, n, capacity, false, s);
 }
 
-// one block per structure: forces of its atoms, its energy and virial (FP64, fixed order)
+// one block per structure: forces of its atoms, its energy and virial (FP64,
+// fixed order); 16 atoms at a time, 16 lanes over each atom's edges
 __global__ __launch_bounds__(256) void k_batch_out(int64_t n, const int32_t* __restrict__ row_ptr,
                                                    const float4* __restrict__ e_vec, const float4* __restrict__ g,
                                                    const int32_t* __restrict__ e_rev, const double* __restrict__ atom_e,
                                                    const int64_t* __restrict__ ptr, int64_t capacity,
                                                    const int64_t* __restrict__ status, double* __restrict__ forces,
                                                    double* __restrict__ energy, double* __restrict__ virial) {
-  __shared__ double sh[10][256];
-  const int b = blockIdx.x;
+  __shared__ double sh[4][10];
+  const int b = blockIdx.x, l16 = threadIdx.x & 15, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double loc[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) loc[k] = 0.0;
   const bool run = (status[ST_FLAGS] == 0) && ((int64_t)row_ptr[n] <= capacity);
   if (run) {
-    for (int64_t i = ptr[b] + threadIdx.x; i < ptr[b + 1]; i += 256) {
+    for (int64_t i0 = ptr[b]; i0 < ptr[b + 1]; i0 += 16) {
+      const int64_t i = i0 + (threadIdx.x >> 4);
       double F[3] = {0.0, 0.0, 0.0};
-      for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-        const int rv = e_rev[e];
-        const float4 ge = g[e];
-        const float4 gr = rv >= 0 ? g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 r = e_vec[e];
-        F[0] += (double)ge.x - (double)gr.x;
-        F[1] += (double)ge.y - (double)gr.y;
-        F[2] += (double)ge.z - (double)gr.z;
-        const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
+      if (i < ptr[b + 1]) {
+        for (int e = row_ptr[i] + l16; e < row_ptr[i + 1]; e += 16) {
+          const int rv = e_rev[e];
+          const float4 ge = g[e];
+          const float4 gr = rv >= 0 ? g[rv] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 r = e_vec[e];
+          F[0] += (double)ge.x - (double)gr.x;
+          F[1] += (double)ge.y - (double)gr.y;
+          F[2] += (double)ge.z - (double)gr.z;
+          const double rr[3] = {r.x, r.y, r.z}, gg[3] = {ge.x, ge.y, ge.z};
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+          for (int p = 0; p < 3; ++p)
 #pragma unroll
-          for (int q = 0; q < 3; ++q) loc[1 + 3 * p + q] += rr[p] * gg[q];
+            for (int q = 0; q < 3; ++q) loc[1 + 3 * p + q] += rr[p] * gg[q];
+        }
       }
-      forces[3 * i + 0] = F[0];
-      forces[3 * i + 1] = F[1];
-      forces[3 * i + 2] = F[2];
-      loc[0] += atom_e[i];
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[d] += __shfl_xor(F[d], off);
+      if (l16 == 0 && i < ptr[b + 1]) {
+        forces[3 * i + 0] = F[0];
+        forces[3 * i + 1] = F[1];
+        forces[3 * i + 2] = F[2];
+        loc[0] += atom_e[i];
+      }
     }
   }
 #pragma unroll
-  for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = loc[k];
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off)
+  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-      for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
-    __syncthreads();
+    for (int k = 0; k < 10; ++k) loc[k] += __shfl_xor(loc[k], off);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) sh[w][k] = loc[k];
+  __syncthreads();
+  if (threadIdx.x < 10) {
+    const double t = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+    if (threadIdx.x == 0) energy[b] = t;
+    else virial[9 * b + threadIdx.x - 1] = -t;
   }
-  if (threadIdx.x == 0) energy[b] = sh[0][0];
-  if (threadIdx.x < 9) virial[9 * b + threadIdx.x] = -sh[1 + threadIdx.x][0];
 }
 
 void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g,

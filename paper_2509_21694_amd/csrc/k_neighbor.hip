@@ -722,10 +722,12 @@ __global__ __launch_bounds__(256) void k_nbr_rev(int64_t n, const int32_t* __res
   const int l16 = threadIdx.x & 15;
   if (i >= n) return;
   if (row_ptr[n] > capacity) return;
-  const GridParams g = *gp;
-  const bool stencil3 = g.stencil[0] && g.stencil[1] && g.stencil[2];
-  int bi[3];
-  {
+  // gp null (batched lists): no stencil blocks, the whole row j is searched
+  GridParams g{};
+  if (gp) g = *gp;
+  const bool stencil3 = gp && g.stencil[0] && g.stencil[1] && g.stencil[2];
+  int bi[3] = {0, 0, 0};
+  if (stencil3) {
     const int bin = info_s[i].w;
     bi[0] = bin % g.nb[0]; bi[1] = (bin / g.nb[0]) % g.nb[1]; bi[2] = bin / (g.nb[0] * g.nb[1]);
   }
@@ -931,9 +933,13 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
                                    b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.cmask, b.status);
   k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
+  reverse_edges(b, n, capacity, true, s);
+}
+
+void reverse_edges(const NbrBuffers& b, int64_t n, int64_t capacity, bool blocks, hipStream_t s) {
   launch_fill32(b.e_rev, 0xffffffffu, sizeof(int32_t) * (size_t)capacity, s);
-  k_nbr_rev<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.info_s, b.grid, b.blk,
-                                                       capacity, b.e_rev);
+  k_nbr_rev<<<(unsigned)((n + 15) / 16), 256, 0, s>>>(n, b.row_ptr, b.e_src, b.e_shift, b.info_s,
+                                                       blocks ? b.grid : nullptr, b.blk, capacity, b.e_rev);
 }
 
 void export_neighbors(const NbrBuffers& b, int64_t n, int64_t capacity, int32_t* oi, int32_t* oj, int32_t* os,

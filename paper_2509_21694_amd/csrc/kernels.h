@@ -332,6 +332,10 @@ struct BatchBuffers {
   const BatchCell* cells;  // [B]
   int32_t* sidx;           // [N] structure of each atom
 };
+// e_rev of a built list: -1, then for each edge pair (i, j, S) / (j, i, -S)
+// the pair's owner searches row j (its stencil block of it when blocks) and
+// writes both entries
+void reverse_edges(const NbrBuffers& b, int64_t n, int64_t capacity, bool blocks, hipStream_t s);
 void build_neighbors_batch(const NbrBuffers& b, const BatchBuffers& bb, int B, const double* pos,
                            const int32_t* spec, int64_t n, int n_species, double rc, int64_t capacity, hipStream_t s);
 void launch_batch_outputs(int64_t n, int B, const NbrBuffers& nb, const float4* g,
