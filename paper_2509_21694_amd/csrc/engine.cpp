@@ -859,6 +859,9 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
   nk.n = N; nk.nlm = nlm; nk.A = A; nk.h = h; nk.w_read = m->w_read; nk.e0 = m->e0;
   nk.spec_s = b.spec_s; nk.owned_s = b.owned_s; nk.atom_e = atom_e;
   nk.dt = LD[K - 1].nk_dt; nk.d = LD[K - 1].nk_d;
+  nk.msg = nodeK && ht_bf16 ? (const unsigned short*)fa.msg : nullptr;
+  nk.row_ptr = b.row_ptr;
+  nk.inv_n = fa.inv_n;
   Node1Args n1;
   n1.n = N; n1.Q = qp; n1.P = qp; n1.h = h; n1.ht = node1 ? (void*)(w + p.o_ht[1]) : nullptr; n1.htbar = htbar;
   n1.spec_s = b.spec_s; n1.owned_s = b.owned_s; n1.emb = m->emb; n1.w_read = m->w_read;
@@ -898,10 +901,12 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
           fa.row_end = root_end;
           launch_l2(prec, C, L, 4, fa, s);
           fa.row_end = nullptr;
-          T.end(s);
-          T.begin("edge_sum_t" + std::to_string(t), s);
-          fa.n = R(K);
-          launch_l2(prec, C, L, 5, fa, s);
+          if (!nodeK) {   // else the last-layer node pass sums the messages itself
+            T.end(s);
+            T.begin("edge_sum_t" + std::to_string(t), s);
+            fa.n = R(K);
+            launch_l2(prec, C, L, 5, fa, s);
+          }
         } else {   // FP32 form (send32)
           fa.n = R(K - 1);
           fa.row_end = root_end;

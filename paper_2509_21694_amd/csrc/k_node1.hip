@@ -361,12 +361,45 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(4
   float* Ai = a.A + at * C;
   // B operand: this atom's messages, k-slot (kc, g, j) = channel 32 kc + 8 g + j
   bf16x8 ab[KC];
+  if (a.msg) {
+    // A_i = inv_n sum over row i's message slots, in edge order (each lane
+    // sums its 8 channels of every chunk)
+    float acc[KC][8];
 #pragma unroll
-  for (int kc = 0; kc < KC; ++kc) {
-    const float4 u = *(const float4*)(Ai + 32 * kc + 8 * g), v = *(const float4*)(Ai + 32 * kc + 8 * g + 4);
-    const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+    for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) ab[kc][j] = (__bf16)x[j];
+      for (int j = 0; j < 8; ++j) acc[kc][j] = 0.f;
+    const int e0 = a.row_ptr[at], e1 = av ? a.row_ptr[at + 1] : e0;
+    const unsigned short* M = a.msg + 8 * g;
+    auto add = [&](const uint4* u) {
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const unsigned w[4] = {u[kc].x, u[kc].y, u[kc].z, u[kc].w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          acc[kc][2 * t] += __uint_as_float(w[t] << 16);
+          acc[kc][2 * t + 1] += __uint_as_float(w[t] & 0xffff0000u);
+        }
+      }
+    };
+    for (int e = e0; e < e1; ++e) {
+      uint4 u0[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) u0[kc] = *(const uint4*)(M + (int64_t)e * C + 32 * kc);
+      add(u0);
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ab[kc][j] = (__bf16)(a.inv_n * acc[kc][j]);
+  } else {
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const float4 u = *(const float4*)(Ai + 32 * kc + 8 * g), v = *(const float4*)(Ai + 32 * kc + 8 * g + 4);
+      const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ab[kc][j] = (__bf16)x[j];
+    }
   }
   const bool own = a.owned_s[at] != 0;
   const float* h0 = a.h + at * (int64_t)a.nlm * C;
@@ -389,7 +422,7 @@ __global__ __launch_bounds__(64 * kN1Waves) __attribute__((amdgpu_waves_per_eu(4
   bf16x8 zo[KC];
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc) zo[kc] = tiles_to_op(zb, kc);
-  // every lane has read its A row above; the wave writes dE/dA over it
+  // every lane has read its A row (or messages) above; the wave writes dE/dA over A
   lds_rows<MT, KC>(sD, KC, 0, zo, lane, [&](int mt, f32x4 d) {
     if (av) *(float4*)(Ai + 16 * mt + 4 * g) = make_float4(d[0], d[1], d[2], d[3]);
   });

@@ -152,7 +152,12 @@ void launch_node1(bool fwd, int C, int L, int S, const Node1Args& a, hipStream_t
 struct NodeKArgs {
   int64_t n;
   int nlm;
-  float* A;               // [N][C]: messages in, dE/dA out (same rows)
+  float* A;               // [N][C]: the message sums in (unless msg), dE/dA out (same rows)
+  // when set, the per-edge BF16 messages [E][C] in receiver-side CSR slots:
+  // A_i = inv_n sum_{e in row i} msg[e] is formed here instead of read from A
+  const unsigned short* msg;
+  const int32_t* row_ptr;
+  float inv_n;
   const float* h;         // [N][nlm][C]: the previous layer's h_0 rows
   const float* w_read;    // [C]
   const float* e0;        // [S]
