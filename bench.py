@@ -101,9 +101,11 @@ def phase_counts(hp, prec):
         zq = 2.0 * KQ * (C * (1 + L) + (nlm - 1) * C)
         up = 2.0 * nlm * C * C
         d["node_fused"] = (0.0, 0.0, 0, 3 * nlm * KQ * 2 + 4 * C + 2 * nlm * C * 2, 2 * (zq + up))
-        # last-layer node update and its adjoint: A and h_0 read, dE/dA written over A,
-        # E_i written; z_0 = W_down^T A and dE/dA = W_down z-bar on MFMA
-        d["node_last"] = (0.0, 0.0, 0, 3 * 4 * C + 8, 2 * 2.0 * C * C)
+        # last-layer node update and its adjoint, with the message sum A_i =
+        # sum over the row of the messages (C adds per edge; the messages are
+        # intermediate, not algorithmic bytes): h_0 read, dE/dA written, E_i
+        # written; z_0 = W_down^T A and dE/dA = W_down z-bar on MFMA
+        d["node_last"] = (0.0, 1.0 * C, 0, 2 * 4 * C + 8, 2 * 2.0 * C * C)
     # neighbour list: positions and species read, the sorted copies, permutation
     # and row pointers written per atom; sender, shift, vector and reverse index
     # written per edge

@@ -358,21 +358,24 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       // hidden 16 nt + el, k = edges 4 g + r), B = Ysel (k = edges 4 g + r, column q)
       const int4 sp4 = *(const int4*)(ssp + 4 * g);
       const int spr[4] = {sp4.x, sp4.y, sp4.z, sp4.w};
+      // A operands of the four hidden tiles, converted in pairs once per tile
+      s16x4 av[4];
+      if constexpr (PREC == 1) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) av[nt] = pk4_bf16(a2[nt]);
+      }
 #pragma unroll
       for (int qt = 0; qt < MQ; ++qt) {
-        float ys[4];
+        f32x4 ys;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const float y = syc[(4 * g + r) * NLM + qlm[qt]];
           ys[r] = (spr[r] == qs[qt]) ? y : 0.f;
         }
         if constexpr (PREC == 1) {
-          const s16x4 bv = {bfbits(ys[0]), bfbits(ys[1]), bfbits(ys[2]), bfbits(ys[3])};
+          const s16x4 bv = pk4_bf16(ys);
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) {
-            const s16x4 av = {bfbits(a2[nt][0]), bfbits(a2[nt][1]), bfbits(a2[nt][2]), bfbits(a2[nt][3])};
-            q[nt][qt] = mfma_bf16_k16(av, bv, q[nt][qt]);
-          }
+          for (int nt = 0; nt < 4; ++nt) q[nt][qt] = mfma_bf16_k16(av[nt], bv, q[nt][qt]);
         } else {
 #pragma unroll
           for (int nt = 0; nt < 4; ++nt)
