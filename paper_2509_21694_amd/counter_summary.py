@@ -7,7 +7,7 @@ evaluates smaller systems).  GRBM_GUI_ACTIVE is summed over the 8 XCDs in
 the CSV, so one dispatch lasts GRBM_GUI_ACTIVE / 8 GPU cycles; utilisations
 are per SIMD (1024) or per CU (256) over that time:
   MFMA busy   = SQ_VALU_MFMA_BUSY_CYCLES / (cycles * 1024)
-  VALU busy   = SQ_ACTIVE_INST_VALU / (cycles * 256)   (quad-cycles per CU)
+  VALU active = SQ_ACTIVE_INST_VALU / (cycles * 256)   (quad-cycles, summed over the waves of a CU: above 100 % when several waves' VALU instructions are in flight together)
   co-issue    = SQ_VALU_MFMA_COEXEC_CYCLES / (cycles * 1024)
   LDS bank conflict = SQ_LDS_BANK_CONFLICT / (cycles * 256)
   waves/SIMD  = 4 SQ_WAVE_CYCLES / (cycles * 1024)      (quad-cycles)
@@ -68,7 +68,7 @@ def main():
     defs = __doc__.split("over that time:")[1].split("usage:")[0].strip().splitlines()
     print("Utilisation per SIMD (1024) or per CU (256) over the dispatch's GRBM_GUI_ACTIVE / 8 cycles:\n")
     print("\n".join("- " + d.strip() for d in defs) + "\n")
-    cols = ["kernel", "time ms", "MFMA busy", "VALU busy", "co-issue", "waves/SIMD", "wait/wave", "LDS conflict",
+    cols = ["kernel", "time ms", "MFMA busy", "VALU active", "co-issue", "waves/SIMD", "wait/wave", "LDS conflict",
             "VALU instr/wave", "MFMA instr/wave", "trans/VALU", "scratch B/lane", "LDS B/workgroup"]
     print("| " + " | ".join(cols) + " |")
     print("|" + "---|" * len(cols))
