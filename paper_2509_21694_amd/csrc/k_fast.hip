@@ -910,7 +910,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
   constexpr int HT = (NLM + 3) / 4 * 4, NG = HT / 4;
   __shared__ bf16x8 sW[(L + 1) * CN * 2 * 64];
   __shared__ bf16x8 sM1[4 * 64], sM2[4 * 2 * 64];
-  __shared__ unsigned sHT[NW][C * HT / 2];
+  __shared__ unsigned sHT[NW][2][C * HT / 2];
   if (fast_guard(a)) return;
   const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
@@ -919,108 +919,153 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
   stage_lds<bf16x8, 4 * 2 * 64>(sM2, a.w2a);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
-  unsigned* sh = sHT[wv];
   const unsigned short* ht = (const unsigned short*)a.ht;
   unsigned short* M = (unsigned short*)a.msg;
   const RowWalk rw = row_walk<NW>(a.n);
-  // each tile's reverse edges and edge vectors are requested during the tile before it
-  RowAhead rah(rw, a.row_ptr, a.row_end);
-  float4 pv = make_float4(-1.f, 0.f, 0.f, 0.f);
-  int prv = -1;
-  auto fetch = [&](int e, int end) {
-    const bool ok = e < end;
-    prv = ok ? a.e_rev[e] : -1;
-    pv = ok ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
-  };
-  if (rah.has_row()) fetch(rah.e0 + el, rah.e1);
-  for (int64_t i = rw.i; i < rw.end; i += rw.step, rah.advance(a.row_ptr, a.row_end)) {
-    const int e0 = rah.e0, e1 = rah.e1;
-    if (e0 >= e1 && rah.has_next()) fetch(rah.n0 + el, rah.n1);
-    const unsigned short* hi = ht + (int64_t)i * NLM * C;
-    // the row's features, transposed: sh[c][lm] (degrees NLM .. HT-1 zero)
+  auto rbeg = [&](int64_t r) { return a.row_ptr[r]; };
+  auto rend = [&](int64_t r) { return a.row_end ? a.row_end[r] : a.row_ptr[r + 1]; };
+  // a row's features, transposed into slot sl: sh[c][lm] (degrees NLM .. HT-1 zero)
+  auto stage = [&](int sl, int64_t r) {
+    unsigned* sh = sHT[wv][sl];
+    const unsigned short* hr = ht + r * NLM * C;
 #pragma unroll
     for (int p0 = 0; p0 < C / 2; p0 += 64) {
       const int p = p0 + lane;
       if (p < C / 2) {
 #pragma unroll
         for (int q = 0; q < HT / 2; ++q) {
-          const unsigned u0 = (2 * q < NLM) ? *(const unsigned*)(hi + (2 * q) * C + 2 * p) : 0u;
-          const unsigned u1 = (2 * q + 1 < NLM) ? *(const unsigned*)(hi + (2 * q + 1) * C + 2 * p) : 0u;
+          const unsigned u0 = (2 * q < NLM) ? *(const unsigned*)(hr + (2 * q) * C + 2 * p) : 0u;
+          const unsigned u1 = (2 * q + 1 < NLM) ? *(const unsigned*)(hr + (2 * q + 1) * C + 2 * p) : 0u;
           sh[(2 * p) * (HT / 2) + q] = (u0 & 0xffffu) | (u1 << 16);
           sh[(2 * p + 1) * (HT / 2) + q] = (u0 >> 16) | (u1 & 0xffff0000u);
         }
       }
     }
-    wave_lds_sync();
-    auto hx_op = [&](int mt) -> s16x4 {
-      const int ch = 32 * (mt / 2) + 8 * (el / 4) + 4 * (mt % 2) + (el % 4);
-      const uint2 v = *(const uint2*)(sh + ch * (HT / 2) + 2 * (g < NG ? g : 0));
-      return (g < NG) ? __builtin_bit_cast(s16x4, v) : (s16x4){0, 0, 0, 0};
-    };
-    for (int t0 = e0; t0 < e1; t0 += kTileE) {
-      const int e = t0 + el;
-      const bool valid = e < e1;
-      const int rv = prv;
-      const float4 v = pv;
-      if (t0 + kTileE < e1) fetch(t0 + kTileE + el, e1);
-      else if (rah.has_next()) fetch(rah.n0 + el, rah.n1);
-      Geo geo;
-      edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
-      float yc[NLM];
-      yc_last<L>(cgd, geo.Y, yc);
-      s16x4 yop[L + 1];
-#pragma unroll
-      for (int l = 0; l <= L; ++l)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          float w = 0.f;
-#pragma unroll
-          for (int gg = 0; gg < 4; ++gg) {
-            const int lm = 4 * gg + jj;
-            if (lm >= l * l && lm < (l + 1) * (l + 1)) w = (g == gg) ? yc[lm] : w;
-          }
-          yop[l][jj] = bfbits(w);
-        }
-      bf16x8 bop[2];
-      {
-        f32x4 p1[4], p2[4], a2[4];
-        mlp_forward_w<1>(geo, lane, sM1, sM2, p1, p2);
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
-#pragma unroll
-        for (int kc = 0; kc < 2; ++kc) bop[kc] = O::from_tiles(a2, kc);
-      }
-      unsigned short* dst = M + (int64_t)(rv < 0 ? 0 : rv) * C + 8 * g;
-      static_for<NK>([&](auto kk) {
-        constexpr int k = decltype(kk)::value;
-        __builtin_amdgcn_sched_barrier(0);
-        const s16x4 hx[2] = {hx_op(2 * k), hx_op(2 * k + 1)};
-        float m8[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) m8[q] = 0.f;
-#pragma unroll
-        for (int l = 0; l <= L; ++l) {
-#pragma unroll
-          for (int hh = 0; hh < 2; ++hh) {
-            f32x4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < 2; ++kc) d = O::mma(sW[((l * CN + 2 * k + hh) * 2 + kc) * 64 + lane], bop[kc], d);
-            const f32x4 x = mfma_bf16_k16(hx[hh], yop[l], (f32x4){0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int r = 0; r < 4; ++r) m8[4 * hh + r] += d[r] * x[r];
-          }
-        }
-        typedef __attribute__((ext_vector_type(8))) float f32x8;
-        f32x8 mv;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) mv[q] = m8[q];
-        if (rv >= 0) *(bf16x8*)(dst + 32 * k) = __builtin_convertvector(mv, bf16x8);
-      });
-      __builtin_amdgcn_sched_barrier(0);
+  };
+  // X operand of M-tile mt from slot sl: row el -> channel 32(mt/2) + 8(el/4) + 4(mt%2) + el%4,
+  // k-slot 4g + j -> degree lm
+  auto hx_op = [&](int sl, int mt) -> s16x4 {
+    const unsigned* sh = sHT[wv][sl];
+    const int ch = 32 * (mt / 2) + 8 * (el / 4) + 4 * (mt % 2) + (el % 4);
+    const uint2 v = *(const uint2*)(sh + ch * (HT / 2) + 2 * (g < NG ? g : 0));
+    return (g < NG) ? __builtin_bit_cast(s16x4, v) : (s16x4){0, 0, 0, 0};
+  };
+  // Tiles are packed across rows: a tile takes the rest of the current row A
+  // and, when that is shorter than 16 edges, the first edges of the wave's
+  // next non-empty row B (features in the other slot), so partial tiles occur
+  // only at the end of the walk.  X of a packed tile is two MFMAs, each row's
+  // features against the YC columns of its own edges.
+  int64_t ia = rw.i;
+  int pa = 0, ea = 0, sa = 0;
+  auto next_row = [&](int64_t r, int& b0, int& b1) -> int64_t {
+    for (; r < rw.end; r += rw.step) {
+      b0 = rbeg(r);
+      b1 = rend(r);
+      if (b0 < b1) return r;
     }
-    wave_lds_sync();
+    return rw.end;
+  };
+  ia = next_row(ia, pa, ea);
+  if (ia < rw.end) stage(sa, ia);
+  wave_lds_sync();
+  while (ia < rw.end) {
+    const int nA = min(kTileE, ea - pa);
+    int64_t ib = rw.end;
+    int b0 = 0, b1 = 0, nB = 0;
+    if (nA < kTileE) {
+      ib = next_row(ia + rw.step, b0, b1);
+      if (ib < rw.end) {
+        nB = min(kTileE - nA, b1 - b0);
+        stage(sa ^ 1, ib);
+        wave_lds_sync();
+      }
+    }
+    const bool inA = el < nA;
+    const bool valid = el < nA + nB;
+    const int e = inA ? pa + el : b0 + (el - nA);
+    const int rv = valid ? a.e_rev[e] : -1;
+    const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
+    Geo geo;
+    edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
+    float yc[NLM];
+    yc_last<L>(cgd, geo.Y, yc);
+    // YC operands of degree l, split by the row of the lane's edge
+    s16x4 yopA[L + 1], yopB[L + 1];
+#pragma unroll
+    for (int l = 0; l <= L; ++l)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        float w = 0.f;
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) {
+          const int lm = 4 * gg + jj;
+          if (lm >= l * l && lm < (l + 1) * (l + 1)) w = (g == gg) ? yc[lm] : w;
+        }
+        yopA[l][jj] = bfbits(inA ? w : 0.f);
+        yopB[l][jj] = bfbits(inA ? 0.f : w);
+      }
+    bf16x8 bop[2];
+    {
+      f32x4 p1[4], p2[4], a2[4];
+      mlp_forward_w<1>(geo, lane, sM1, sM2, p1, p2);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
+#pragma unroll
+      for (int kc = 0; kc < 2; ++kc) bop[kc] = O::from_tiles(a2, kc);
+    }
+    unsigned short* dst = M + (int64_t)(rv < 0 ? 0 : rv) * C + 8 * g;
+    const bool packed = nB > 0;
+    static_for<NK>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      __builtin_amdgcn_sched_barrier(0);
+      const s16x4 hx[2] = {hx_op(sa, 2 * k), hx_op(sa, 2 * k + 1)};
+      s16x4 hy[2] = {hx[0], hx[1]};
+      if (packed) { hy[0] = hx_op(sa ^ 1, 2 * k); hy[1] = hx_op(sa ^ 1, 2 * k + 1); }
+      float m8[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) m8[q] = 0.f;
+#pragma unroll
+      for (int l = 0; l <= L; ++l) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kc = 0; kc < 2; ++kc) d = O::mma(sW[((l * CN + 2 * k + hh) * 2 + kc) * 64 + lane], bop[kc], d);
+          f32x4 x = mfma_bf16_k16(hx[hh], yopA[l], (f32x4){0.f, 0.f, 0.f, 0.f});
+          if (packed) x = mfma_bf16_k16(hy[hh], yopB[l], x);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) m8[4 * hh + r] += d[r] * x[r];
+        }
+      }
+      typedef __attribute__((ext_vector_type(8))) float f32x8;
+      f32x8 mv;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) mv[q] = m8[q];
+      if (rv >= 0) *(bf16x8*)(dst + 32 * k) = __builtin_convertvector(mv, bf16x8);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    wave_lds_sync();   // this tile's reads of the slots are done before either is restaged
+    if (packed) {
+      // row A is done; row B's rest becomes the current row
+      ia = ib;
+      pa = b0 + nB;
+      ea = b1;
+      sa ^= 1;
+      if (pa >= ea) {   // row B ended inside the tile too
+        ia = next_row(ia + rw.step, pa, ea);
+        if (ia < rw.end) { stage(sa, ia); wave_lds_sync(); }
+      }
+    } else if (nA < kTileE) {
+      ia = rw.end;   // the last row of the walk, partial tile
+    } else {
+      pa += kTileE;
+      if (pa >= ea) {
+        ia = next_row(ia + rw.step, pa, ea);
+        if (ia < rw.end) { stage(sa, ia); wave_lds_sync(); }
+      }
+    }
   }
 }
 

@@ -82,7 +82,7 @@ def compare(o, ref, n, prec, label, volume, n_owned=None):
 
 # ----------------------------------------------------------- neighbour list
 
-NBR_CASES = ["small", "mpdp", "slab_pbc011", "thin_cell", "unwrapped", "cluster", "dense", "three_bins"]
+NBR_CASES = ["small", "mpdp", "slab_pbc011", "thin_cell", "unwrapped", "cluster", "dense", "three_bins", "cutoff_shell"]
 
 
 def nbr_case(name):
@@ -119,6 +119,13 @@ def nbr_case(name):
         # neighbours, more than one 64-lane round of the fill
         a = 1.8825
         pos = W.lattice_positions(8, 8, 8, a, 9, jitter=0.1)
+        return pos, np.eye(3) * 8 * a, np.array([True, True, True])
+    if name == "cutoff_shell":
+        # 2.5 A lattice in a 20 A box (three stencil bins per axis): the shell
+        # at 2a = r_cut is jittered by 1e-7 A, so thousands of pairs lie far
+        # inside the FP32 prefilter's band and are decided by the FP64 test
+        a = 2.5
+        pos = W.lattice_positions(8, 8, 8, a, 10, jitter=1e-7)
         return pos, np.eye(3) * 8 * a, np.array([True, True, True])
     raise KeyError(name)
 
