@@ -563,7 +563,7 @@ struct Plan {
   size_t total = 0;
   size_t o_status, o_bounds, o_grid, o_bcount, o_bcursor, o_bstart, o_rcount, o_rstart, o_scan, o_info, o_perm, o_iperm, o_pos,
       o_info_s, o_spec, o_owned, o_cnt, o_row, o_blk, o_cmask, o_esrc, o_eshift, o_evec, o_erev, o_edst, o_g,
-      o_ypos;
+      o_ypos, o_cand;
   size_t o_ht1, o_h, o_A, o_hbar, o_htbar, o_atom_e, o_partials;
   size_t o_qp = 0;  // first-layer species factorisation: Q (forward) / P (adjoint) [N][nlm][64 S]
   size_t o_msg = 0; // last-layer messages of the BF16 form, [max_edges][C] bf16
@@ -571,6 +571,7 @@ struct Plan {
   LayerOffsets o_ht, o_z0, o_zl;  // per layer 1..K (index t-1)
   int max_bins;
   int nblocks_out;
+  int64_t N = 0;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -584,6 +585,7 @@ size_t take(size_t& cur, size_t bytes) {
 Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K, int prec = MPIP_FP32) {
   Plan p;
   size_t cur = 0;
+  p.N = N;
   p.max_bins = (int)std::min<int64_t>(std::max<int64_t>(4096, 2 * N), 1 << 26);
   p.o_status = take(cur, sizeof(int64_t) * ST_WORDS);
   p.o_bounds = take(cur, sizeof(double) * kBoundsParts * 6);
@@ -606,6 +608,7 @@ Plan make_plan(int64_t N, int64_t cap, const mpip_hparams* hp, int K, int prec =
   p.o_row = take(cur, sizeof(int32_t) * (N + 1));
   p.o_blk = take(cur, sizeof(int32_t) * 28 * N);
   p.o_cmask = take(cur, sizeof(uint64_t) * kCandWords * N);
+  p.o_cand = take(cur, sizeof(uint32_t) * kCandList * N);
   p.o_esrc = take(cur, sizeof(int32_t) * cap);
   p.o_eshift = take(cur, sizeof(uint32_t) * cap);
   p.o_evec = take(cur, sizeof(float4) * cap);
@@ -684,6 +687,7 @@ NbrBuffers nbr_buffers(char* ws, const Plan& p) {
   b.row_ptr = (int32_t*)(ws + p.o_row);
   b.blk = (int32_t*)(ws + p.o_blk);
   b.cmask = (uint64_t*)(ws + p.o_cmask);
+  b.cand = p.N < ((int64_t)1 << 27) ? (uint32_t*)(ws + p.o_cand) : nullptr;
   b.e_src = (int32_t*)(ws + p.o_esrc);
   b.e_shift = (uint32_t*)(ws + p.o_eshift);
   b.e_vec = (float4*)(ws + p.o_evec);

@@ -503,7 +503,8 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
                                                int32_t* __restrict__ cnt, const int32_t* __restrict__ row_ptr,
                                                int64_t capacity, int32_t* __restrict__ e_src,
                                                uint32_t* __restrict__ e_shift, float4* __restrict__ e_vec,
-                                               uint64_t* __restrict__ cmask, int64_t* __restrict__ status) {
+                                               uint64_t* __restrict__ cmask, uint32_t* __restrict__ cand,
+                                               int64_t* __restrict__ status) {
   __shared__ int sPre[4][28], sStart[4][27], sShift[4][27], sCnt[4][27];
   __shared__ float4 sSf[4][27];   // the blocks' shifts Sp . cell, rounded to FP32 (prefilter)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -514,6 +515,51 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
   if (FILL && row_ptr[n] > capacity) return;
   const int4 me = info_s[i];
   const int bi[3] = {me.w % g.nb[0], (me.w / g.nb[0]) % g.nb[1], me.w / (g.nb[0] * g.nb[1])};
+  if (FILL && cand && row_ptr[i + 1] - row_ptr[i] <= kCandList) {
+    // the counting pass listed this row's passing candidates (sender, stencil
+    // block) in scan order: lane q writes edge q after the FP64 difference
+    const int npass = row_ptr[i + 1] - row_ptr[i];
+    const int64_t out = row_ptr[i];
+    if (lane < 27) sCnt[wv][lane] = 0;
+    wave_lds_sync();
+    const double xi[3] = {pos_s[3 * i], pos_s[3 * i + 1], pos_s[3 * i + 2]};
+    int coincident = 0;
+    if (lane < npass) {
+      const uint32_t c = cand[i * kCandList + lane];
+      const int j = (int)(c >> 5), k = (int)(c & 31u);
+      const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+      const int4 oj = info_s[j];
+      const int nj[3] = {oj.x, oj.y, oj.z}, ni[3] = {me.x, me.y, me.z};
+      int S[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int cc = bi[d] + o[d];
+        const int Sp = cc < 0 ? -1 : (cc >= g.nb[d] ? 1 : 0);
+        S[d] = ci.pbc[d] ? Sp - nj[d] + ni[d] : 0;
+      }
+      const double xj[3] = {pos_s[3 * (int64_t)j], pos_s[3 * (int64_t)j + 1], pos_s[3 * (int64_t)j + 2]};
+      double dx[3];
+      pair_test(xi, xj, ci, S[0], S[1], S[2], ci.rc * ci.rc, dx);
+      if (dx[0] == 0.0 && dx[1] == 0.0 && dx[2] == 0.0) coincident = 1;
+      const int64_t eidx = out + lane;
+      e_src[eidx] = j;
+      e_shift[eidx] = (uint32_t)(S[0] & 0xff) | ((uint32_t)(S[1] & 0xff) << 8) | ((uint32_t)(S[2] & 0xff) << 16);
+      e_vec[eidx] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], __int_as_float(spec_s[j]));
+      atomicAdd(&sCnt[wv][k], 1);
+    }
+    wave_lds_sync();
+    int cb = lane < 27 ? sCnt[wv][lane] : 0;
+    int wsum = cb;
+#pragma unroll
+    for (int oo = 1; oo < 32; oo <<= 1) {
+      const int t = __shfl_up(wsum, oo);
+      if (lane >= oo) wsum += t;
+    }
+    if (lane < 27) blk[28 * i + lane] = wsum - cb;
+    if (lane == 0) blk[28 * i + 27] = npass;
+    if (__any(coincident) && lane == 0) atomicOr((unsigned long long*)&status[ST_FLAGS], (unsigned long long)FL_COINCIDENT);
+    return;
+  }
   // lane k < 27: stencil block k = ((oz+1)*3 + (oy+1))*3 + (ox+1)
   int bc = 0;
   if (lane < 27) {
@@ -672,6 +718,10 @@ __global__ __launch_bounds__(256) void k_nbr_w(int64_t n, const double* __restri
     }
     const unsigned long long m = __ballot(pass);
     if (!FILL && lane == 0 && (base >> 6) < kCandWords) cmask[(int64_t)i * kCandWords + (base >> 6)] = m;
+    if (!FILL && cand && pass) {
+      const int slot = count + __popcll(m & ((1ull << lane) - 1ull));
+      if (slot < kCandList) cand[i * kCandList + slot] = ((uint32_t)j << 5) | (uint32_t)k;
+    }
     if (FILL && pass) {
       const int64_t eidx = out + count + __popcll(m & ((1ull << lane) - 1ull));
       e_src[eidx] = j;
@@ -924,13 +974,13 @@ void build_neighbors(const NbrBuffers& b, const mpip_system& sys, const CellInfo
   // one of each pair does the work: k_nbr_w when all dimensions use the 27-bin stencil, else k_nbr
   const unsigned gw = (unsigned)((n + 3) / 4);
   k_nbr_w<false><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.ypos_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt,
-                                    nullptr, capacity, nullptr, nullptr, nullptr, b.cmask, b.status);
+                                    nullptr, capacity, nullptr, nullptr, nullptr, b.cmask, b.cand, b.status);
   k_nbr<false><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, nullptr, b.cnt, nullptr,
                                    capacity, nullptr, nullptr, nullptr, b.status);
   exclusive_scan(b.cnt, n, b.row_ptr, b.scan_tmp, s);
   k_check_capacity<<<1, 64, 0, s>>>(b.row_ptr, n, capacity, b.status);
   k_nbr_w<true><<<gw, 256, 0, s>>>(n, b.pos_s, b.info_s, b.ypos_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr,
-                                   b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.cmask, b.status);
+                                   b.row_ptr, capacity, b.e_src, b.e_shift, b.e_vec, b.cmask, b.cand, b.status);
   k_nbr<true><<<ga, nblk, 0, s>>>(n, b.pos_s, b.info_s, b.spec_s, ci, b.grid, b.bin_start, b.bin_count, b.blk, nullptr, b.row_ptr,
                                   capacity, b.e_src, b.e_shift, b.e_vec, b.status);
   reverse_edges(b, n, capacity, true, s);

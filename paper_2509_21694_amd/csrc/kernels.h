@@ -6,6 +6,7 @@ namespace mpip {
 
 constexpr int kBoundsParts = 1024;
 constexpr int kCandWords = 8;   // atoms with more than 64 kCandWords candidates test them again when filling
+constexpr int kCandList = 64;   // rows of at most this many edges are filled from the counting pass's list
 
 struct CellInfo {
   double cell[9];
@@ -38,6 +39,8 @@ struct NbrBuffers {
   int32_t* row_ptr;      // [N+1]
   int32_t* blk;          // [N][28] start of each of the 27 stencil-offset blocks within a row, and its end
   uint64_t* cmask;       // [N][kCandWords] candidate pass masks of the counting pass (64 candidates a word)
+  uint32_t* cand;        // [N][kCandList] the counting pass's passing candidates in scan order,
+                         // sender << 5 | stencil block (null when N >= 2^27)
   int32_t* e_src;        // [cap] sender (sorted index)
   uint32_t* e_shift;     // [cap] S packed as three int8
   float4* e_vec;         // [cap] r_e (FP32 of the FP64 difference), species of sender in .w bits
