@@ -301,7 +301,7 @@ def main():
                     help="also time this many evaluations of the 8M-atom box as 8 slab partitions (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the halo-partition design for several GPUs is described, not built).", file=sys.stderr)
         sys.exit(2)
 

@@ -50,18 +50,23 @@ typedef enum {
   MPIP_ECAPACITY = -3,     /* edge capacity or workspace too small (required size reported)      */
   MPIP_EDEVICE = -4,       /* HIP runtime error                                                  */
   MPIP_ENOMEM = -5,        /* device allocation failed (model creation only)                     */
-  MPIP_EUNSUPPORTED = -6   /* valid input outside what this build implements                     */
+  MPIP_EUNSUPPORTED = -6   /* valid input outside what this library implements                   */
 } mpip_status;
 
 typedef enum {
   MPIP_FP32 = 0,           /* all arithmetic in FP32 (FP32 MFMA for the dense contractions)       */
   MPIP_BF16_MIXED = 1      /* radial MLP and channel mixing as BF16 MFMA with FP32 accumulation.
                               In the specialised first and last layers (64 or 128 channels) the
-                              tensor-product contractions also run on BF16 MFMA with BF16 operands
-                              and FP32 accumulation (first layer: Q = a2 (x) YC and its adjoint;
-                              last layer: X = ht . YC, dE/dYC and the sender-side pull), and the
-                              last layer's ht and per-edge messages are stored in BF16; generic
-                              (middle) layers form the tensor product on the VALU in FP32.
+                              radial MLP's second hidden layer a(r) is read from a per-layer
+                              table instead (built at model creation in FP64 from the FP32
+                              weights: 4096 intervals over [0, r_c], BF16 value and increment
+                              per interval, linear interpolation, the interval's slope as
+                              da/dr); the tensor-product contractions run on BF16 MFMA with
+                              BF16 operands and FP32 accumulation (first layer: Q = a2 (x) YC
+                              and its adjoint; last layer: X = ht . YC, dE/dYC and the
+                              sender-side pull), and the last layer's ht and per-edge messages
+                              are stored in BF16; generic (middle) layers evaluate the MLP on
+                              BF16 MFMA and form the tensor product on the VALU in FP32.
                               Geometry (basis, harmonics) in FP32; r_e is the FP64 displacement
                               rounded to FP32 (also in the virial); energy, force and virial
                               sums in FP64                                                        */
@@ -111,7 +116,8 @@ size_t mpip_weights_count(const mpip_hparams* hp);
 
 /* Validate hparams, build the coupling tables and upload the weights
  * (host float32 [n]) to `device`.  The model owns its device memory
- * (weights in FP32 and BF16 operand layouts, coupling tables) until
+ * (weights in FP32 and BF16 operand layouts, coupling tables, the BF16
+ * form's radial tables: 1 MiB per layer) until
  * mpip_model_destroy.  Synchronous.  Errors: EINVAL (bad hparams or n),
  * ENOMEM, EDEVICE. */
 mpip_status mpip_model_create(const mpip_hparams* hp, const float* weights_host, size_t n,

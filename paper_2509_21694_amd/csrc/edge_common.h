@@ -180,6 +180,71 @@ __device__ __forceinline__ void edge_geometry(float4 v, bool valid, const GeoK& 
   }
 }
 
+// Direction, length and harmonics only (the kernels that take the radial
+// MLP's output from its table need no basis): the same u, d and Y as
+// edge_geometry, basis and dbasis left unset.
+__device__ __forceinline__ void edge_direction(float4 v, bool valid, Geo& g) {
+  const float vx = valid ? v.x : 1.f, vy = valid ? v.y : 0.f, vz = valid ? v.z : 0.f;
+  const float d2 = vx * vx + vy * vy + vz * vz;
+  const float inv = __builtin_amdgcn_rsqf(d2);
+  const float d = d2 * inv;
+  const float x = vx * inv, y = vy * inv, z = vz * inv;
+  const float msk = valid ? 1.f : 0.f;
+  g.u[0] = msk * x; g.u[1] = msk * y; g.u[2] = msk * z; g.d = d;
+  const float s3 = 1.7320508075688772f, s5 = 2.23606797749979f, s15 = 3.872983346207417f;
+  g.Y[0] = msk;
+  g.Y[1] = msk * s3 * y; g.Y[2] = msk * s3 * z; g.Y[3] = msk * s3 * x;
+  g.Y[4] = msk * s15 * x * y; g.Y[5] = msk * s15 * y * z; g.Y[6] = msk * 0.5f * s5 * (3.f * z * z - 1.f);
+  g.Y[7] = msk * s15 * x * z; g.Y[8] = msk * 0.5f * s15 * (x * x - y * y);
+}
+
+// Tabulated radial MLP (BF16 form).  The second hidden layer a(d) in R^64
+// of one layer's radial MLP is a function of the edge length alone; the
+// table holds, for the kRadTab intervals [d_k, d_k+1) of [0, r_c]
+// (d_k = k r_c / kRadTab), a(d_k) and the increment a(d_k+1) - a(d_k) as a
+// BF16 pair per hidden unit (value in the low half), [kRadTab][64] words.
+// Between the knots a is interpolated linearly:
+//   a(d) = a(d_k) + tau (a(d_k+1) - a(d_k)),  tau = d kRadTab / r_c - k,
+// and its derivative is the interval's slope, (a(d_k+1) - a(d_k)) kRadTab / r_c.
+// Lengths at or past r_c take the last interval at tau = 1 (a = 0 there).
+struct RadPos {
+  int k;
+  float tau;
+};
+__device__ __forceinline__ RadPos rad_pos(float d, float scale) {
+  const float t = fminf(d * scale, (float)kRadTab);
+  const int k = min((int)t, kRadTab - 1);
+  return {k, fminf(t - (float)k, 1.f)};
+}
+// a(d) in the features x edges D-tile layout (lane (g, el): hidden
+// 16 mt + 4 g + r of the lane's edge) and, when sl is given, the increments
+__device__ __forceinline__ void rad_tiles(const uint32_t* tab, RadPos rp, int g, f32x4* a2, f32x4* sl) {
+  const uint4* row = (const uint4*)(tab + (size_t)rp.k * 64) + g;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const uint4 u = row[4 * mt];
+    const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float v = __uint_as_float(w[r] << 16), inc = __uint_as_float(w[r] & 0xffff0000u);
+      a2[mt][r] = fmaf(rp.tau, inc, v);
+      if (sl) sl[mt][r] = inc;
+    }
+  }
+}
+// dE/dd of the lane's edge from dE/da (ab2, same layout) and the increments:
+// sum over the 64 hidden units, the four lane groups of an edge combined
+__device__ __forceinline__ float rad_dbar(const f32x4* ab2, const f32x4* sl, float scale) {
+  float s = 0.f;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s = fmaf(ab2[mt][r], sl[mt][r], s);
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  return s * scale;
+}
+
 // gu = (dP/du)^T Ybar for the polynomials above
 __device__ __forceinline__ void sh_grad_contract(const float* Yb, const float* u, float* gu) {
   const float s3 = 1.7320508075688772f, s5 = 2.23606797749979f, s15 = 3.872983346207417f;

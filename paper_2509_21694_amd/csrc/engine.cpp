@@ -41,6 +41,46 @@ uint16_t f2bf(float f) {  // round to nearest even
 
 int n_paths_stored(int t, int L) { return (int)layer_paths(t, L).size(); }
 
+// The BF16 form's radial table of one layer, in the layout rad_pos and
+// rad_tiles read (edge_common.h): the MLP's second hidden layer
+// a(d) = silu(W2^T silu(W1^T b(d))) at the kRadTab + 1 knots
+// d_k = k r_c / kRadTab, in FP64 from the FP32 weights, with the Bessel
+// basis times the polynomial envelope, b_n(d) = sqrt(2/r_c) sin(n pi d / r_c) / d f(d / r_c)
+// (at d = 0 its limit sqrt(2/r_c) n pi / r_c), f(x) = 1 - a x^p + b x^(p+1) - c x^(p+2)
+// below x = 1 and 0 from there.  Word (k, h) packs BF16 a_h(d_k) (low
+// half) and BF16 of a_h(d_k+1) - a_h(d_k) (high half).
+std::vector<uint32_t> radial_table(const float* W1, const float* W2, int nb, int H, double rc, int p) {
+  const int N = kRadTab;
+  const double pi = 3.14159265358979323846;
+  const double ea = 0.5 * (p + 1) * (p + 2), eb = (double)p * (p + 2), ec = 0.5 * p * (p + 1);
+  std::vector<double> a((size_t)(N + 1) * H), b(nb), h1(H);
+  for (int k = 0; k <= N; ++k) {
+    const double d = rc * k / N, x = (double)k / N;
+    const double env = x < 1.0 ? 1.0 - ea * std::pow(x, p) + eb * std::pow(x, p + 1) - ec * std::pow(x, p + 2) : 0.0;
+    for (int n_ = 0; n_ < nb; ++n_) {
+      const double w = (n_ + 1) * pi / rc;
+      b[n_] = std::sqrt(2.0 / rc) * (k == 0 ? w : std::sin(w * d) / d) * env;
+    }
+    for (int h = 0; h < H; ++h) {
+      double z = 0.0;
+      for (int n_ = 0; n_ < nb; ++n_) z += (double)W1[(size_t)n_ * H + h] * b[n_];
+      h1[h] = z / (1.0 + std::exp(-z));
+    }
+    for (int h = 0; h < H; ++h) {
+      double z = 0.0;
+      for (int i = 0; i < H; ++i) z += (double)W2[(size_t)i * H + h] * h1[i];
+      a[(size_t)k * H + h] = z / (1.0 + std::exp(-z));
+    }
+  }
+  std::vector<uint32_t> t((size_t)N * H);
+  for (int k = 0; k < N; ++k)
+    for (int h = 0; h < H; ++h) {
+      const double v = a[(size_t)k * H + h], dv = a[(size_t)(k + 1) * H + h] - v;
+      t[(size_t)k * H + h] = (uint32_t)f2bf((float)v) | ((uint32_t)f2bf((float)dv) << 16);
+    }
+  return t;
+}
+
 bool valid_hp(const mpip_hparams* hp, std::string* why) {
   if (!hp) { *why = "null hparams"; return false; }
   if (hp->n_species < 1 || hp->n_species > 64) { *why = "n_species must be in 1..64"; return false; }
@@ -309,6 +349,12 @@ mpip_status mpip_model_create(const mpip_hparams* hp, const float* w, size_t n, 
         }
       };
       const int KC64 = bf ? 2 : 16;
+      d.rtab = nullptr;
+      if (bf) {
+        const void* tp;
+        if ((st = upload(m, radial_table(x.W1, x.W2, nb, H, hp->r_cut, hp->envelope_p), &tp)) != MPIP_OK) goto done;
+        d.rtab = (const uint32_t*)tp;
+      }
       // w1a: [mt 4][k][lane]: row h = 16mt + lane%16; bf16 k-slot (g,j) -> basis 8g+j; f32 chunk q -> basis 4q+g
       if ((st = pack(4, bf ? 1 : 2, [&](int mt, int k, int lane, int j) {
              const int h = 16 * mt + (lane & 15), g = lane >> 4;
@@ -844,6 +890,7 @@ static void run_model(mpip_model* m, const Plan& p, char* w, const NbrBuffers& b
     fa.w1a = d.w1a; fa.w2a = d.w2a; fa.w2b = d.w2b; fa.w1b = d.w1b; fa.w2f = d.w2f;
     fa.w3f = d.w3fp[role]; fa.w3t = d.w3t[role]; fa.w3b = d.w3bp[role]; fa.cg = d.cg[role];
     fa.w1r = d.w1r; fa.w2r = d.w2r; fa.w3r = d.w3r;
+    fa.rtab = d.rtab; fa.rtab_scale = (float)(kRadTab / hp.r_cut);
   };
   const int ht_bf16 = prec == MPIP_BF16_MIXED ? 1 : 0;
   // two-layer evaluation with specialised first and last layers (BF16 form):

@@ -7,8 +7,10 @@
 //   A_i[lm, c] = sum_{s,k} Q_i[lm, (s, k)] V_l[(s, k), c],
 //   Q_i[lm, (s, k)] = sum_{e: s_e = s} a2_e[k] YC_e[lm],
 //   V_l[(s, k), c]  = ht1[s, c] W3[k, (l, c)] / n_avg.
-// The per-edge work drops to the two hidden MLP layers plus a 16-edge MFMA
-// contraction into Q; the channel dimension moves to one node GEMM per l.
+// The per-edge work drops to the radial MLP's hidden layers (in the BF16
+// form read from the layer's radial table, edge_common.h rad_pos) plus a
+// 16-edge MFMA contraction into Q; the channel dimension moves to one node
+// GEMM per l.
 // Its adjoint uses P_i = dA_i V^T: dE/da2_e[k] = sum_lm YC_e[lm] P_i[lm, (s_e, k)]
 // and dE/dYC_e[lm] = sum_k a2_e[k] P_i[lm, (s_e, k)], both small MFMAs.
 //
@@ -17,7 +19,8 @@
 //             with R in edges x channels MFMA layout (each lane: 4 edges x
 //             C/16 contiguous channels), messages summed in registers.
 //   adjoint a: channels x edges layout (each lane: one edge x C/4 channels):
-//             dR, dE/dY, and the MLP adjoint fed straight from registers.
+//             dR, dE/dY, and the MLP adjoint (BF16: dE/dd from the radial
+//             table's increments) fed straight from registers.
 //   adjoint b: edges x channels layout: the sender-side feature adjoint
 //             pulled through the reverse edge (same length, Y_l(-u) =
 //             (-1)^l Y_l(u)), summed in registers.
@@ -99,11 +102,8 @@ __device__ __forceinline__ void yc_last_adj(const CgDiag<L>& cd, const float* yc
 }
 
 
-// geometry backward: dE/dr_e = dbar u + (I - u u^T)/d (dP/du)^T Ybar
-__device__ __forceinline__ float4 edge_grad(const Geo& geo, const float* ebar, const float* Yb) {
-  float dbar = 0.f;
-#pragma unroll
-  for (int n = 0; n < kNB; ++n) dbar += ebar[n] * geo.dbasis[n];
+// geometry backward: dE/dr_e = dbar u + (I - u u^T)/d (dP/du)^T Ybar, dbar = dE/dd
+__device__ __forceinline__ float4 edge_grad_d(const Geo& geo, float dbar, const float* Yb) {
   float gu[3];
   sh_grad_contract(Yb, geo.u, gu);
   const float ud = gu[0] * geo.u[0] + gu[1] * geo.u[1] + gu[2] * geo.u[2];
@@ -112,9 +112,16 @@ __device__ __forceinline__ float4 edge_grad(const Geo& geo, const float* ebar, c
                      dbar * geo.u[2] + (gu[2] - ud * geo.u[2]) * invd, 0.f);
 }
 
-// g_e += dE/dr_e
-__device__ __forceinline__ void add_edge_grad(float4* g, int e, const Geo& geo, const float* ebar, const float* Yb) {
-  const float4 d = edge_grad(geo, ebar, Yb);
+// the same with dE/dd from the basis adjoint ebar
+__device__ __forceinline__ float4 edge_grad(const Geo& geo, const float* ebar, const float* Yb) {
+  float dbar = 0.f;
+#pragma unroll
+  for (int n = 0; n < kNB; ++n) dbar += ebar[n] * geo.dbasis[n];
+  return edge_grad_d(geo, dbar, Yb);
+}
+
+// g_e += d (dE/dr_e)
+__device__ __forceinline__ void add_grad(float4* g, int e, float4 d) {
   float4 acc = g[e];
   acc.x += d.x;
   acc.y += d.y;
@@ -122,145 +129,19 @@ __device__ __forceinline__ void add_edge_grad(float4* g, int e, const Geo& geo, 
   g[e] = acc;
 }
 
-// remaining MLP adjoint: pb2 = ab2 * silu'(p2) -> W2 -> silu'(p1) -> W1 -> ebar (LDS [16][8])
-template <int PREC>
-__device__ __forceinline__ void mlp_backward(const f32x4* ab2, const f32x4* p1, const f32x4* p2, int lane,
-                                             const void* w2b, const void* w1b, float* seb) {
-  typedef Op<PREC> O;
-  const int g = lane >> 4, el = lane & 15;
-  f32x4 pb2[4], pb1[4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pb2[mt][r] = ab2[mt][r] * dsilu(p2[mt][r]);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kc = 0; kc < O::KC64; ++kc)
-      acc = O::mma(O::ldt(w2b, mt * O::KC64 + kc, lane), O::from_tiles(pb2, kc), acc);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
-  }
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(O::ldt(w1b, kc, lane), O::from_tiles(pb1, kc), acc);
-  if (g < 2) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) seb[el * kNB + 4 * g + r] = acc[r];
-  }
-}
-
-// sum over the 16 lanes of each DPP row (lanes 16g .. 16g+15); every lane of
-// the row receives the total
-template <int CTRL>
-__device__ __forceinline__ float dpp_add(float v) {
-  const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false);
-  return v + __int_as_float(o);
-}
-__device__ __forceinline__ float row16_sum(float v) {
-  v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
-  v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
-  v = dpp_add<0x141>(v);   // row_half_mirror
-  v = dpp_add<0x140>(v);   // row_mirror
-  return v;
-}
-
-
 template <typename T, int NT>
 __device__ __forceinline__ void stage_lds(T* dst, const void* src) {
   const T* s = (const T*)src;
   for (int t = threadIdx.x; t < NT; t += blockDim.x) dst[t] = s[t];
 }
 
-// remaining MLP adjoint as in mlp_backward, with dE/de of edge el returned in
-// registers of lane el (< 16)
-// remaining MLP adjoint as in mlp_backward, with dE/de of edge el returned in
-// registers of lane el (< 16); W2B, W1B in global memory or LDS
-template <int PREC, typename WT>
-__device__ __forceinline__ void mlp_backward_reg(const f32x4* ab2, const f32x4* p1, const f32x4* p2, int lane,
-                                                 const WT* W2B, const WT* W1B, float* eb) {
-  typedef Op<PREC> O;
-  f32x4 pb2[4], pb1[4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pb2[mt][r] = ab2[mt][r] * dsilu(p2[mt][r]);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kc = 0; kc < O::KC64; ++kc)
-      acc = O::mma(W2B[(mt * O::KC64 + kc) * 64 + lane], O::from_tiles(pb2, kc), acc);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * dsilu(p1[mt][r]);
-  }
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kc = 0; kc < O::KC64; ++kc) acc = O::mma(W1B[kc * 64 + lane], O::from_tiles(pb1, kc), acc);
-  // D rows n = 4g + r (basis index, g < 2), column = edge: lane el takes rows 0..3 from
-  // itself and rows 4..7 from lane el + 16
-  const int src = (lane & 15) + 16;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    eb[r] = acc[r];
-    eb[4 + r] = __shfl(acc[r], src);
-  }
-}
-
-// silu'(p) of one hidden layer's pre-activations (16 per lane), kept in BF16
-// between the forward and the adjoint of the MLP
-struct DsPack {
-  bf16x8 v[2];
-};
-__device__ __forceinline__ DsPack ds_pack(const f32x4* p) {
-  typedef __attribute__((ext_vector_type(8))) float f32x8;
-  DsPack d;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    f32x8 x;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) x[q] = dsilu(p[2 * h + q / 4][q % 4]);
-    d.v[h] = __builtin_convertvector(x, bf16x8);
-  }
-  return d;
-}
-
-// mlp_backward_reg with the silu' factors taken from DsPack (BF16 form)
-template <typename WT>
-__device__ __forceinline__ void mlp_backward_ds(const f32x4* ab2, const DsPack& d1, const DsPack& d2, int lane,
-                                                const WT* W2B, const WT* W1B, float* eb) {
-  typedef Op<1> O;
-  f32x4 pb2[4], pb1[4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pb2[mt][r] = ab2[mt][r] * (float)d2.v[mt / 2][(mt % 2) * 4 + r];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc) acc = O::mma(W2B[(mt * 2 + kc) * 64 + lane], O::from_tiles(pb2, kc), acc);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) pb1[mt][r] = acc[r] * (float)d1.v[mt / 2][(mt % 2) * 4 + r];
-  }
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kc = 0; kc < 2; ++kc) acc = O::mma(W1B[kc * 64 + lane], O::from_tiles(pb1, kc), acc);
-  const int src = (lane & 15) + 16;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    eb[r] = acc[r];
-    eb[4 + r] = __shfl(acc[r], src);
-  }
-}
-
 // ============================================================ first layer
 
-// Workgroups of NW waves, each wave walking its own rows (row_walk); the
-// MLP weights sit in LDS in the BF16 form.  The per-tile harmonics and
-// sender species are exchanged between the lanes of a wave through a
-// wave-private LDS slice.
+// Workgroups of NW waves, each wave walking its own rows (row_walk).  The
+// BF16 form reads the radial MLP's output from the layer's radial table
+// (rad_pos); the FP32 form evaluates the MLP from row-major weight copies in
+// LDS.  The per-tile harmonics and sender species are exchanged between the
+// lanes of a wave through a wave-private LDS slice.
 //
 // Rows of Q and P: the (species s, degree-order lm) pairs, numbered
 // q = lm S + s, so that Q_i[lm][s * 64 + k] = Q_i[q][k] (row q of 64 hidden
@@ -274,23 +155,19 @@ template <int PREC, int L, int S, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 1))) void k_l1_fwd(FastArgs a) {
   typedef Op<PREC> O;
   constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, MROWS = S * NLM, MQ = (MROWS + 15) / 16;
-  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
-  __shared__ typename O::T sM1[NM1], sM2[NM2];
-  // FP32 form: W1, W2 as row-major copies (one copy serves both orientations)
+  // FP32 form: W1, W2 as row-major copies (one copy serves both
+  // orientations); the BF16 form reads the MLP's output from its radial table
   __shared__ float sR1[PREC == 0 ? 8 * 65 : 1], sR2[PREC == 0 ? 64 * 65 : 1];
   __shared__ float sY[NW][kTileE * NLM];
   __shared__ __align__(16) int sS[NW][kTileE];
   if (fast_guard(a)) return;
   const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
-  if constexpr (PREC == 1) {
-    stage_lds<typename O::T, NM1>(sM1, a.w1a);
-    stage_lds<typename O::T, NM2>(sM2, a.w2f);
-  } else {
+  if constexpr (PREC == 0) {
     stage_rows<8 * 65>(sR1, a.w1r);
     stage_rows<64 * 65>(sR2, a.w2r);
+    __syncthreads();
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* syc = sY[wv];
   int* ssp = sS[wv];
@@ -315,7 +192,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       const bool valid = e < e1;
       Geo geo;
       const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      edge_geometry(v, valid, gk, geo);
+      if constexpr (PREC == 1) edge_direction(v, valid, geo);
+      else edge_geometry(v, valid, gk, geo);
       if (g == 0) {
         float yc[NLM];
         yc_last<L>(cgd, geo.Y, yc);
@@ -323,19 +201,33 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         for (int k = 0; k < NLM; ++k) syc[el * NLM + k] = yc[k];
         ssp[el] = valid ? __float_as_int(v.w) : -1;
       }
-      // radial MLP layer 1 (features x edges), layer 2 (edges x features)
-      f32x4 a1[4], a2[4];
-      {
+      // the MLP's second hidden layer, edges x features: a2[nt][r] = a(edge
+      // 4 g + r)[hidden 16 nt + el]
+      f32x4 a2[4];
+      if constexpr (PREC == 1) {
+        // from the radial table: each lane takes the interval of its four
+        // edges from the lanes that hold their geometry
+        const RadPos rp = rad_pos(geo.d, a.rtab_scale);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ke = __shfl(rp.k, 4 * g + r);
+          const float te = __shfl(rp.tau, 4 * g + r);
+          const uint32_t* row = a.rtab + (size_t)ke * 64 + el;
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) {
+            const uint32_t w = row[16 * nt];
+            a2[nt][r] = fmaf(te, __uint_as_float(w & 0xffff0000u), __uint_as_float(w << 16));
+          }
+        }
+      } else {
+        // layer 1 (features x edges), layer 2 (edges x features)
+        f32x4 a1[4];
         const f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
           f32x4 acc = z;
-          if constexpr (PREC == 1) {
-            acc = O::mma(sM1[mt * 64 + lane], basis_op_bf16(geo.basis, g), acc);
-          } else {
 #pragma unroll
-            for (int qq = 0; qq < 2; ++qq) acc = O::mma(sR1[(4 * qq + g) * 65 + 16 * mt + el], geo.basis[4 * qq + g], acc);
-          }
+          for (int qq = 0; qq < 2; ++qq) acc = O::mma(sR1[(4 * qq + g) * 65 + 16 * mt + el], geo.basis[4 * qq + g], acc);
 #pragma unroll
           for (int r = 0; r < 4; ++r) a1[mt][r] = silu(acc[r]);
         }
@@ -343,12 +235,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         for (int nt = 0; nt < 4; ++nt) {
           f32x4 acc = z;
 #pragma unroll
-          for (int kc = 0; kc < O::KC64; ++kc) {
-            typename O::T w;
-            if constexpr (PREC == 1) w = sM2[(nt * O::KC64 + kc) * 64 + lane];
-            else w = sR2[phi_f(kc, g) * 65 + 16 * nt + el];   // B = W2 [h1][h2 = 16 nt + el]
-            acc = O::mma(O::from_tiles(a1, kc), w, acc);
-          }
+          for (int kc = 0; kc < O::KC64; ++kc)   // B = W2 [h1][h2 = 16 nt + el]
+            acc = O::mma(O::from_tiles(a1, kc), sR2[phi_f(kc, g) * 65 + 16 * nt + el], acc);
 #pragma unroll
           for (int r = 0; r < 4; ++r) a2[nt][r] = silu(acc[r]);
         }
@@ -419,10 +307,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, MROWS = S * NLM, MQ = (MROWS + 15) / 16;
   constexpr int KCL = (PREC == 1) ? (NLM + 7) / 8 : NLM;   // chunks over lm per species group
   constexpr int KCY = ((S + 3) / 4) * KCL;                  // chunks of the (s, lm) slots
-  constexpr int NM1 = (PREC == 1) ? 4 * 64 : 1, NM2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1;
-  constexpr int NB2 = (PREC == 1) ? 4 * O::KC64 * 64 : 1, NB1 = (PREC == 1) ? O::KC64 * 64 : 1;
-  __shared__ typename O::T sM1[NM1], sM2[NM2], sB2[NB2], sB1[NB1];
-  // FP32 form: W1, W2 as row-major copies (one copy serves forward and adjoint)
+  // FP32 form: W1, W2 as row-major copies (one copy serves forward and
+  // adjoint); the BF16 form takes the MLP and its derivative from the radial table
   __shared__ float sR1[PREC == 0 ? 8 * 65 : 1], sR2[PREC == 0 ? 64 * 65 : 1];
   // dE/dYC rows of the tile: row el (edge), q = 16 mq + 4 g + r stored at
   // 16 g + 4 mq + r (sy_pos), row stride 65: a D-tile store's 64 lanes meet
@@ -434,16 +320,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   if (fast_guard(a)) return;
   const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
-  if constexpr (PREC == 1) {
-    stage_lds<typename O::T, NM1>(sM1, a.w1a);
-    stage_lds<typename O::T, NM2>(sM2, a.w2a);
-    stage_lds<typename O::T, NB2>(sB2, a.w2b);
-    stage_lds<typename O::T, NB1>(sB1, a.w1b);
-  } else {
+  if constexpr (PREC == 0) {
     stage_rows<8 * 65>(sR1, a.w1r);
     stage_rows<64 * 65>(sR2, a.w2r);
+    __syncthreads();
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   float* syb = sYB[wv];
   // BF16 form: P rows staged as [q][64] (q < 16 MQ, zero past MROWS) plus
@@ -544,21 +425,25 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       // BF16 form: the last layer's reverse-edge gradient of this edge, requested early
       float4 gq = make_float4(0.f, 0.f, 0.f, 0.f);
       if constexpr (PREC == 1) gq = (a.g2p && lane < kTileE && valid) ? a.g2p[e] : gq;
-      edge_geometry(v, valid, gk, geo);
+      if constexpr (PREC == 1) edge_direction(v, valid, geo);
+      else edge_geometry(v, valid, gk, geo);
       const int sp = valid ? __float_as_int(v.w) : -1;
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
+      // the MLP's second hidden layer a2 (BF16 form: from the radial table,
+      // with the increments sl for its derivative); FP32: p1, p2 kept for the adjoint
       f32x4 p1[4], p2[4], a2[4], ab2[4];
+      f32x4 sl[4];
       if constexpr (PREC == 1) {
-        mlp_forward_w<PREC>(geo, lane, sM1, sM2, p1, p2);
+        rad_tiles(a.rtab, rad_pos(geo.d, a.rtab_scale), g, a2, sl);
       } else {
         f32x4 a1[4];
         mlp_fwd_rows(geo, lane, sR1, sR2, p1, a1, p2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
       }
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
       // Ysel operand of this lane's edge (column el): slot (g, j) of chunk c
       // is species 4 (c / KCL) + g, lm = 8 (c % KCL) + j (FP32: lm = c % KCL)
       typename O::T yb[KCY];
@@ -593,7 +478,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
         for (int r = 0; r < 4; ++r) syb[el * SYB + 16 * g + 4 * mq + r] = acc[r];
       }
       float eb[kNB];
-      if constexpr (PREC == 1) mlp_backward_reg<PREC>(ab2, p1, p2, lane, sB2, sB1, eb);
+      float dbar = 0.f;
+      if constexpr (PREC == 1) dbar = rad_dbar(ab2, sl, a.rtab_scale);
       else mlp_bwd_rows(ab2, p1, p2, lane, sR1, sR2, eb);
       wave_lds_sync();
       if (lane < kTileE && valid) {
@@ -603,16 +489,18 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 #pragma unroll
         for (int k = 0; k < NLM; ++k) ycb[k] = syb[el * SYB + sy_pos(k * S + sp)];
         yc_last_adj<L>(cgd, ycb, Yb);
+        float4 d;
+        if constexpr (PREC == 1) d = edge_grad_d(geo, dbar, Yb);
+        else d = edge_grad(geo, eb, Yb);
         if (a.g2p) {
           // h_e = (this layer's dE/dr_e) - g2p[e], where g2p[e] is the last
           // layer's dE/dr of the reverse edge: then F_i = sum_e h_e - h_rev(e)
           // and the virial is -sum_e r_e (x) h_e (r_rev(e) = -r_e), so the
           // outputs gather one array through the reverse edges instead of two
-          const float4 d = edge_grad(geo, eb, Yb);
           if constexpr (PREC == 0) gq = a.g2p[e];
           a.g[e] = make_float4(d.x - gq.x, d.y - gq.y, d.z - gq.z, 0.f);
         } else {
-          add_edge_grad(a.g, e, geo, eb, Yb);
+          add_grad(a.g, e, d);
         }
       }
       wave_lds_sync();
@@ -653,18 +541,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
   constexpr int NG = HT / 4;                // lane groups holding degrees in the X operand
   __shared__ bf16x8 sW[(L + 1) * CN * 2 * 64];
   __shared__ bf16x8 sWB[(L + 1) * 4 * KCC * 64];
-  __shared__ bf16x8 sM1[4 * 64], sM2[4 * 2 * 64], sB2[4 * 2 * 64], sB1[2 * 64];
   __shared__ unsigned sHT[NW][C * HT / 2];
   __shared__ __align__(16) float sY[NW][kTileE * 20];
   if (fast_guard(a)) return;
-  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   stage_lds<bf16x8, (L + 1) * CN * 2 * 64>(sW, a.w3t);
   stage_lds<bf16x8, (L + 1) * 4 * KCC * 64>(sWB, a.w3b);
-  stage_lds<bf16x8, 4 * 64>(sM1, a.w1a);
-  stage_lds<bf16x8, 4 * 2 * 64>(sM2, a.w2a);
-  stage_lds<bf16x8, 4 * 2 * 64>(sB2, a.w2b);
-  stage_lds<bf16x8, 2 * 64>(sB1, a.w1b);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   unsigned* sh = sHT[wv];
@@ -728,7 +610,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       float4 an0 = *(const float4*)Aj, an1 = *(const float4*)(Aj + 4);
       wave_lds_sync();   // the previous tile's transposition reads are done
       Geo geo;
-      edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
+      edge_direction(make_float4(-v.x, -v.y, -v.z, 0.f), valid, geo);
       float yc[NLM];
       yc_last<L>(cgd, geo.Y, yc);
       if (g == 0) {
@@ -749,20 +631,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
           }
           yop[l][jj] = bfbits(w);
         }
-      f32x4 ab2[4];
+      // the MLP's second hidden layer from the radial table (B operand of
+      // R), with the increments sl for its derivative
+      f32x4 ab2[4], sl[4];
       bf16x8 bop[2];
-      DsPack d1, d2;
       {
-        f32x4 p1[4], p2[4], a2[4];
-        mlp_forward_w<1>(geo, lane, sM1, sM2, p1, p2);
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) { a2[mt][r] = silu(p2[mt][r]); ab2[mt][r] = 0.f; }
+        f32x4 a2[4];
+        rad_tiles(a.rtab, rad_pos(geo.d, a.rtab_scale), g, a2, sl);
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc) bop[kc] = O::from_tiles(a2, kc);
-        d1 = ds_pack(p1);
-        d2 = ds_pack(p2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) ab2[mt] = (f32x4){0.f, 0.f, 0.f, 0.f};
       }
       wave_lds_sync();
       // pull operands: A[lm = el][k-slot 4g + j] = YC_{e'}[lm] of edge 4g + j
@@ -860,8 +739,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         const int l = lm < 1 ? 0 : (lm < 4 ? 1 : (lm < 9 ? 2 : 3));
         ycb[lm] = __shfl(dy[l][lm % 4], el + 16 * (lm / 4));
       }
-      float eb[kNB];
-      mlp_backward_ds(ab2, d1, d2, lane, sB2, sB1, eb);
+      const float dbar = rad_dbar(ab2, sl, a.rtab_scale);
       if (lane < kTileE && valid) {
         float Yb[kMaxNlm];
 #pragma unroll
@@ -869,10 +747,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         yc_last_adj<L>(cgd, ycb, Yb);
         if (a.g2p) {
           // dE/dr of the reverse edge, kept in this edge's slot (written once, coalesced)
-          a.g2p[e] = edge_grad(geo, eb, Yb);
+          a.g2p[e] = edge_grad_d(geo, dbar, Yb);
         } else {
           const int rv = a.e_rev[e];
-          if (rv >= 0) add_edge_grad(a.g, rv, geo, eb, Yb);
+          if (rv >= 0) add_grad(a.g, rv, edge_grad_d(geo, dbar, Yb));
         }
       }
     }
@@ -909,14 +787,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
   constexpr int NK = C / 32, CN = C / 16;
   constexpr int HT = (NLM + 3) / 4 * 4, NG = HT / 4;
   __shared__ bf16x8 sW[(L + 1) * CN * 2 * 64];
-  __shared__ bf16x8 sM1[4 * 64], sM2[4 * 2 * 64];
   __shared__ unsigned sHT[NW][2][C * HT / 2];
   if (fast_guard(a)) return;
-  const GeoK gk = geo_consts(a.rc, a.envelope_p);
   const CgDiag<L> cgd = cg_diag<L>(a.cg);
   stage_lds<bf16x8, (L + 1) * CN * 2 * 64>(sW, a.w3t);
-  stage_lds<bf16x8, 4 * 64>(sM1, a.w1a);
-  stage_lds<bf16x8, 4 * 2 * 64>(sM2, a.w2a);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, el = lane & 15, wv = threadIdx.x >> 6;
   const unsigned short* ht = (const unsigned short*)a.ht;
@@ -986,7 +860,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
     const int rv = valid ? a.e_rev[e] : -1;
     const float4 v = valid ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
     Geo geo;
-    edge_geometry(make_float4(-v.x, -v.y, -v.z, 0.f), valid, gk, geo);
+    edge_direction(make_float4(-v.x, -v.y, -v.z, 0.f), valid, geo);
     float yc[NLM];
     yc_last<L>(cgd, geo.Y, yc);
     // YC operands of degree l, split by the row of the lane's edge
@@ -1004,14 +878,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4)
         yopA[l][jj] = bfbits(inA ? w : 0.f);
         yopB[l][jj] = bfbits(inA ? 0.f : w);
       }
+    // the MLP's second hidden layer from the radial table (B operand of R)
     bf16x8 bop[2];
     {
-      f32x4 p1[4], p2[4], a2[4];
-      mlp_forward_w<1>(geo, lane, sM1, sM2, p1, p2);
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a2[mt][r] = silu(p2[mt][r]);
+      f32x4 a2[4];
+      rad_tiles(a.rtab, rad_pos(geo.d, a.rtab_scale), g, a2, nullptr);
 #pragma unroll
       for (int kc = 0; kc < 2; ++kc) bop[kc] = O::from_tiles(a2, kc);
     }

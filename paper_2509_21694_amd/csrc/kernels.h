@@ -98,6 +98,9 @@ struct LayerDev {
   // radial MLP, backward
   const void* w2b;   // [4 mt][kc][64][..]
   const void* w1b;   // [kc][64][..]
+  // BF16 form: the MLP's second hidden layer tabulated over [0, r_c]
+  // (edge_common.h: rad_pos), [kRadTab][64] BF16 (value, increment) pairs
+  const uint32_t* rtab;
   // W3 of the live paths, for t < K (index 0) and t == K (index 1)
   const void* w3f[2];   // forward B operand [p][nt][kc][64][..]
   const void* w3b[2];   // backward A operand [p][mt][kc][64][..]
@@ -208,6 +211,8 @@ struct FastArgs {
   const float* w1r;      // FP32 row-major copies (k_fast32.hip)
   const float* w2r;
   const float* w3r;
+  const uint32_t* rtab;  // BF16 form: radial table of the layer (LayerDev::rtab)
+  float rtab_scale;      // kRadTab / r_c
   const float* cg;
   float* Q;              // first layer forward: [N][nlm][S*64]
   const float* P;        // first layer adjoint: [N][nlm][S*64]
