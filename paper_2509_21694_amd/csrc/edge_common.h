@@ -216,21 +216,40 @@ __device__ __forceinline__ RadPos rad_pos(float d, float scale) {
   const int k = min((int)t, kRadTab - 1);
   return {k, fminf(t - (float)k, 1.f)};
 }
-// a(d) in the features x edges D-tile layout (lane (g, el): hidden
-// 16 mt + 4 g + r of the lane's edge) and, when sl is given, the increments
-__device__ __forceinline__ void rad_tiles(const uint32_t* tab, RadPos rp, int g, f32x4* a2, f32x4* sl) {
+// The table words of a lane's four D tiles in the features x edges layout
+// (lane (g, el): hidden 16 mt + 4 g + r of the lane's edge), with tau
+struct RadRow {
+  uint4 w[4];
+  float tau;
+};
+__device__ __forceinline__ RadRow rad_load(const uint32_t* tab, RadPos rp, int g) {
   const uint4* row = (const uint4*)(tab + (size_t)rp.k * 64) + g;
+  RadRow rr;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) rr.w[mt] = row[4 * mt];
+  rr.tau = rp.tau;
+  return rr;
+}
+// a(d) in that layout and, when sl is given, the increments
+__device__ __forceinline__ void rad_eval(const RadRow& rr, f32x4* a2, f32x4* sl) {
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
-    const uint4 u = row[4 * mt];
-    const unsigned w[4] = {u.x, u.y, u.z, u.w};
+    const unsigned w[4] = {rr.w[mt].x, rr.w[mt].y, rr.w[mt].z, rr.w[mt].w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float v = __uint_as_float(w[r] << 16), inc = __uint_as_float(w[r] & 0xffff0000u);
-      a2[mt][r] = fmaf(rp.tau, inc, v);
+      a2[mt][r] = fmaf(rr.tau, inc, v);
       if (sl) sl[mt][r] = inc;
     }
   }
+}
+__device__ __forceinline__ void rad_tiles(const uint32_t* tab, RadPos rp, int g, f32x4* a2, f32x4* sl) {
+  rad_eval(rad_load(tab, rp, g), a2, sl);
+}
+// |v| as edge_direction forms it (tail lanes carry a unit vector)
+__device__ __forceinline__ float edge_length(float4 v) {
+  const float d2 = v.x * v.x + v.y * v.y + v.z * v.z;
+  return d2 * __builtin_amdgcn_rsqf(d2);
 }
 // dE/dd of the lane's edge from dE/da (ab2, same layout) and the increments:
 // sum over the 64 hidden units, the four lane groups of an edge combined

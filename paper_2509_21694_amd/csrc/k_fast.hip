@@ -367,10 +367,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
   auto fetch = [&](int e, int end) {
     if constexpr (PREC == 1) pv = e < end ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
   };
-  if (ra.has_row()) fetch(ra.e0 + el, ra.e1);
+  // BF16 form: the radial-table words of the edges in pv, requested once pv
+  // has arrived (at the end of the tile before)
+  RadRow rn{};
+  auto tab_fetch = [&]() {
+    if constexpr (PREC == 1) rn = rad_load(a.rtab, rad_pos(edge_length(pv), a.rtab_scale), g);
+  };
+  if (ra.has_row()) {
+    fetch(ra.e0 + el, ra.e1);
+    tab_fetch();
+  }
   for (int64_t i = rw.i; i < rw.end; i += rw.step, ra.advance(a.row_ptr, nullptr)) {
     const int e0 = ra.e0, e1 = ra.e1;
-    if (e0 >= e1 && ra.has_next()) fetch(ra.n0 + el, ra.n1);
+    if (e0 >= e1 && ra.has_next()) {
+      fetch(ra.n0 + el, ra.n1);
+      tab_fetch();
+    }
     p_stage();
     p_fetch(i + rw.step);
     const float* Pi = a.P + (int64_t)i * NLM * KQ;
@@ -435,7 +447,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       f32x4 p1[4], p2[4], a2[4], ab2[4];
       f32x4 sl[4];
       if constexpr (PREC == 1) {
-        rad_tiles(a.rtab, rad_pos(geo.d, a.rtab_scale), g, a2, sl);
+        rad_eval(rn, a2, sl);
       } else {
         f32x4 a1[4];
         mlp_fwd_rows(geo, lane, sR1, sR2, p1, a1, p2);
@@ -479,8 +491,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       }
       float eb[kNB];
       float dbar = 0.f;
-      if constexpr (PREC == 1) dbar = rad_dbar(ab2, sl, a.rtab_scale);
-      else mlp_bwd_rows(ab2, p1, p2, lane, sR1, sR2, eb);
+      if constexpr (PREC == 1) {
+        dbar = rad_dbar(ab2, sl, a.rtab_scale);
+        tab_fetch();
+      } else {
+        mlp_bwd_rows(ab2, p1, p2, lane, sR1, sR2, eb);
+      }
       wave_lds_sync();
       if (lane < kTileE && valid) {
         float ycb[NLM], Yb[kMaxNlm];
@@ -568,10 +584,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
     pj = ok ? a.e_src[e] : 0;
     pv = ok ? a.e_vec[e] : make_float4(-1.f, 0.f, 0.f, 0.f);
   };
-  if (rah.has_row()) fetch(rah.e0 + el, rah.e1);
+  // the radial-table words of the edges in pv, requested once pv has
+  // arrived (at the end of the tile before)
+  RadRow rn{};
+  auto tab_fetch = [&]() { rn = rad_load(a.rtab, rad_pos(edge_length(pv), a.rtab_scale), g); };
+  if (rah.has_row()) {
+    fetch(rah.e0 + el, rah.e1);
+    tab_fetch();
+  }
   for (int64_t i = rw.i; i < rw.end; i += rw.step, rah.advance(a.row_ptr, a.row_end)) {
     const int e0 = rah.e0, e1 = rah.e1;
-    if (e0 >= e1 && rah.has_next()) fetch(rah.n0 + el, rah.n1);
+    if (e0 >= e1 && rah.has_next()) {
+      fetch(rah.n0 + el, rah.n1);
+      tab_fetch();
+    }
     const unsigned short* hi = ht + (int64_t)i * NLM * C;
     // the row's features, transposed: sh[c][lm] (degrees NLM .. HT-1 zero)
 #pragma unroll
@@ -637,7 +663,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
       bf16x8 bop[2];
       {
         f32x4 a2[4];
-        rad_tiles(a.rtab, rad_pos(geo.d, a.rtab_scale), g, a2, sl);
+        rad_eval(rn, a2, sl);
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc) bop[kc] = O::from_tiles(a2, kc);
 #pragma unroll
@@ -740,6 +766,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) vo
         ycb[lm] = __shfl(dy[l][lm % 4], el + 16 * (lm / 4));
       }
       const float dbar = rad_dbar(ab2, sl, a.rtab_scale);
+      tab_fetch();
       if (lane < kTileE && valid) {
         float Yb[kMaxNlm];
 #pragma unroll
