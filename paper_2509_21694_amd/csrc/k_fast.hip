@@ -180,8 +180,40 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
     qs[qt] = q < MROWS ? q - (q / S) * S : -2;   // -2 matches no sender (invalid edges carry -1)
   }
   const RowWalk rw = row_walk<NW>(a.n);
-  for (int64_t i = rw.i; i < rw.end; i += rw.step) {
-    const int e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+  // BF16 form: each tile's edge vectors are requested during the tile before
+  // it, and the radial-table words of its edges once they have arrived (at
+  // the end of that tile): tw[r][nt] = word (interval of edge 4 g + r,
+  // hidden 16 nt + el), tt[r] its tau
+  RowAhead ra(rw, a.row_ptr, nullptr);
+  float4 pv = make_float4(1.f, 0.f, 0.f, 0.f);
+  uint32_t tw[4][4] = {};
+  float tt[4] = {};
+  auto fetch = [&](int e, int end) {
+    if constexpr (PREC == 1) pv = e < end ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
+  };
+  auto tab_fetch = [&]() {
+    if constexpr (PREC == 1) {
+      const RadPos rp = rad_pos(edge_length(pv), a.rtab_scale);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ke = __shfl(rp.k, 4 * g + r);
+        tt[r] = __shfl(rp.tau, 4 * g + r);
+        const uint32_t* row = a.rtab + (size_t)ke * 64 + el;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) tw[r][nt] = row[16 * nt];
+      }
+    }
+  };
+  if (ra.has_row()) {
+    fetch(ra.e0 + el, ra.e1);
+    tab_fetch();
+  }
+  for (int64_t i = rw.i; i < rw.end; i += rw.step, ra.advance(a.row_ptr, nullptr)) {
+    const int e0 = ra.e0, e1 = ra.e1;
+    if (e0 >= e1 && ra.has_next()) {
+      fetch(ra.n0 + el, ra.n1);
+      tab_fetch();
+    }
     f32x4 q[4][MQ];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
@@ -191,9 +223,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       const int e = t0 + el;
       const bool valid = e < e1;
       Geo geo;
-      const float4 v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
-      if constexpr (PREC == 1) edge_direction(v, valid, geo);
-      else edge_geometry(v, valid, gk, geo);
+      float4 v;
+      if constexpr (PREC == 1) {
+        v = pv;
+        if (t0 + kTileE < e1) fetch(t0 + kTileE + el, e1);
+        else if (ra.has_next()) fetch(ra.n0 + el, ra.n1);
+        edge_direction(v, valid, geo);
+      } else {
+        v = valid ? a.e_vec[e] : make_float4(1.f, 0.f, 0.f, 0.f);
+        edge_geometry(v, valid, gk, geo);
+      }
       if (g == 0) {
         float yc[NLM];
         yc_last<L>(cgd, geo.Y, yc);
@@ -205,20 +244,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
       // 4 g + r)[hidden 16 nt + el]
       f32x4 a2[4];
       if constexpr (PREC == 1) {
-        // from the radial table: each lane takes the interval of its four
-        // edges from the lanes that hold their geometry
-        const RadPos rp = rad_pos(geo.d, a.rtab_scale);
+        // from the radial-table words requested a tile ahead
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ke = __shfl(rp.k, 4 * g + r);
-          const float te = __shfl(rp.tau, 4 * g + r);
-          const uint32_t* row = a.rtab + (size_t)ke * 64 + el;
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) {
-            const uint32_t w = row[16 * nt];
-            a2[nt][r] = fmaf(te, __uint_as_float(w & 0xffff0000u), __uint_as_float(w << 16));
-          }
-        }
+          for (int nt = 0; nt < 4; ++nt)
+            a2[nt][r] = fmaf(tt[r], __uint_as_float(tw[r][nt] & 0xffff0000u), __uint_as_float(tw[r][nt] << 16));
       } else {
         // layer 1 (features x edges), layer 2 (edges x features)
         f32x4 a1[4];
@@ -271,6 +302,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
             for (int r = 0; r < 4; ++r) q[nt][qt] = mfma_f32(a2[nt][r], ys[r], q[nt][qt]);
         }
       }
+      tab_fetch();
       wave_lds_sync();
     }
     // row q = 16 qt + el, hidden 16 nt + 4 g + r: four consecutive values per store
