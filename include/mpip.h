@@ -301,6 +301,21 @@ mpip_status mpip_accumulate_rows(const double* src, const int32_t* index, int64_
  * (m1, m2, m3).  EINVAL for l > 2 or a triple without natural parity. */
 mpip_status mpip_coupling_tensor(int32_t l1, int32_t l2, int32_t l3, double* out);
 
+#define MPIP_RADIAL_TABLE_INTERVALS 4096
+
+/* The BF16 form's radial table of layer `layer` (1-based), as
+ * mpip_model_create builds it: the radial MLP's second hidden layer
+ * a(d) = silu(W2^T silu(W1^T e(d))) (e: Bessel basis times envelope) at the
+ * knots d_k = k r_cut / MPIP_RADIAL_TABLE_INTERVALS, in FP64 from the FP32
+ * weights.  Host only, no GPU needed.  out: host
+ * [MPIP_RADIAL_TABLE_INTERVALS][radial_hidden] words; word (k, h) holds
+ * BF16 a_h(d_k) in bits 0..15 and BF16 (a_h(d_k+1) - a_h(d_k)) in bits
+ * 16..31.  The specialised layers interpolate it linearly in d and take
+ * the interval's slope as da/dd.  EINVAL for bad hparams, weight count or
+ * layer. */
+mpip_status mpip_radial_table(const mpip_hparams* hp, const float* weights_host, size_t n, int32_t layer,
+                              uint32_t* out);
+
 /* Molecular dynamics on the device around mpip_evaluate (the MD runs of
  * the results section use Langevin dynamics).  Each of n_steps steps is the
  * BAOAB splitting (Leimkuhler and Matthews): v += a dt/2; x += v dt/2;

@@ -95,6 +95,8 @@ def _load():
     lib.mpip_neighbor_list.restype = I32
     lib.mpip_coupling_tensor.argtypes = [I32, I32, I32, P(ctypes.c_double)]
     lib.mpip_coupling_tensor.restype = I32
+    lib.mpip_radial_table.argtypes = [P(HParamsC), P(ctypes.c_float), SZ, I32, P(ctypes.c_uint32)]
+    lib.mpip_radial_table.restype = I32
     lib.mpip_timing_enable.argtypes = [V, I32]
     lib.mpip_timing_enable.restype = I32
     lib.mpip_timing_read.argtypes = [V, P(TimingC)]
@@ -135,7 +137,8 @@ lib = _load()
 
 EXPORTED = ["mpip_weights_count", "mpip_model_create", "mpip_model_destroy", "mpip_workspace_size",
             "mpip_evaluate", "mpip_workspace_status", "mpip_neighbor_workspace_size",
-            "mpip_neighbor_list", "mpip_coupling_tensor", "mpip_timing_enable", "mpip_timing_read",
+            "mpip_neighbor_list", "mpip_coupling_tensor", "mpip_radial_table", "mpip_timing_enable",
+            "mpip_timing_read",
             "mpip_slab_workspace_size", "mpip_slab_share", "mpip_accumulate_rows",
             "mpip_batch_workspace_size", "mpip_evaluate_batch", "mpip_md_workspace_size", "mpip_md_run",
             "mpip_partitioned_workspace_size", "mpip_evaluate_partitioned", "mpip_bfs_share_workspace_size",
@@ -163,6 +166,20 @@ def coupling_tensor(l1: int, l2: int, l3: int) -> np.ndarray:
     out = np.zeros((2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1), dtype=np.float64)
     _check(lib.mpip_coupling_tensor(l1, l2, l3, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out.reshape(2 * l1 + 1, 2 * l2 + 1, 2 * l3 + 1)
+
+
+# intervals of the radial table over [0, r_cut]
+RADIAL_TABLE_INTERVALS = 4096
+
+
+def radial_table(hp, weights: np.ndarray, layer: int) -> np.ndarray:
+    """The BF16 form's radial table of one layer: uint32 [4096, radial_hidden]
+    (low half BF16 a(d_k), high half BF16 a(d_k+1) - a(d_k))."""
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    out = np.zeros((RADIAL_TABLE_INTERVALS, hp.radial_hidden), dtype=np.uint32)
+    _check(lib.mpip_radial_table(ctypes.byref(hparams_c(hp)), w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                 w.size, int(layer), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return out
 
 
 def _system(positions, species, cell, pbc, n_owned) -> SystemC:

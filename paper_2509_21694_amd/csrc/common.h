@@ -11,7 +11,7 @@ constexpr int kWave = 64;
 constexpr int kTileE = 16;      // edges per MFMA tile (16x16 MFMA shapes)
 constexpr int kHidden = 64;     // radial MLP hidden width (fixed in this library)
 constexpr int kNB = 8;          // radial basis size (fixed in this library)
-constexpr int kRadTab = 4096;   // intervals of the BF16 form's radial table over [0, r_c]
+constexpr int kRadTab = MPIP_RADIAL_TABLE_INTERVALS;   // intervals of the BF16 form's radial table over [0, r_c]
 constexpr int kMaxNlm = 9;      // (l_max+1)^2 for l_max <= 2
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;

@@ -242,6 +242,24 @@ mpip_status mpip_coupling_tensor(int32_t l1, int32_t l2, int32_t l3, double* out
   return MPIP_OK;
 }
 
+mpip_status mpip_radial_table(const mpip_hparams* hp, const float* w, size_t n, int32_t layer, uint32_t* out) {
+  std::string why;
+  if (!valid_hp(hp, &why)) return fail(MPIP_EINVAL, why);
+  if (!w || !out) return fail(MPIP_EINVAL, "null weights or output");
+  if (n != count_weights(*hp)) return fail(MPIP_EINVAL, "weight count does not match the hyper-parameters");
+  if (layer < 1 || layer > hp->n_layers) return fail(MPIP_EINVAL, "no such layer");
+  // the layer's W1 and W2 in the weight blob (the order mpip_model_create reads)
+  const size_t C = hp->channels, H = hp->radial_hidden, nb = hp->n_basis, L = hp->l_max, S = hp->n_species;
+  size_t off = S * C;
+  for (int t = 1; t < layer; ++t)
+    off += ((t == 1) ? 1 : (L + 1)) * C * C + nb * H + H * H + H * n_paths_stored(t, (int)L) * C +
+           C * C * (1 + L) + L * C * C;
+  off += ((layer == 1) ? 1 : (L + 1)) * C * C;
+  const std::vector<uint32_t> t = radial_table(w + off, w + off + nb * H, (int)nb, (int)H, hp->r_cut, hp->envelope_p);
+  std::memcpy(out, t.data(), t.size() * sizeof(uint32_t));
+  return MPIP_OK;
+}
+
 mpip_status mpip_model_destroy(mpip_model* m) {
   if (!m) return MPIP_OK;
   int cur = 0;
