@@ -334,7 +334,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC ==
 // The row's P (BF16) is staged in a wave-private LDS slice, the next row's
 // loaded into registers while this row's tiles run.
 template <int PREC, int L, int S, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 2 : 1))) void k_l1_bwd(FastArgs a) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 3 : 1))) void k_l1_bwd(FastArgs a) {
   typedef Op<PREC> O;
   constexpr int NLM = (L + 1) * (L + 1), KQ = 64 * S, MROWS = S * NLM, MQ = (MROWS + 15) / 16;
   constexpr int KCL = (PREC == 1) ? (NLM + 7) / 8 : NLM;   // chunks over lm per species group
@@ -1061,9 +1061,10 @@ static int l2_grid(int64_t n, int nw, int per_xcd) {
 
 template <int PREC, int L>
 static void l1_launch(bool fwd, int S, const FastArgs& a, hipStream_t s) {
-  // 4 waves per workgroup; forward 4 waves per SIMD, adjoint 2
+  // 4 waves per workgroup; forward 4 waves per SIMD, adjoint 3 (BF16 form,
+  // whose radial table leaves the tile's registers within 168 VGPRs)
   constexpr int NW = 4;
-  const int gf = l2_grid(a.n, NW, 128), gb = l2_grid(a.n, NW, PREC == 1 ? 64 : 128);
+  const int gf = l2_grid(a.n, NW, 128), gb = l2_grid(a.n, NW, PREC == 1 ? 96 : 128);
 #define MPIP_L1(SS)                                                        \
   if (fwd) k_l1_fwd<PREC, L, SS, NW><<<gf, 64 * NW, 0, s>>>(a);              \
   else k_l1_bwd<PREC, L, SS, NW><<<gb, 64 * NW, 0, s>>>(a);
