@@ -281,7 +281,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="bulk1m")
     ap.add_argument("--precisions", default="bf16,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
