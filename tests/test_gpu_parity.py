@@ -263,3 +263,35 @@ def test_fast_kernels_parity(torch, M, L, C, S, prec):
     og = generic.evaluate(pos, sp, s.cell, s.pbc, precision=prec, atom_energy=True)
     compare(o, ref, 128, prec, f"fast L={L} C={C} S={S}", abs(np.linalg.det(s.cell)))
     compare(og, ref, 128, prec, f"generic L={L} C={C} S={S}", abs(np.linalg.det(s.cell)))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_edge_length_range_parity(torch, M, prec):
+    """The specialised kernels (K = 2, l_max = 2, C = 128) over the whole
+    range of edge lengths, against the oracle: isolated triangles, 20 A
+    apart in a non-periodic box, whose sides run from 0.4 A to a hair under
+    r_c, so the BF16 form's radial table is read in its first and last
+    intervals (tau near 0 and near 1) as well as in between."""
+    hp = W.HParams(n_species=3, n_layers=2, l_max=2, channels=128)
+    rng = np.random.default_rng(17)
+    firsts = [0.4, 0.9, 1.7, 2.6, 3.5, 4.2, 4.8, 4.99, 4.9999, hp.r_cut * (1.0 - 1e-7)]
+    pos = []
+    for t, d1 in enumerate(firsts):
+        c = np.array([20.0 * (t % 5), 20.0 * (t // 5), 0.0]) + 10.0
+        u1, u2 = rng.standard_normal(3), rng.standard_normal(3)
+        d2 = firsts[(t + 3) % len(firsts)]
+        pos += [c, c + d1 * u1 / np.linalg.norm(u1), c + d2 * u2 / np.linalg.norm(u2)]
+    pos = np.array(pos)
+    n = pos.shape[0]
+    cell = np.diag([120.0, 60.0, 40.0])
+    pbc = (False, False, False)
+    sp_np = (np.arange(n) % 3).astype(np.int32)
+    blob = W.make_weights(hp, 77)
+    ref = oracle.evaluate(pos, sp_np, cell, pbc, blob, hp)
+    model = M.Model(hp, blob)
+    o = model.evaluate(torch.tensor(pos, dtype=torch.float64, device="cuda"),
+                       torch.tensor(sp_np, dtype=torch.int32, device="cuda"), cell, pbc, precision=prec,
+                       atom_energy=True)
+    assert o["n_edges"] == 2 * sum(1 for t in range(len(firsts)) for (a, b) in ((0, 1), (0, 2), (1, 2))
+                                   if np.linalg.norm(pos[3 * t + a] - pos[3 * t + b]) < hp.r_cut)
+    compare(o, ref, n, prec, "edge-length range", float(np.linalg.det(cell)))
